@@ -1,0 +1,439 @@
+"""Pins of the CPU oracle to facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: a brute-force
+evaluation of a definition, a closed-form solution, an exact invariant of the
+semi-discrete system, or a second route to the same number.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_2012_04838_amd import inputs
+
+
+def _grid(N):
+    x = 2.0 * np.pi * np.arange(N) / N
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return X, Y, Z
+
+
+def _full_from_half(fhat):
+    """Full-spectrum array [kz][ky][kx] from a half spectrum, by Hermitian symmetry."""
+    N = fhat.shape[0]
+    full = np.zeros((N, N, N), dtype=np.complex128)
+    full[:, :, : N // 2 + 1] = fhat
+    for ix in range(N // 2 + 1, N):
+        full[:, :, ix] = np.conj(fhat[(-np.arange(N)) % N][:, (-np.arange(N)) % N][:, :, (N - ix)])
+    return full
+
+
+def _solenoidal_state(N, S, seed, kp=3.0, energy=1.0):
+    st = ora.init_field(N, S, seed, kp, energy)
+    if S:
+        sc = inputs.random_spectral_state(N, S, seed + 100, ora.kmax_retained(N), 3.0, 1.0)
+        st[3:] = sc
+    return st
+
+
+# ---------------------------------------------------------------- transforms (Eq. (5))
+@pytest.mark.parametrize("N", [6, 8])
+def test_forward_transform_is_brute_force_dft(N):
+    rng = np.random.default_rng(1)
+    f = rng.standard_normal((N, N, N))
+    X, Y, Z = _grid(N)
+    got = ora.to_spectral(f)
+    k1 = ora.wavenumbers_1d(N)
+    for iz in range(N):
+        for iy in range(N):
+            for ix in range(N // 2 + 1):
+                kz, ky, kx = k1[iz], k1[iy], ix
+                ref = np.sum(f * np.exp(-1j * (kx * X + ky * Y + kz * Z)))
+                assert abs(got[iz, iy, ix] - ref) <= 1e-12 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("N", [6, 8])
+def test_inverse_transform_is_brute_force_sum(N):
+    K = ora.kmax_retained(N)
+    fhat = inputs.random_spectral_state(N, 1, 3, N // 2, 2.0)[0]
+    fhat[:, :, N // 2] = 0.0          # the stored kx = N/2 plane is its own mirror; keep it empty
+    fhat[N // 2, :, :] = 0.0
+    fhat[:, N // 2, :] = 0.0
+    full = _full_from_half(fhat)
+    X, Y, Z = _grid(N)
+    got = ora.to_physical(fhat)
+    k1 = ora.wavenumbers_1d(N)
+    ref = np.zeros((N, N, N), dtype=np.complex128)
+    for iz in range(N):
+        for iy in range(N):
+            for ix in range(N):
+                ref += full[iz, iy, ix] * np.exp(1j * (k1[ix] * X + k1[iy] * Y + k1[iz] * Z))
+    ref /= N ** 3
+    assert np.max(np.abs(ref.imag)) < 1e-12 * np.max(np.abs(ref))
+    assert np.allclose(got, ref.real, rtol=0, atol=1e-12 * np.max(np.abs(ref)))
+    assert K >= 1
+
+
+def test_wavenumber_index_set_matches_paper():
+    # k_i = -N/2+1, ..., N/2 (Sec. 2.2)
+    for N in (6, 8, 16):
+        k = ora.wavenumbers_1d(N)
+        assert sorted(k.tolist()) == list(range(-N // 2 + 1, N // 2 + 1))
+
+
+def test_two_thirds_rule_kmax():
+    for N in range(6, 70, 2):
+        K = ora.kmax_retained(N)
+        assert 3 * K < N <= 3 * (K + 1)
+        # alias of any retained product lands outside the retained cube
+        assert N - 2 * K > K
+
+
+# ---------------------------------------------------------------- right-hand side (Eqs. (6)-(8))
+def test_rhs_analytic_nonlinear_and_scalar_terms():
+    """u = (sin z, sin x, 0): u.grad u = (0, cos x sin z, 0) is solenoidal, so
+    du/dt = (0, -cos x sin z, 0) at nu = 0.  phi = sin y with g = (0, 1, 0):
+    dphi/dt = -u.grad phi - g.u = -sin x cos y - sin x."""
+    N = 16
+    X, Y, Z = _grid(N)
+    u = [np.sin(Z), np.sin(X), np.zeros_like(X)]
+    phi = np.sin(Y)
+    st = np.stack([ora.to_spectral(f) for f in (*u, phi)])
+    prm = ora.Params(nu=0.0, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), forcing=False)
+    F = ora.rhs(st, prm)
+    got = [ora.to_physical(F[i]) for i in range(4)]
+    assert np.allclose(got[0], 0.0, atol=1e-13)
+    assert np.allclose(got[1], -np.cos(X) * np.sin(Z), atol=1e-13)
+    assert np.allclose(got[2], 0.0, atol=1e-13)
+    assert np.allclose(got[3], -np.sin(X) * np.cos(Y) - np.sin(X), atol=1e-13)
+
+
+def test_rhs_viscous_term_on_single_mode():
+    """u = (0, 0, cos(2x + y)) is a solenoidal single-wavevector field, u.grad u = 0, so
+    du/dt = -nu |k|^2 u with |k|^2 = 5; scalar phi = cos(3x) is not advected by u3(x, y):
+    dphi/dt = -D 9 phi."""
+    N = 16
+    X, Y, Z = _grid(N)
+    nu, sc = 0.3, 0.5
+    st = np.stack([ora.to_spectral(f) for f in (0 * X, 0 * X, np.cos(2 * X + Y), np.cos(3 * X))])
+    prm = ora.Params(nu=nu, schmidt=(sc,), mean_grad=((0.0, 0.0, 0.0),), forcing=False)
+    F = ora.rhs(st, prm)
+    assert np.allclose(ora.to_physical(F[2]), -nu * 5 * np.cos(2 * X + Y), atol=1e-13)
+    assert np.allclose(ora.to_physical(F[3]), -(nu / sc) * 9 * np.cos(3 * X), atol=1e-13)
+
+
+@pytest.mark.parametrize("N", [8, 12, 16])
+def test_pseudo_spectral_equals_galerkin_convolution(N):
+    """The dealiased pseudo-spectral product equals the truncated Galerkin convolution,
+    computed mode by mode straight from its definition (no FFT)."""
+    K = ora.kmax_retained(N)
+    S = 2
+    st = inputs.random_spectral_state(N, 3 + S, 7 + N, K, 3.0)
+    prm = ora.Params(nu=0.0, schmidt=(1.0, 0.7), mean_grad=((0.0, 1.0, 0.0), (0.3, -0.2, 0.5)),
+                     power=0.1, k_force=2.0)
+    F = ora.nonlinear(st, prm)
+    rng = np.random.default_rng(N)
+    modes = [(0, 1, 0), (1, 0, 0), (K, K, K), (0, -K, K), (1, -1, 2)]
+    modes += [tuple(int(v) for v in rng.integers(-K, K + 1, 3)) for _ in range(6)]
+    scale = np.max(np.abs(F))
+    for k in modes:
+        if k[0] < 0:
+            k = (-k[0], -k[1], -k[2])
+        ref = ora.galerkin_mode(st, prm, k)
+        got = ora.mode_value(F, k)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (k, got, ref)
+
+
+def test_rotational_equals_convective():
+    N = 16
+    st = _solenoidal_state(N, 1, 5)
+    prm = ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1)
+    a = ora.rhs(st, prm, "rotational")
+    b = ora.rhs(st, prm, "convective")
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+def test_projection_makes_rhs_solenoidal_and_is_idempotent():
+    N = 16
+    K = ora.kmax_retained(N)
+    st = inputs.random_spectral_state(N, 4, 11, K, 3.0)
+    prm = ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1)
+    F = ora.nonlinear(st, prm)
+    kx, ky, kz = ora.kgrid(N)
+    A = ora.forcing_amplitude(st[:3], prm)
+    fu = F[:3] - A * ora.band_mask(N, 2.0) * st[:3]  # forcing acts on a non-solenoidal input here
+    div = kx * fu[0] + ky * fu[1] + kz * fu[2]
+    assert np.max(np.abs(div)) <= 1e-13 * np.max(np.abs(fu)) * N
+    assert np.allclose(ora.project(fu), fu, rtol=0, atol=1e-13 * np.max(np.abs(fu)))
+
+
+def test_translation_commutes_with_rhs():
+    N = 16
+    st = _solenoidal_state(N, 1, 3)
+    prm = ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1)
+    kx, ky, kz = ora.kgrid(N)
+    dx = 2 * np.pi / N
+    shift = np.exp(-1j * (kx * dx + 2 * kz * dx))
+    a = ora.rhs(st * shift, prm)
+    b = ora.rhs(st, prm) * shift
+    assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
+
+
+def test_rhs_energy_and_scalar_variance_budgets():
+    """For solenoidal u: dK/dt = P - eps and d<phi^2>/dt = production - chi exactly
+    (u.(u x omega) = 0 and u.grad(phi^2/2) integrate to zero on the dealiased grid)."""
+    N = 16
+    st = _solenoidal_state(N, 2, 9)
+    prm = ora.Params(nu=0.02, schmidt=(1.0, 0.7), mean_grad=((0.0, 1.0, 0.0), (0.0, 1.0, 0.0)),
+                     power=0.1, k_force=2.0)
+    F = ora.rhs(st, prm)
+    w = ora.half_weights(N)
+    n6 = float(N) ** 6
+    dK = float(np.sum(w * np.real(np.conj(st[:3]) * F[:3]))) / n6
+    sp = ora.spectra(st, prm)
+    assert abs(dK - (prm.power - sp["eps"])) <= 1e-12 * abs(sp["eps"])
+    for s in range(2):
+        dvar = 2.0 * float(np.sum(w * np.real(np.conj(st[3 + s]) * F[3 + s]))) / n6
+        ref = sp["production"][s] - sp["chi"][s]
+        assert abs(dvar - ref) <= 1e-11 * (abs(sp["production"][s]) + abs(sp["chi"][s]))
+
+
+# ---------------------------------------------------------------- time stepping
+def _abc(N, k0, A=1.0, B=0.7, C=0.4):
+    X, Y, Z = _grid(N)
+    u1 = A * np.sin(k0 * Z) + C * np.cos(k0 * Y)
+    u2 = B * np.sin(k0 * X) + A * np.cos(k0 * Z)
+    u3 = C * np.sin(k0 * Y) + B * np.cos(k0 * X)
+    return [ora.to_spectral(f) for f in (u1, u2, u3)]
+
+
+def test_beltrami_flow_decays_exactly():
+    """ABC flow on one shell: omega = k0 u, u x omega = 0, so u(t) = exp(-nu k0^2 t) u(0)."""
+    N, k0, nu = 16, 3, 0.05
+    st = np.stack(_abc(N, k0))
+    prm = ora.Params(nu=nu, forcing=False)
+    dt, n = 0.07, 6
+    out = ora.step(st, prm, dt, n)
+    ref = st * math.exp(-nu * k0 * k0 * dt * n)
+    assert np.max(np.abs(out - ref)) <= 1e-13 * np.max(np.abs(st))
+
+
+def test_single_mode_scalar_decays_exactly():
+    N, nu, sc = 16, 0.05, 0.5
+    X, Y, Z = _grid(N)
+    ph = ora.to_spectral(np.cos(2 * X - Y + 3 * Z))
+    z = np.zeros_like(ph)
+    st = np.stack([z, z, z, ph])
+    prm = ora.Params(nu=nu, schmidt=(sc,), mean_grad=((0.0, 1.0, 0.0),), forcing=False)
+    dt, n = 0.1, 5
+    out = ora.step(st, prm, dt, n)
+    ref = ph * math.exp(-(nu / sc) * 14 * dt * n)
+    assert np.max(np.abs(out[3] - ref)) <= 1e-13 * np.max(np.abs(ph))
+    assert np.max(np.abs(out[:3])) == 0.0
+
+
+def test_mean_gradient_shear_wave_exact():
+    """u = (0, U sin(k0 x), 0), phi0 = 0, g = (0, G, 0), Sc = 1: the velocity decays
+    exactly and phi(t) = -G U t exp(-nu k0^2 t) sin(k0 x) (the integrating-factor frame
+    sees a constant forcing, which RK4 integrates exactly)."""
+    N, k0, nu, U, G = 16, 2, 0.04, 0.8, 1.3
+    X, Y, Z = _grid(N)
+    z = np.zeros((N, N, N))
+    st = np.stack([ora.to_spectral(f) for f in (z, U * np.sin(k0 * X), z, z)])
+    prm = ora.Params(nu=nu, schmidt=(1.0,), mean_grad=((0.0, G, 0.0),), forcing=False)
+    dt, n = 0.1, 7
+    t = dt * n
+    out = ora.step(st, prm, dt, n)
+    phi = ora.to_physical(out[3])
+    ref = -G * U * t * math.exp(-nu * k0 * k0 * t) * np.sin(k0 * X)
+    assert np.max(np.abs(phi - ref)) <= 1e-13
+    u2 = ora.to_physical(out[1])
+    assert np.max(np.abs(u2 - U * math.exp(-nu * k0 * k0 * t) * np.sin(k0 * X))) <= 1e-13
+
+
+def test_mean_gradient_shear_wave_unequal_diffusivity_converges():
+    N, k0, nu, U, G, sc = 16, 2, 0.04, 0.8, 1.3, 0.5
+    X, Y, Z = _grid(N)
+    z = np.zeros((N, N, N))
+    st = np.stack([ora.to_spectral(f) for f in (z, U * np.sin(k0 * X), z, z)])
+    prm = ora.Params(nu=nu, schmidt=(sc,), mean_grad=((0.0, G, 0.0),), forcing=False)
+    T = 1.0
+    D = nu / sc
+    ref = -G * U * (math.exp(-nu * k0 ** 2 * T) - math.exp(-D * k0 ** 2 * T)) / ((D - nu) * k0 ** 2) * np.sin(k0 * X)
+    errs = []
+    for n in (2, 4, 8):
+        out = ora.step(st, prm, T / n, n)
+        errs.append(np.max(np.abs(ora.to_physical(out[3]) - ref)))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 12 < r1 < 20 and 12 < r2 < 20, errs
+
+
+def test_constant_power_forcing_energy_ode():
+    """ABC flow on |k| = 1 inside the forced band: dE/dt = -2 nu E + P exactly in the
+    semi-discrete system, E(t) = P/(2nu) + (E0 - P/(2nu)) exp(-2 nu t); RK4 converges at 4th order."""
+    N, nu, P = 16, 0.05, 0.3
+    st = np.stack(_abc(N, 1, 0.2, 0.1, 0.15))
+    prm = ora.Params(nu=nu, power=P, k_force=2.0)
+    E0 = ora.kinetic_energy_of(st)
+    T = 2.0
+    Eex = P / (2 * nu) + (E0 - P / (2 * nu)) * math.exp(-2 * nu * T)
+    errs = []
+    for n in (8, 16, 32):
+        out = ora.step(st, prm, T / n, n)
+        errs.append(abs(ora.kinetic_energy_of(out) - Eex))
+    assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12, errs
+    assert errs[2] < 1e-5 * Eex
+
+
+def test_inviscid_energy_conservation_fourth_order():
+    N = 16
+    st = ora.init_field(N, 0, 21, 4.0, 1.0)
+    prm = ora.Params(nu=0.0, forcing=False)
+    T = 0.8
+    errs = []
+    for n in (8, 16, 32):
+        out = ora.step(st, prm, T / n, n)
+        errs.append(abs(ora.kinetic_energy_of(out) - 1.0))
+    assert errs[0] > 1e-11
+    s1 = math.log2(errs[0] / errs[1])
+    s2 = math.log2(errs[1] / errs[2])
+    assert 3.3 < s1 < 5.5 and 3.3 < s2 < 5.5, (errs, s1, s2)
+
+
+def test_steps_keep_velocity_solenoidal():
+    N = 16
+    st = _solenoidal_state(N, 1, 4)
+    prm = ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1)
+    out = ora.step(st, prm, 0.02, 3)
+    kx, ky, kz = ora.kgrid(N)
+    div = kx * out[0] + ky * out[1] + kz * out[2]
+    assert np.max(np.abs(div)) <= 1e-13 * N * np.max(np.abs(out[:3]))
+
+
+def test_cfl_timestep():
+    N, U, C = 16, 0.7, 0.5
+    X, Y, Z = _grid(N)
+    z = np.zeros((N, N, N))
+    st = np.stack([ora.to_spectral(f) for f in (U * np.sin(X), z, z)])
+    assert abs(ora.cfl_dt(st, C) - C * (2 * np.pi / N) / U) < 1e-14
+
+
+# ---------------------------------------------------------------- initial condition
+def test_splitmix64_reference_stream():
+    """First two outputs of the SplitMix64 reference generator seeded with 0."""
+    out = ora.splitmix64(0, np.array([0, 1], dtype=np.uint64))
+    assert int(out[0]) == 0xE220A8397B1DCDAF
+    assert int(out[1]) == 0x6E789E6AA1B965F4
+
+
+def test_init_field_properties():
+    N, S = 32, 2
+    st = ora.init_field(N, S, 1, 4.0, 1.0)
+    assert abs(ora.kinetic_energy_of(st) - 1.0) < 1e-14
+    assert np.all(st[3:] == 0)
+    mask = ora.retained_mask(N)
+    assert np.all(st[:, ~mask] == 0)
+    kx, ky, kz = ora.kgrid(N)
+    assert np.max(np.abs(kx * st[0] + ky * st[1] + kz * st[2])) <= 1e-12 * np.max(np.abs(st))
+    assert np.all(st[:, 0, 0, 0] == 0)
+    # Hermitian kx = 0 plane: the field is real, so the full complex inverse has no imaginary part
+    for c in range(3):
+        full = _full_from_half(st[c])
+        f = np.fft.ifftn(full)
+        assert np.max(np.abs(f.imag)) <= 1e-14 * np.max(np.abs(f.real))
+    # same seed reproduces, different seed differs
+    assert np.array_equal(st, ora.init_field(N, S, 1, 4.0, 1.0))
+    assert not np.allclose(st, ora.init_field(N, S, 2, 4.0, 1.0))
+
+
+def test_init_field_shell_energies_follow_spectrum():
+    N = 64
+    kp = 6.0
+    st = ora.init_field(N, 0, 3, kp, 1.0)
+    prm = ora.Params(nu=0.01)
+    E = ora.spectra(st, prm)["E"]
+    sh = ora.shell_index(N)
+    mask = ora.retained_mask(N)
+    w = ora.half_weights(N)
+    model = []
+    for s in range(len(E)):
+        m = (sh == s) & mask
+        kk = np.sqrt(ora.k_squared(N))
+        model.append(float(np.sum((w * m) * np.where(m, ora.init_spectrum(kk, kp) / (4 * np.pi * np.where(kk > 0, kk, 1) ** 2), 0))))
+    model = np.array(model)
+    model *= E.sum() / model.sum()
+    for s in range(3, 18):
+        cnt = float(np.sum(((sh == s) & mask) * w))
+        assert abs(E[s] / model[s] - 1.0) < 4.0 / math.sqrt(cnt), s
+
+
+# ---------------------------------------------------------------- statistics (Table 1, Eqs. (11)-(13))
+def test_vgt_skewness_flatness_closed_form():
+    """du1/dx1 = a cos x + b cos 2x: <.^3> = 3a^2 b/4, <.^2> = (a^2+b^2)/2,
+    <.^4> = 3(a^4+b^4)/8 + 3a^2 b^2/2."""
+    N = 16
+    X, Y, Z = _grid(N)
+    a, b = 1.0, 0.6
+    u1 = a * np.sin(X) + 0.5 * b * np.sin(2 * X)
+    z = np.zeros_like(X)
+    st = np.stack([ora.to_spectral(f) for f in (u1, z, z, np.sin(Y) + 0.25 * np.sin(2 * Y))])
+    res = ora.physical_stats(st)
+    m2 = (a * a + b * b) / 2
+    assert abs(res["vgt_skew"][0] - 0.75 * a * a * b / m2 ** 1.5) < 1e-12
+    assert abs(res["vgt_flat"][0] - (3 * (a ** 4 + b ** 4) / 8 + 1.5 * a * a * b * b) / m2 ** 2) < 1e-12
+    # dphi/dx2 = cos y + 0.5 cos 2y
+    a2, b2 = 1.0, 0.5
+    m2p = (a2 * a2 + b2 * b2) / 2
+    assert abs(res["phi2_skew"][0] - 0.75 * a2 * a2 * b2 / m2p ** 1.5) < 1e-12
+    assert abs(res["max_abs_u_sum"] - np.max(np.abs(u1))) < 1e-12
+
+
+def test_spectral_dissipation_equals_physical_strain_average():
+    """eps = 2 nu <S:S> with S = (grad u + grad u^T)/2 formed in physical space (Table 1),
+    for a non-solenoidal random field so that the |k.u|^2 part is exercised."""
+    N = 16
+    K = ora.kmax_retained(N)
+    st = inputs.random_spectral_state(N, 3, 5, K, 3.0)
+    nu = 0.013
+    sp = ora.spectra(st, ora.Params(nu=nu))
+    k1 = ora.wavenumbers_1d(N)
+    kvec = [np.arange(N // 2 + 1)[None, None, :], k1[None, :, None], k1[:, None, None]]
+    grad = [[np.fft.irfftn(1j * kvec[j] * st[i], s=(N, N, N), axes=(0, 1, 2)) for j in range(3)] for i in range(3)]
+    ss = 0.0
+    for i in range(3):
+        for j in range(3):
+            sij = 0.5 * (grad[i][j] + grad[j][i])
+            ss += np.mean(sij * sij)
+    assert abs(sp["eps"] - 2 * nu * ss) <= 1e-12 * sp["eps"]
+    # K from the spectrum equals 1/2 <u.u> in physical space
+    u = [np.fft.irfftn(st[i], s=(N, N, N), axes=(0, 1, 2)) for i in range(3)]
+    assert abs(sp["K"] - 0.5 * np.mean(u[0] ** 2 + u[1] ** 2 + u[2] ** 2)) <= 1e-12 * sp["K"]
+    assert abs(sp["E"].sum() - sp["K"]) <= 1e-12 * sp["K"]
+
+
+def test_table1_derived_scales():
+    N = 16
+    st = ora.init_field(N, 0, 2, 3.0, 1.5)
+    nu = 0.02
+    sp = ora.spectra(st, ora.Params(nu=nu))
+    urms = math.sqrt(2 * 1.5 / 3)
+    assert abs(sp["u_rms"] - urms) < 1e-13
+    eps = sp["eps"]
+    assert abs(sp["eta"] - (nu ** 3 / eps) ** 0.25) < 1e-15
+    assert abs(sp["Re_lambda"] - urms * math.sqrt(15 * nu / eps) * urms / nu) < 1e-10
+    assert abs(sp["T_e"] - (urms ** 3 / eps) / urms) < 1e-12
+
+
+def test_scalar_variance_and_production_physical():
+    N = 16
+    K = ora.kmax_retained(N)
+    st = inputs.random_spectral_state(N, 4, 8, K, 3.0)
+    g = (0.2, 1.0, -0.4)
+    prm = ora.Params(nu=0.01, schmidt=(0.7,), mean_grad=(g,))
+    sp = ora.spectra(st, prm)
+    f = [np.fft.irfftn(st[i], s=(N, N, N), axes=(0, 1, 2)) for i in range(4)]
+    assert abs(sp["phi_var"][0] - np.mean(f[3] ** 2)) <= 1e-12 * sp["phi_var"][0]
+    prod = -2 * np.mean(f[3] * (g[0] * f[0] + g[1] * f[1] + g[2] * f[2]))
+    assert abs(sp["production"][0] - prod) <= 1e-12 * abs(prod)
+    assert abs(2 * sp["E_phi"][0].sum() - sp["phi_var"][0]) <= 1e-12 * sp["phi_var"][0]
