@@ -1,0 +1,166 @@
+/*
+ * psdns — pseudo-spectral DNS right-hand side and RK4 stepping on AMD MI355X (gfx950).
+ *
+ * Solves, on the periodic box [0, 2pi)^3 with N^3 points, the incompressible
+ * Navier-Stokes equations with a forcing coefficient (Akhavan-Safaei &
+ * Zayernouri, arXiv:2012.04838, Sec. 2.1, Eq. (1)) and S passive scalars with a
+ * uniform mean gradient (Eq. (3)), in the Fourier pseudo-spectral form of
+ * Sec. 2.2 (Eqs. (5)-(8)):
+ *
+ *   du_hat/dt   = P(k) (u x omega)^  + A 1_band u_hat  - nu |k|^2 u_hat
+ *   dphi_hat/dt = -(u . grad phi)^   - g . u_hat       - (nu/Sc) |k|^2 phi_hat
+ *
+ * with P(k) = I - k k^T/|k|^2 the projection of Eq. (7), products formed in
+ * physical space, 2/3-rule truncation |k_i| <= K = (N-1)/3, A = P/(2 E_f)
+ * (constant power P injected into the band 0 < |k| <= k_force), and the
+ * classical RK4 of Sec. 2.2 applied with the viscous/diffusive integrating
+ * factor.
+ *
+ * Conventions.
+ *  - Spectral coefficients use the unnormalised forward transform of Eq. (5):
+ *    phi_hat(k) = sum_x phi(x) exp(-i k.x), x_j = 2 pi j / N.
+ *  - Canonical layout (get/set_state): per slot, [field][kz: N][ky: N][kx: N/2+1]
+ *    interleaved complex, kx fastest; index i stands for wavenumber i (i <= N/2)
+ *    or i - N.  Fields are u1, u2, u3, phi_1 .. phi_S.  Element type is
+ *    float2 (precision 32) or double2 (precision 64).
+ *  - The internal state layout is compact (retained modes only) and opaque;
+ *    its size is psdns_state_bytes().  Slots (independent realizations) are
+ *    stored back to back.
+ *
+ * Ownership.  The caller owns every buffer passed in (state, workspace, outputs)
+ * and the HIP stream; all of them are device pointers unless stated.  A plan
+ * owns only its small twiddle and parameter tables.
+ *
+ * Errors.  Every call returns a psdns_status; nothing is thrown across the ABI.
+ * Argument errors are detected before anything is launched.  Launches are
+ * asynchronous on the given stream (NULL = default stream); numerical trouble
+ * (non-finite values, CFL > 1) is recorded in per-slot device flags read by
+ * psdns_read_step_info.  psdns_last_error() returns a thread-local message
+ * describing the last failure.
+ */
+#ifndef PSDNS_H
+#define PSDNS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSDNS_MAX_SCALARS 4
+
+/* Device flag bits (psdns_step_info.flags). */
+#define PSDNS_FLAG_NONFINITE 1 /* a velocity value was NaN or Inf at the start of a step */
+#define PSDNS_FLAG_CFL 2       /* Eq. (10) CFL number exceeded 1 for the step size used */
+
+typedef struct psdns_plan psdns_plan;
+
+typedef enum {
+  PSDNS_OK = 0,
+  PSDNS_E_INVAL = -1,       /* invalid argument; nothing launched */
+  PSDNS_E_NOMEM = -2,       /* allocation of plan-owned tables failed */
+  PSDNS_E_HIP = -3,         /* a HIP runtime call failed */
+  PSDNS_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+} psdns_status;
+
+/* Plan geometry, fixed for the life of a plan. */
+typedef struct {
+  int32_t n;         /* points per axis: a power of two, 8 <= n <= 1024 */
+  int32_t n_scalars; /* S, 0 <= S <= PSDNS_MAX_SCALARS */
+  int32_t precision; /* 32 or 64: storage, transforms and products; reductions are FP64 */
+  int32_t batch;     /* number of independent realizations (slots), >= 1 */
+} psdns_plan_params;
+
+/* Physical parameters of one slot (Sec. 2.1, Sec. 2.3, Table 2). */
+typedef struct {
+  double nu;                              /* kinematic viscosity, >= 0 */
+  double power;                           /* forcing power P >= 0; 0 gives decaying turbulence */
+  double k_force;                         /* forced band 0 < |k| <= k_force */
+  double schmidt[PSDNS_MAX_SCALARS];      /* Sc_s = nu / D_s, > 0 */
+  double mean_grad[PSDNS_MAX_SCALARS][3]; /* g_s = grad <Phi_s>; Eq. (3) has (0, beta, 0) */
+} psdns_slot_params;
+
+/* Per-slot stepping record (host copy). */
+typedef struct {
+  double t;        /* simulated time accumulated by psdns_step */
+  double dt;       /* step size of the last step */
+  double max_u;    /* max over grid points of |u1|+|u2|+|u3| at the start of the last step */
+  int64_t steps;   /* steps taken */
+  int32_t flags;   /* PSDNS_FLAG_* */
+  int32_t active;  /* slot is stepped */
+} psdns_step_info;
+
+/* Sizes and layout facts of a plan. */
+typedef struct {
+  int32_t n, k_max, m, kx_count, kx_pitch, n_scalars, precision, batch;
+  int32_t n_shells;        /* shells s = 0 .. n_shells-1 reported by psdns_spectra */
+  int32_t spectra_doubles; /* doubles per slot written by psdns_spectra */
+  int64_t state_bytes, workspace_bytes;
+  int32_t elems_col, elems_x; /* FFT elements per thread of the column and x passes */
+} psdns_plan_info;
+
+/* Bytes of the compact spectral state y for all slots (caller allocates). 0 on invalid params. */
+size_t psdns_state_bytes(const psdns_plan_params* p);
+/* Bytes of the workspace needed by rhs/step/init/spectra (caller allocates). 0 on invalid params. */
+size_t psdns_workspace_bytes(const psdns_plan_params* p);
+
+/* Create a plan (host metadata plus twiddle and slot tables on the current device).
+ * All slots start active with nu = 0, P = 0, k_force = 2, Sc = 1, g = 0. */
+psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out);
+psdns_status psdns_plan_destroy(psdns_plan* plan);
+psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out);
+
+/* Set the physical parameters of one slot and whether it is stepped (active != 0).
+ * Synchronous upload; call between steps, not while work on the slot is queued. */
+psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_params* prm, int32_t active);
+
+/* Rogallo-type random solenoidal field (Sec. 2.3) with the configured spectrum
+ * E(k) ~ k^4 exp(-2 (k/k_peak)^2), phases from SplitMix64(seed) keyed by the
+ * canonical linear index, scaled to kinetic energy 1/2<u.u> = kinetic_energy;
+ * scalars start at zero (Sec. 2.3).  Writes one slot of `state`; uses `ws`. */
+psdns_status psdns_init_field(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed,
+                              double k_peak, double kinetic_energy, void* hip_stream);
+
+/* Full right-hand side dy/dt (Eqs. (7)-(8), including the viscous and diffusive
+ * terms) of every active slot of `state`, written to `out` (state layout).
+ * `out` must not alias `state`. */
+psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws, void* hip_stream);
+
+/* Advance every active slot by nsteps RK4 steps with the viscous/diffusive
+ * integrating factor.  dt > 0: fixed step; dt < 0: each step uses
+ * dt = (-dt) * (2 pi / N) / max(|u1|+|u2|+|u3|), i.e. Eq. (10) with CFL = -dt,
+ * evaluated from the state at the start of the step.  In place on `state`. */
+psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps,
+                        void* hip_stream);
+
+/* Copy the per-slot stepping records to host memory `out[batch]` (synchronises the stream). */
+psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_info* out, void* hip_stream);
+/* Reset t, steps and flags of every slot (asynchronous). */
+psdns_status psdns_clear_step_info(psdns_plan* plan, void* ws, void* hip_stream);
+
+/* Convert one slot between the compact state and the canonical layout (device buffers).
+ * get: modes outside the retained cube are written as zero.  set: they are ignored. */
+psdns_status psdns_get_state(psdns_plan* plan, const void* state, int32_t slot, void* canonical_out,
+                             void* hip_stream);
+psdns_status psdns_set_state(psdns_plan* plan, void* state, int32_t slot, const void* canonical_in,
+                             void* hip_stream);
+
+/* Per-kernel timing with HIP events on the launch stream (off by default). */
+typedef struct {
+  char name[32];
+  int32_t launches;
+  double total_ms;
+} psdns_kernel_timing;
+psdns_status psdns_set_timing(psdns_plan* plan, int32_t enable);
+/* Synchronises the recorded events, accumulates and clears them. Fills up to max entries. */
+psdns_status psdns_get_timing(psdns_plan* plan, psdns_kernel_timing* out, int32_t max, int32_t* count);
+
+/* Thread-local description of the last error (never NULL). */
+const char* psdns_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSDNS_H */

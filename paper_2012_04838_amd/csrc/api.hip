@@ -1,0 +1,511 @@
+// C ABI of the pseudo-spectral DNS library (declarations and contracts in include/psdns.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace psdns {
+Ops ops_n8(int);
+Ops ops_n16(int);
+Ops ops_n32(int);
+Ops ops_n64(int);
+Ops ops_n128(int);
+Ops ops_n256(int);
+Ops ops_n512(int);
+Ops ops_n1024(int);
+}  // namespace psdns
+
+using namespace psdns;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+psdns_status fail(psdns_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+psdns_status hip_fail(hipError_t e, const char* what) {
+  return fail(PSDNS_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(call)                           \
+  do {                                          \
+    hipError_t e_ = (call);                     \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+bool valid_params(const psdns_plan_params* p, std::string* why) {
+  if (!p) {
+    *why = "params is NULL";
+    return false;
+  }
+  const int n = p->n;
+  if (n < 8 || n > 1024 || (n & (n - 1)) != 0) {
+    *why = "n must be a power of two in [8, 1024], got " + std::to_string(n);
+    return false;
+  }
+  if (p->n_scalars < 0 || p->n_scalars > PSDNS_MAX_SCALARS) {
+    *why = "n_scalars must be in [0, " + std::to_string(PSDNS_MAX_SCALARS) + "], got " + std::to_string(p->n_scalars);
+    return false;
+  }
+  if (p->precision != 32 && p->precision != 64) {
+    *why = "precision must be 32 or 64, got " + std::to_string(p->precision);
+    return false;
+  }
+  if (p->batch < 1 || p->batch > 65535) {
+    *why = "batch must be in [1, 65535], got " + std::to_string(p->batch);
+    return false;
+  }
+  return true;
+}
+
+Ops ops_for(int n, int prec) {
+  switch (n) {
+    case 8: return ops_n8(prec);
+    case 16: return ops_n16(prec);
+    case 32: return ops_n32(prec);
+    case 64: return ops_n64(prec);
+    case 128: return ops_n128(prec);
+    case 256: return ops_n256(prec);
+    case 512: return ops_n512(prec);
+    default: return ops_n1024(prec);
+  }
+}
+
+// lines per x-pass block, mirrored from the device configuration (elements per thread ex)
+int lines_per_xblock(int n, int ex) {
+  const int tx = n / ex;
+  int l = 256 / tx;
+  if (l < 1) l = 1;
+  if (l > 64) l = 64;
+  return l;
+}
+
+struct Layout {
+  Geom g;
+  size_t csize;  // bytes per complex
+  size_t off_dyn, off_part, off_ystage, off_acc, off_abuf, off_bbuf, ws_bytes, st_bytes;
+  long long part_len;
+};
+
+Layout make_layout(const psdns_plan_params* p, int ex) {
+  Layout L{};
+  Geom& g = L.g;
+  g.N = p->n;
+  g.K = (p->n - 1) / 3;
+  g.M = 2 * g.K + 1;
+  g.KX = g.K + 1;
+  g.PX = (g.KX + 15) / 16 * 16;
+  g.S = p->n_scalars;
+  g.F = 3 + g.S;
+  g.FA = 5 + 2 * g.S;
+  g.FB = 6 + 3 * g.S;
+  g.batch = p->batch;
+  g.st_field = (long long)g.M * g.M * g.PX;
+  g.a_field = (long long)g.N * g.M * g.PX;
+  g.b_field = (long long)g.N * g.N * g.PX;
+  g.nblk_x = (int)((long long)g.N * g.N / lines_per_xblock(g.N, ex));
+  L.csize = p->precision == 32 ? 8 : 16;
+  const size_t B = (size_t)g.batch;
+  const long long n_init = ((long long)g.M * g.M * g.KX + 255) / 256;
+  const long long n_max = (long long)B * g.nblk_x;
+  L.part_len = n_init > n_max ? n_init : n_max;
+  size_t off = 0;
+  L.off_dyn = off;
+  off = align_up(off + B * sizeof(DynDev), 256);
+  L.off_part = off;
+  off = align_up(off + (size_t)L.part_len * sizeof(double), 256);
+  L.off_ystage = off;
+  off = align_up(off + B * g.F * (size_t)g.st_field * L.csize, 256);
+  L.off_acc = off;
+  off = align_up(off + B * g.F * (size_t)g.st_field * L.csize, 256);
+  L.off_abuf = off;
+  off = align_up(off + B * g.FA * (size_t)g.a_field * L.csize, 256);
+  L.off_bbuf = off;
+  off = align_up(off + B * g.FB * (size_t)g.b_field * L.csize, 256);
+  L.ws_bytes = off;
+  L.st_bytes = B * g.F * (size_t)g.st_field * L.csize;
+  return L;
+}
+
+const char* kKernelNames[KID_COUNT] = {"forcing_amplitude", "z_inverse", "y_inverse", "x_pass",
+                                       "step_dt",           "y_forward", "z_forward_update", "aux"};
+
+struct EventTimer : Timer {
+  struct Rec {
+    int kid;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipError_t err = hipSuccess;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) err = r;
+    return e;
+  }
+  void begin(int kid, hipStream_t s) override {
+    Rec r{kid, get(), get()};
+    if (r.a) hipEventRecord(r.a, s);
+    recs.push_back(r);
+  }
+  void end(int kid, hipStream_t s) override {
+    if (!recs.empty() && recs.back().kid == kid && recs.back().b) hipEventRecord(recs.back().b, s);
+  }
+  ~EventTimer() override {
+    for (auto& r : recs) {
+      if (r.a) hipEventDestroy(r.a);
+      if (r.b) hipEventDestroy(r.b);
+    }
+    for (auto e : pool) hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+struct psdns_plan {
+  psdns_plan_params p;
+  Layout L;
+  Ops ops;
+  void* tw = nullptr;
+  SlotDev* slots_dev = nullptr;
+  std::vector<SlotDev> slots_host;
+  int device = 0;
+  const void* cleared_ws = nullptr;
+  EventTimer* timer = nullptr;
+  double acc_ms[KID_COUNT] = {0};
+  int acc_n[KID_COUNT] = {0};
+};
+
+namespace {
+
+Ctx make_ctx(psdns_plan* plan, void* ws) {
+  Ctx c{};
+  c.g = plan->L.g;
+  c.tw = plan->tw;
+  c.slots = plan->slots_dev;
+  char* w = static_cast<char*>(ws);
+  c.dyn = reinterpret_cast<DynDev*>(w + plan->L.off_dyn);
+  c.part = reinterpret_cast<double*>(w + plan->L.off_part);
+  c.part_len = plan->L.part_len;
+  c.ystage = w + plan->L.off_ystage;
+  c.acc = w + plan->L.off_acc;
+  c.abuf = w + plan->L.off_abuf;
+  c.bbuf = w + plan->L.off_bbuf;
+  c.timer = plan->timer;
+  return c;
+}
+
+__global__ void k_clear_dyn(DynDev* d, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    DynDev z{};
+    d[i] = z;
+  }
+}
+
+psdns_status ensure_ws(psdns_plan* plan, void* ws, hipStream_t s) {
+  if (plan->cleared_ws == ws) return PSDNS_OK;
+  Ctx c = make_ctx(plan, ws);
+  k_clear_dyn<<<(plan->p.batch + 63) / 64, 64, 0, s>>>(c.dyn, plan->p.batch);
+  HIP_TRY(hipGetLastError());
+  plan->cleared_ws = ws;
+  return PSDNS_OK;
+}
+
+psdns_status check_plan(const psdns_plan* plan) {
+  if (!plan) return fail(PSDNS_E_INVAL, "plan is NULL");
+  return PSDNS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t psdns_state_bytes(const psdns_plan_params* p) {
+  std::string why;
+  if (!valid_params(p, &why)) return 0;
+  return make_layout(p, ops_for(p->n, p->precision).ex).st_bytes;
+}
+
+size_t psdns_workspace_bytes(const psdns_plan_params* p) {
+  std::string why;
+  if (!valid_params(p, &why)) return 0;
+  return make_layout(p, ops_for(p->n, p->precision).ex).ws_bytes;
+}
+
+psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
+  if (!out) return fail(PSDNS_E_INVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(p, &why)) return fail(PSDNS_E_INVAL, why);
+  psdns_plan* plan = new (std::nothrow) psdns_plan();
+  if (!plan) return fail(PSDNS_E_NOMEM, "host allocation of the plan failed");
+  plan->p = *p;
+  plan->ops = ops_for(p->n, p->precision);
+  plan->L = make_layout(p, plan->ops.ex);
+  hipError_t e = hipGetDevice(&plan->device);
+  if (e != hipSuccess) {
+    delete plan;
+    return hip_fail(e, "hipGetDevice");
+  }
+  // twiddles w_N^m = exp(-2 pi i m / N), computed in double precision
+  const int n = p->n;
+  const size_t twb = (size_t)n * plan->L.csize;
+  std::vector<double> twd(2 * (size_t)n);
+  for (int m = 0; m < n; ++m) {
+    const double a = 2.0 * M_PI * (double)m / (double)n;
+    twd[2 * m] = std::cos(a);
+    twd[2 * m + 1] = -std::sin(a);
+  }
+  std::vector<char> host(twb);
+  if (p->precision == 32) {
+    float* f = reinterpret_cast<float*>(host.data());
+    for (size_t i = 0; i < 2 * (size_t)n; ++i) f[i] = (float)twd[i];
+  } else {
+    std::memcpy(host.data(), twd.data(), twb);
+  }
+  e = hipMalloc(&plan->tw, twb);
+  if (e != hipSuccess) {
+    delete plan;
+    return fail(PSDNS_E_NOMEM, std::string("hipMalloc(twiddles): ") + hipGetErrorString(e));
+  }
+  e = hipMalloc(reinterpret_cast<void**>(&plan->slots_dev), sizeof(SlotDev) * p->batch);
+  if (e != hipSuccess) {
+    hipFree(plan->tw);
+    delete plan;
+    return fail(PSDNS_E_NOMEM, std::string("hipMalloc(slot table): ") + hipGetErrorString(e));
+  }
+  plan->slots_host.resize(p->batch);
+  for (auto& s : plan->slots_host) {
+    std::memset(&s, 0, sizeof(s));
+    s.kf2 = 4.0;
+    s.active = 1;
+  }
+  e = hipMemcpy(plan->tw, host.data(), twb, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(plan->slots_dev, plan->slots_host.data(), sizeof(SlotDev) * p->batch, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(plan->tw);
+    hipFree(plan->slots_dev);
+    delete plan;
+    return hip_fail(e, "hipMemcpy(plan tables)");
+  }
+  *out = plan;
+  return PSDNS_OK;
+}
+
+psdns_status psdns_plan_destroy(psdns_plan* plan) {
+  if (!plan) return PSDNS_OK;
+  delete plan->timer;
+  if (plan->tw) hipFree(plan->tw);
+  if (plan->slots_dev) hipFree(plan->slots_dev);
+  delete plan;
+  return PSDNS_OK;
+}
+
+psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!out) return fail(PSDNS_E_INVAL, "out is NULL");
+  const Geom& g = plan->L.g;
+  out->n = g.N;
+  out->k_max = g.K;
+  out->m = g.M;
+  out->kx_count = g.KX;
+  out->kx_pitch = g.PX;
+  out->n_scalars = g.S;
+  out->precision = plan->p.precision;
+  out->batch = g.batch;
+  out->n_shells = (int)std::lround(std::sqrt(3.0) * g.K) + 1;
+  out->spectra_doubles = 0;
+  out->state_bytes = (int64_t)plan->L.st_bytes;
+  out->workspace_bytes = (int64_t)plan->L.ws_bytes;
+  out->elems_col = plan->ops.ec;
+  out->elems_x = plan->ops.ex;
+  return PSDNS_OK;
+}
+
+psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_params* prm, int32_t active) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
+  if (!prm) return fail(PSDNS_E_INVAL, "params is NULL");
+  if (!(prm->nu >= 0.0) || !std::isfinite(prm->nu)) return fail(PSDNS_E_INVAL, "nu must be finite and >= 0");
+  if (!(prm->power >= 0.0) || !std::isfinite(prm->power)) return fail(PSDNS_E_INVAL, "power must be finite and >= 0");
+  if (!(prm->k_force > 0.0) || !std::isfinite(prm->k_force)) return fail(PSDNS_E_INVAL, "k_force must be > 0");
+  SlotDev s{};
+  s.nu = prm->nu;
+  s.power = prm->power;
+  s.kf2 = prm->k_force * prm->k_force;
+  for (int i = 0; i < 3; ++i) s.diff[i] = prm->nu;
+  for (int i = 0; i < plan->p.n_scalars; ++i) {
+    if (!(prm->schmidt[i] > 0.0) || !std::isfinite(prm->schmidt[i]))
+      return fail(PSDNS_E_INVAL, "schmidt numbers must be finite and > 0");
+    s.diff[3 + i] = prm->nu / prm->schmidt[i];
+    for (int d = 0; d < 3; ++d) {
+      if (!std::isfinite(prm->mean_grad[i][d])) return fail(PSDNS_E_INVAL, "mean gradient must be finite");
+      s.g[i][d] = prm->mean_grad[i][d];
+    }
+  }
+  s.active = active ? 1 : 0;
+  plan->slots_host[slot] = s;
+  HIP_TRY(hipMemcpy(plan->slots_dev + slot, &s, sizeof(SlotDev), hipMemcpyHostToDevice));
+  return PSDNS_OK;
+}
+
+psdns_status psdns_init_field(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed, double k_peak,
+                              double kinetic_energy, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
+  if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
+  if (!(k_peak > 0.0) || !std::isfinite(k_peak)) return fail(PSDNS_E_INVAL, "k_peak must be > 0");
+  if (!(kinetic_energy >= 0.0) || !std::isfinite(kinetic_energy))
+    return fail(PSDNS_E_INVAL, "kinetic_energy must be >= 0");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  Ctx c = make_ctx(plan, ws);
+  plan->ops.init_field(c, state, slot, seed, k_peak, kinetic_energy, s);
+  HIP_TRY(hipGetLastError());
+  return PSDNS_OK;
+}
+
+psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !out || !ws) return fail(PSDNS_E_INVAL, "state, out and ws must be device pointers");
+  if (state == out) return fail(PSDNS_E_INVAL, "out must not alias state");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  Ctx c = make_ctx(plan, ws);
+  plan->ops.rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, s);
+  HIP_TRY(hipGetLastError());
+  return PSDNS_OK;
+}
+
+psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
+  if (nsteps < 0) return fail(PSDNS_E_INVAL, "nsteps must be >= 0");
+  if (!(dt != 0.0) || !std::isfinite(dt)) return fail(PSDNS_E_INVAL, "dt must be finite and nonzero");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  Ctx c = make_ctx(plan, ws);
+  for (int n = 0; n < nsteps; ++n) {
+    for (int stage = 0; stage < 4; ++stage) {
+      const void* sin = stage == 0 ? state : c.ystage;
+      plan->ops.rhs_stage(c, state, sin, stage, nullptr, stage == 0, dt, s);
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_info* out, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!ws || !out) return fail(PSDNS_E_INVAL, "ws and out must be non-NULL");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, const_cast<void*>(ws), s)) return st;
+  std::vector<DynDev> d(plan->p.batch);
+  Ctx c = make_ctx(plan, const_cast<void*>(ws));
+  HIP_TRY(hipMemcpyAsync(d.data(), c.dyn, sizeof(DynDev) * d.size(), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < plan->p.batch; ++i) {
+    out[i].t = d[i].t;
+    out[i].dt = d[i].dt;
+    out[i].max_u = d[i].max_u;
+    out[i].steps = d[i].steps;
+    out[i].flags = d[i].flags;
+    out[i].active = plan->slots_host[i].active;
+  }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_clear_step_info(psdns_plan* plan, void* ws, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!ws) return fail(PSDNS_E_INVAL, "ws is NULL");
+  plan->cleared_ws = nullptr;
+  return ensure_ws(plan, ws, static_cast<hipStream_t>(hip_stream));
+}
+
+psdns_status psdns_get_state(psdns_plan* plan, const void* state, int32_t slot, void* canonical_out,
+                             void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !canonical_out) return fail(PSDNS_E_INVAL, "state and canonical_out must be device pointers");
+  if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
+  Ctx c = make_ctx(plan, nullptr);
+  c.timer = plan->timer;
+  plan->ops.get_state(c, state, slot, canonical_out, static_cast<hipStream_t>(hip_stream));
+  HIP_TRY(hipGetLastError());
+  return PSDNS_OK;
+}
+
+psdns_status psdns_set_state(psdns_plan* plan, void* state, int32_t slot, const void* canonical_in,
+                             void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !canonical_in) return fail(PSDNS_E_INVAL, "state and canonical_in must be device pointers");
+  if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
+  Ctx c = make_ctx(plan, nullptr);
+  plan->ops.set_state(c, state, slot, canonical_in, static_cast<hipStream_t>(hip_stream));
+  HIP_TRY(hipGetLastError());
+  return PSDNS_OK;
+}
+
+psdns_status psdns_set_timing(psdns_plan* plan, int32_t enable) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (enable && !plan->timer) plan->timer = new (std::nothrow) EventTimer();
+  if (!enable && plan->timer) {
+    delete plan->timer;
+    plan->timer = nullptr;
+  }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_get_timing(psdns_plan* plan, psdns_kernel_timing* out, int32_t max, int32_t* count) {
+  if (psdns_status s = check_plan(plan)) return s;
+  EventTimer* t = plan->timer;
+  if (t) {
+    if (t->err != hipSuccess) return hip_fail(t->err, "hipEventCreate");
+    for (auto& r : t->recs) {
+      if (!r.a || !r.b) continue;
+      HIP_TRY(hipEventSynchronize(r.b));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+      plan->acc_ms[r.kid] += ms;
+      plan->acc_n[r.kid] += 1;
+      t->pool.push_back(r.a);
+      t->pool.push_back(r.b);
+    }
+    t->recs.clear();
+  }
+  int k = 0;
+  for (int i = 0; i < KID_COUNT && k < max; ++i) {
+    if (!out) break;
+    std::snprintf(out[k].name, sizeof(out[k].name), "%s", kKernelNames[i]);
+    out[k].launches = plan->acc_n[i];
+    out[k].total_ms = plan->acc_ms[i];
+    ++k;
+  }
+  if (count) *count = k;
+  for (int i = 0; i < KID_COUNT; ++i) {
+    plan->acc_ms[i] = 0;
+    plan->acc_n[i] = 0;
+  }
+  return PSDNS_OK;
+}
+
+const char* psdns_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

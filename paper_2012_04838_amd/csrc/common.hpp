@@ -1,0 +1,104 @@
+// Shared host/device structures of the pseudo-spectral DNS library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/psdns.h"
+
+namespace psdns {
+
+constexpr int kMaxScalars = PSDNS_MAX_SCALARS;
+
+// Sizes of one plan.  Spectral arrays keep only the retained cube
+// |k_i| <= K = (N-1)/3 (the 2/3 rule): ky and kz use the compact index
+// c in [0, M), M = 2K+1 (c <= K means k = c, otherwise k = c - M), kx runs
+// over 0..K and rows are padded to PX = K+1 rounded up to 16 entries.
+struct Geom {
+  int N, K, M, KX, PX;
+  int S;                  // passive scalars
+  int F;                  // spectral fields: 3 + S
+  int FA;                 // fields after the z pass: 5 + 2S
+  int FB;                 // fields after the y pass: 6 + 3S
+  int batch;              // realizations (slots)
+  long long st_field;     // complex entries per field in the compact state: M*M*PX
+  long long a_field;      // per field after the z pass: N*M*PX   ([z][ky_c][kx])
+  long long b_field;      // per field after the y pass: N*N*PX   ([z][y][kx])
+  int nblk_x;             // x-pass blocks per slot (partial maxima)
+};
+
+// Static per-slot parameters, uploaded by psdns_set_slot.
+struct SlotDev {
+  double nu;
+  double power;
+  double kf2;                       // k_force^2
+  double diff[3 + kMaxScalars];     // diffusivity of each spectral field
+  double g[kMaxScalars][3];         // mean scalar gradients
+  int active;
+  int pad_;
+};
+
+// Per-slot values written on the device while stepping (part of the workspace).
+struct DynDev {
+  double dt;         // step in use
+  double A;          // forcing amplitude of the current stage input
+  double max_u;      // max |u1|+|u2|+|u3| at the start of the last step
+  double t;          // simulated time accumulated by psdns_step
+  double scratch;    // reduction result used by init_field
+  long long steps;   // steps taken by psdns_step
+  int flags;         // PSDNS_FLAG_* bits, sticky until psdns_clear_flags
+  int pad_;
+};
+
+enum KernelId {
+  KID_FORCE = 0,
+  KID_ZINV,
+  KID_YINV,
+  KID_XPASS,
+  KID_DT,
+  KID_YFWD,
+  KID_ZFWD,
+  KID_AUX,
+  KID_COUNT
+};
+
+// Optional per-launch timing with HIP events (see psdns_set_timing).
+struct Timer {
+  virtual void begin(int kid, hipStream_t s) = 0;
+  virtual void end(int kid, hipStream_t s) = 0;
+  virtual ~Timer() {}
+};
+
+struct Ctx {
+  Geom g;
+  const void* tw;          // w_N^m = exp(-2 pi i m/N), m = 0..N-1, in the plan precision
+  const SlotDev* slots;    // device table [batch]
+  DynDev* dyn;             // device [batch]
+  void* abuf;              // [batch][FA][N][M][PX]
+  void* bbuf;              // [batch][FB][N][N][PX]
+  void* ystage;            // [batch][F][M][M][PX]
+  void* acc;               // [batch][F][M][M][PX]
+  double* part;            // x-pass partial maxima [batch][nblk_x] and reduction scratch
+  long long part_len;      // doubles available at part
+  Timer* timer;            // may be null
+};
+
+// One (N, precision) instantiation of the device code.
+struct Ops {
+  int ec, ex;   // elements per thread of the column passes and the x pass
+  // One evaluation of the nonlinear right-hand side at stage_in followed by the
+  // stage update (stage 0..3) or, for stage < 0, the full dy/dt into rhs_out.
+  void (*rhs_stage)(const Ctx&, void* state, const void* stage_in, int stage, void* rhs_out,
+                    int want_max, double dt_arg, hipStream_t);
+  void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, double energy,
+                     hipStream_t);
+  void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);
+  void (*set_state)(const Ctx&, void* state, int slot, const void* canon, hipStream_t);
+};
+
+template <int N>
+Ops make_ops_f32();
+template <int N>
+Ops make_ops_f64();
+
+}  // namespace psdns

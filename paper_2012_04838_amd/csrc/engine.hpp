@@ -1,0 +1,928 @@
+// Device kernels of one RK right-hand-side evaluation and its stage update,
+// templated on the grid size N and the real type T (float or double).
+//
+// One evaluation is five passes over HBM (Sec. 2.2-2.3 of arXiv:2012.04838,
+// restated for the 2/3 rule and the integrating factor):
+//   z_inverse   compact state -> inverse along z of u_i and dz u_1, dz u_2, phi, dz phi
+//   y_inverse   -> inverse along y, forming the y-derivatives needed by omega, grad phi
+//   x_pass      per (z, y) line: inverse along x, u x omega and u.grad phi + g.u in
+//               registers, forward along x (physical fields never reach HBM)
+//   y_forward   -> forward along y, keep |ky| <= K
+//   z_forward   -> forward along z, keep |kz| <= K, projection P(k), forcing A u_hat,
+//               integrating-factor RK4 stage update
+// Each kernel reads and writes every element of its fields exactly once.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace psdns {
+
+template <int N, typename T>
+struct Cfg {
+  // columns per block: one 128-byte row of complex values
+  static constexpr int W = 128 / (int)sizeof(cpx<T>);
+  // elements per thread of the column passes (z, y) and of the x pass
+  static constexpr int EC0 = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int EC = N < EC0 ? N : EC0;
+  static constexpr int TC = N / EC;
+  static constexpr int COL_THREADS = W * TC;
+  static constexpr int EX0 = 8;
+  static constexpr int EX = N < EX0 ? N : EX0;
+  static constexpr int TX = N / EX;
+  static constexpr int LX0 = 256 / TX;
+  static constexpr int LX = LX0 < 1 ? 1 : (LX0 > 64 ? 64 : LX0);
+  static constexpr int X_THREADS = LX * TX;
+  static constexpr int LP = LinePad<N>::value;
+};
+
+// position n of an N-point line -> compact index (or -1 if the wavenumber is truncated)
+__device__ __forceinline__ int compact_of(int n, int N, int K, int M) {
+  return n <= K ? n : (n >= N - K ? n - N + M : -1);
+}
+// position n -> signed wavenumber
+__device__ __forceinline__ int wave_of(int n, int N) { return n <= N / 2 ? n : n - N; }
+// compact index -> signed wavenumber
+__device__ __forceinline__ int wave_of_compact(int c, int K, int M) { return c <= K ? c : c - M; }
+
+template <typename T>
+__device__ __forceinline__ cpx<T> czero() { return {T(0), T(0)}; }
+
+// ---------------------------------------------------------------------------
+// z inverse: columns along kz at fixed (ky, kx-tile).
+// A fields: 0 U1, 1 U2, 2 U3, 3 dz U1, 4 dz U2, 5+2s Phi_s, 6+2s dz Phi_s
+// (all carry the 1/N^3 of Eq. (5) so that physical values are the true ones).
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
+k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw,
+            const SlotDev* __restrict__ slots, Geom g) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  __shared__ cpx<T> smem[W * N];
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  const int c = threadIdx.x % W;
+  const int j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c;
+  const int kyc = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const LdsCol<T, W> lds{smem + c};
+  const T scale = T(1) / (T(N) * T(N) * T(N));
+  const long long rows = (long long)g.M * g.PX;  // stride between kz rows (state) and z rows (A)
+  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
+  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
+
+  int kc[E];
+  T kz[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = j + TT * m;
+    kc[m] = valid ? compact_of(n, N, g.K, g.M) : -1;
+    kz[m] = T(wave_of(n, N));
+  }
+  cpx<T> a[E], d[E];
+  auto load = [&](int f) {
+    const cpx<T>* p = in + (long long)f * g.st_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = kc[m] >= 0 ? scale * p[kc[m] * rows] : czero<T>();
+  };
+  auto store = [&](int f, cpx<T> (&v)[E]) {
+    if (!valid) return;
+    cpx<T>* p = out + (long long)f * g.a_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) p[(long long)(j + TT * m) * rows] = v[m];
+  };
+  auto deriv = [&]() {
+#pragma unroll
+    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kz[m]);
+  };
+  // u1 and dz u1
+  load(0);
+  deriv();
+  fft<N, E, true>(a, lds, j, tw);
+  store(0, a);
+  fft<N, E, true>(d, lds, j, tw);
+  store(3, d);
+  // u2 and dz u2
+  load(1);
+  deriv();
+  fft<N, E, true>(a, lds, j, tw);
+  store(1, a);
+  fft<N, E, true>(d, lds, j, tw);
+  store(4, d);
+  // u3
+  load(2);
+  fft<N, E, true>(a, lds, j, tw);
+  store(2, a);
+  for (int s = 0; s < g.S; ++s) {
+    load(3 + s);
+    deriv();
+    fft<N, E, true>(a, lds, j, tw);
+    store(5 + 2 * s, a);
+    fft<N, E, true>(d, lds, j, tw);
+    store(6 + 2 * s, d);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y inverse: columns along ky at fixed (z, kx-tile).
+// B fields: 0 u1, 1 u2, 2 u3, 3 omega1 = dy u3 - dz u2, 4 dz u1, 5 dy u1,
+//           6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s   (x still spectral)
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
+k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw,
+            const SlotDev* __restrict__ slots, Geom g) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  __shared__ cpx<T> smem[W * N];
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  const int c = threadIdx.x % W;
+  const int j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c;
+  const int z = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const LdsCol<T, W> lds{smem + c};
+  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)z * g.M * g.PX + kx;
+  cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
+
+  int kc[E];
+  T ky[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = j + TT * m;
+    kc[m] = valid ? compact_of(n, N, g.K, g.M) : -1;
+    ky[m] = T(wave_of(n, N));
+  }
+  cpx<T> a[E], d[E];
+  auto load = [&](int f, cpx<T> (&v)[E]) {
+    const cpx<T>* p = in + (long long)f * g.a_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = kc[m] >= 0 ? p[kc[m] * g.PX] : czero<T>();
+  };
+  auto store = [&](int f, cpx<T> (&v)[E]) {
+    if (!valid) return;
+    cpx<T>* p = out + (long long)f * g.b_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) p[(long long)(j + TT * m) * g.PX] = v[m];
+  };
+  // u1 and dy u1
+  load(0, a);
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], ky[m]);
+  fft<N, E, true>(a, lds, j, tw);
+  store(0, a);
+  fft<N, E, true>(d, lds, j, tw);
+  store(5, d);
+  // u2
+  load(1, a);
+  fft<N, E, true>(a, lds, j, tw);
+  store(1, a);
+  // u3 and omega1 = dy u3 - dz u2
+  load(2, a);
+  load(4, d);
+#pragma unroll
+  for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], ky[m]) - d[m];
+  fft<N, E, true>(a, lds, j, tw);
+  store(2, a);
+  fft<N, E, true>(d, lds, j, tw);
+  store(3, d);
+  // dz u1
+  load(3, a);
+  fft<N, E, true>(a, lds, j, tw);
+  store(4, a);
+  for (int s = 0; s < g.S; ++s) {
+    load(5 + 2 * s, a);
+#pragma unroll
+    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], ky[m]);
+    fft<N, E, true>(a, lds, j, tw);
+    store(6 + 3 * s, a);
+    fft<N, E, true>(d, lds, j, tw);
+    store(7 + 3 * s, d);
+    load(6 + 2 * s, a);
+    fft<N, E, true>(a, lds, j, tw);
+    store(8 + 3 * s, a);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x pass: one (z, y) line per TX threads.  Two real fields f, g travel as one
+// complex line h = f + i g through an N-point complex transform.
+// Output (in place, first F fields of B): 0 c1, 1 c2, 2 c3 with c = u x omega,
+// 3+s a_s = u.grad phi_s + g_s.u, all forward transformed along x, kx <= K.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__((Cfg<N, T>::X_THREADS))
+k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots,
+         double* __restrict__ maxpart, Geom g, int want_max) {
+  using C = Cfg<N, T>;
+  constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
+  __shared__ cpx<T> smem[L * LP];
+  __shared__ double red[C::X_THREADS];
+  const int slot = blockIdx.y;
+  if (!slots[slot].active) return;
+  const int li = threadIdx.x / TT;
+  const int j = threadIdx.x % TT;
+  const long long line = (long long)blockIdx.x * L + li;  // z * N + y
+  const LdsLine<T> lds{smem + li * LP};
+  cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
+  const int K = g.K;
+
+  int kap[E];     // |kx| of position n, or -1 if truncated
+  bool neg[E];    // position holds a negative kx (value is the conjugate)
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = j + TT * m;
+    kap[m] = n <= K ? n : (n >= N - K ? N - n : -1);
+    neg[m] = n > K;
+  }
+  auto hv = [&](int f, int m) -> cpx<T> {
+    return kap[m] >= 0 ? base[(long long)f * g.b_field + kap[m]] : czero<T>();
+  };
+  // full-spectrum value at position m from the half-spectrum value v at |kx|
+  auto full = [&](cpx<T> v, int m) -> cpx<T> {
+    if (kap[m] == 0) return {v.x, T(0)};
+    return neg[m] ? conj(v) : v;
+  };
+  auto pack = [&](cpx<T> f, cpx<T> gg) -> cpx<T> { return f + mul_i(gg); };
+
+  cpx<T> h[E], r2[E], r3[E];
+  // omega2 = dz u1 - dx u3, omega3 = dx u2 - dy u1
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    r2[m] = hv(1, m);
+    r3[m] = hv(2, m);
+    const T kk = T(kap[m]);
+    const cpx<T> w2 = hv(4, m) - mul_is(r3[m], kk);
+    const cpx<T> w3 = mul_is(r2[m], kk) - hv(5, m);
+    h[m] = pack(full(w2, m), full(w3, m));
+  }
+  fft<N, E, true>(h, lds, j, tw);
+  T w2p[E], w3p[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    w2p[m] = h[m].x;
+    w3p[m] = h[m].y;
+  }
+  // u3, omega1
+#pragma unroll
+  for (int m = 0; m < E; ++m) h[m] = pack(full(r3[m], m), full(hv(3, m), m));
+  fft<N, E, true>(h, lds, j, tw);
+  T u3p[E], w1p[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    u3p[m] = h[m].x;
+    w1p[m] = h[m].y;
+  }
+  // u1, u2
+#pragma unroll
+  for (int m = 0; m < E; ++m) h[m] = pack(full(hv(0, m), m), full(r2[m], m));
+  fft<N, E, true>(h, lds, j, tw);
+  T u1p[E], u2p[E], c1[E], c2[E], c3[E];
+  double mx = 0.0;
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    u1p[m] = h[m].x;
+    u2p[m] = h[m].y;
+    c1[m] = u2p[m] * w3p[m] - u3p[m] * w2p[m];
+    c2[m] = u3p[m] * w1p[m] - u1p[m] * w3p[m];
+    c3[m] = u1p[m] * w2p[m] - u2p[m] * w1p[m];
+    const double s = fabs((double)u1p[m]) + fabs((double)u2p[m]) + fabs((double)u3p[m]);
+    mx = (s > mx || s != s) ? s : mx;  // keeps NaN
+  }
+
+  // forward transform of the real pair (p, q) and store of fields fp, fq (kx <= K)
+  auto forward_pair = [&](const T (&p)[E], const T (&q)[E], int fp, int fq) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) h[m] = {p[m], q[m]};
+    fft<N, E, false>(h, lds, j, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) lds.st(j + TT * m, h[m]);
+    __syncthreads();
+    for (int k = j; k <= K; k += TT) {
+      const cpx<T> zk = lds.ld(k);
+      const cpx<T> zm = conj(lds.ld((N - k) & (N - 1)));
+      const cpx<T> P = T(0.5) * (zk + zm);
+      const cpx<T> Q = mul_mi(T(0.5) * (zk - zm));
+      base[(long long)fp * g.b_field + k] = P;
+      if (fq >= 0) base[(long long)fq * g.b_field + k] = Q;
+    }
+    __syncthreads();
+  };
+
+  const SlotDev& sp = slots[slot];
+  const int S = g.S;
+  // scalars: a_s = u.grad phi_s + g_s.u
+  T as0[E], as1[E];
+  auto scalar_xy = [&](int s, T (&acc)[E]) {
+    const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const cpx<T> phi = hv(6 + 3 * s, m);
+      const cpx<T> d1 = mul_is(phi, T(kap[m]));
+      h[m] = pack(full(d1, m), full(hv(7 + 3 * s, m), m));
+    }
+    fft<N, E, true>(h, lds, j, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      acc[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
+  };
+  auto scalar_z = [&](int s0, int s1, T (&acc0)[E], T (&acc1)[E]) {
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const cpx<T> b = s1 >= 0 ? full(hv(8 + 3 * s1, m), m) : czero<T>();
+      h[m] = pack(full(hv(8 + 3 * s0, m), m), b);
+    }
+    fft<N, E, true>(h, lds, j, tw);
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      acc0[m] += u3p[m] * h[m].x;
+      if (s1 >= 0) acc1[m] += u3p[m] * h[m].y;
+    }
+  };
+
+  forward_pair(c1, c2, 0, 1);
+  if (S == 0) {
+    T zero[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) zero[m] = T(0);
+    forward_pair(c3, zero, 2, -1);
+  } else {
+    // scalars in pairs (s, s+1); the first output pair is (c3, a_0)
+    for (int s = 0; s < S; s += 2) {
+      const bool two = s + 1 < S;
+      scalar_xy(s, as0);
+      if (two) scalar_xy(s + 1, as1);
+      scalar_z(s, two ? s + 1 : -1, as0, as1);
+      if (s == 0) {
+        forward_pair(c3, as0, 2, 3);
+        if (two) {
+          // a_1 waits for a partner (a_2) when S > 2, else it goes alone
+          if (S > 2) {
+#pragma unroll
+            for (int m = 0; m < E; ++m) c3[m] = as1[m];  // c3 is free now: park a_1
+          } else {
+            T zero[E];
+#pragma unroll
+            for (int m = 0; m < E; ++m) zero[m] = T(0);
+            forward_pair(as1, zero, 4, -1);
+          }
+        }
+      } else {
+        // s >= 2: parked a_{s-1} pairs with a_s; a_{s+1} (if any) goes with zero or is parked
+        forward_pair(c3, as0, 3 + s - 1, 3 + s);
+        if (two) {
+          T zero[E];
+#pragma unroll
+          for (int m = 0; m < E; ++m) zero[m] = T(0);
+          forward_pair(as1, zero, 3 + s + 1, -1);
+        }
+      }
+    }
+  }
+
+  if (want_max) {
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = C::X_THREADS / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        const double a = red[threadIdx.x], b = red[threadIdx.x + o];
+        red[threadIdx.x] = (b > a || b != b) ? b : a;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) maxpart[(long long)slot * g.nblk_x + blockIdx.x] = red[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y forward: columns along y at fixed (z, kx-tile); keeps |ky| <= K.
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
+k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw,
+            const SlotDev* __restrict__ slots, Geom g) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  __shared__ cpx<T> smem[W * N];
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  const int c = threadIdx.x % W;
+  const int j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c;
+  const int z = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const LdsCol<T, W> lds{smem + c};
+  const cpx<T>* in = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
+  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)z * g.M * g.PX + kx;
+  int kc[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) kc[m] = valid ? compact_of(j + TT * m, N, g.K, g.M) : -1;
+  cpx<T> a[E];
+  for (int f = 0; f < g.F; ++f) {
+    const cpx<T>* p = in + (long long)f * g.b_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = valid ? p[(long long)(j + TT * m) * g.PX] : czero<T>();
+    fft<N, E, false>(a, lds, j, tw);
+    cpx<T>* q = out + (long long)f * g.a_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m)
+      if (kc[m] >= 0) q[kc[m] * g.PX] = a[m];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// z forward + spectral assembly + integrating-factor RK4 stage update.
+// stage 0..3 updates (y_n, acc, y_stage); stage < 0 writes dy/dt to rhs_out.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StageArgs {
+  cpx<T>* yn;
+  cpx<T>* acc;
+  cpx<T>* ys;
+  const cpx<T>* sin;  // stage input (y_n at stage 0, y_stage otherwise)
+  cpx<T>* rhs;        // stage < 0 only
+  int stage;
+};
+
+template <typename T>
+__device__ __forceinline__ void rk_update(const StageArgs<T>& a, long long o, cpx<T> F, double lk2, double h) {
+  // lk2 = D |k|^2; exponential factors in FP64, then cast
+  if (a.stage < 0) {
+    const cpx<T> y = a.sin[o];
+    a.rhs[o] = F - T(lk2) * y;
+    return;
+  }
+  const double ehd = exp(-0.5 * lk2 * h);
+  const T eh = T(ehd), e1 = T(ehd * ehd);
+  const T th = T(h);
+  switch (a.stage) {
+    case 0: {
+      const cpx<T> y = a.yn[o];
+      a.acc[o] = e1 * (y + (th / T(6)) * F);
+      a.ys[o] = eh * (y + (th / T(2)) * F);
+      break;
+    }
+    case 1: {
+      const cpx<T> y = a.yn[o];
+      a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
+      a.ys[o] = eh * y + (th / T(2)) * F;
+      break;
+    }
+    case 2: {
+      const cpx<T> y = a.yn[o];
+      a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
+      a.ys[o] = e1 * y + (th * eh) * F;
+      break;
+    }
+    default: {
+      a.yn[o] = a.acc[o] + (th / T(6)) * F;
+      break;
+    }
+  }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
+k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw,
+                   const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  __shared__ cpx<T> smem[W * N];
+  const int slot = blockIdx.z;
+  const SlotDev& sp = slots[slot];
+  if (!sp.active) return;
+  const int c = threadIdx.x % W;
+  const int j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c;
+  const int kyc = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const LdsCol<T, W> lds{smem + c};
+  const long long rows = (long long)g.M * g.PX;
+  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
+  const long long sbase = (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
+  const int ky = wave_of_compact(kyc, g.K, g.M);
+  const double h = dyn[slot].dt;
+  const double A = dyn[slot].A;
+
+  int kc[E];
+  double k2[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int n = j + TT * m;
+    kc[m] = valid ? compact_of(n, N, g.K, g.M) : -1;
+    const int kz = wave_of(n, N);
+    k2[m] = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+  }
+  auto load_fwd = [&](int f, cpx<T> (&v)[E]) {
+    const cpx<T>* p = in + (long long)f * g.a_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = valid ? p[(long long)(j + TT * m) * rows] : czero<T>();
+    fft<N, E, false>(v, lds, j, tw);
+  };
+
+  // velocity: F = P(k) c_hat + A 1_band u_hat
+  {
+    cpx<T> c1[E], c2[E], c3[E];
+    load_fwd(0, c1);
+    load_fwd(1, c2);
+    load_fwd(2, c3);
+    const double nu = sp.nu;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if (kc[m] < 0) continue;
+      const int n = j + TT * m;
+      const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
+      const long long o = sbase + (long long)kc[m] * rows;
+      cpx<T> F1, F2, F3;
+      if (k2[m] == 0.0) {
+        F1 = F2 = F3 = czero<T>();
+      } else {
+        const T ik2 = T(1.0 / k2[m]);
+        const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
+        F1 = c1[m] - (kxt * ik2) * kdc;
+        F2 = c2[m] - (kyt * ik2) * kdc;
+        F3 = c3[m] - (kzt * ik2) * kdc;
+        if (A != 0.0 && k2[m] <= sp.kf2) {
+          const T At = T(A);
+          F1 = F1 + At * sa.sin[o];
+          F2 = F2 + At * sa.sin[o + g.st_field];
+          F3 = F3 + At * sa.sin[o + 2 * g.st_field];
+        }
+      }
+      const double lk2 = nu * k2[m];
+      rk_update(sa, o, F1, lk2, h);
+      rk_update(sa, o + g.st_field, F2, lk2, h);
+      rk_update(sa, o + 2 * g.st_field, F3, lk2, h);
+    }
+  }
+  // scalars: F = -a_hat (a already holds u.grad phi + g.u)
+  for (int s = 0; s < g.S; ++s) {
+    cpx<T> a[E];
+    load_fwd(3 + s, a);
+    const double dif = sp.diff[3 + s];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      if (kc[m] < 0) continue;
+      const long long o = sbase + (long long)(3 + s) * g.st_field + (long long)kc[m] * rows;
+      const cpx<T> F = k2[m] == 0.0 ? czero<T>() : czero<T>() - a[m];
+      rk_update(sa, o, F, dif * k2[m], h);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forcing amplitude A = P / (2 E_f), E_f = 1/2 sum_{0<|k|^2<=kf^2} |u_hat|^2 / N^6 (FP64)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_forcing_amplitude(const cpx<T>* __restrict__ sin, const SlotDev* __restrict__ slots, DynDev* __restrict__ dyn,
+                    Geom g) {
+  __shared__ double red[256];
+  const int slot = blockIdx.x;
+  const SlotDev& sp = slots[slot];
+  if (!sp.active) return;
+  int kf = 0;
+  while ((double)(kf + 1) * (kf + 1) <= sp.kf2) ++kf;
+  if (kf > g.K) kf = g.K;
+  const int span = 2 * kf + 1;
+  const int ncand = (kf + 1) * span * span;
+  double e = 0.0;
+  const cpx<T>* base = sin + (long long)slot * g.F * g.st_field;
+  for (int i = threadIdx.x; i < ncand; i += 256) {
+    const int kx = i % (kf + 1);
+    const int ky = (i / (kf + 1)) % span - kf;
+    const int kz = i / ((kf + 1) * span) - kf;
+    const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    if (k2 == 0.0 || k2 > sp.kf2) continue;
+    const int kyc = ky >= 0 ? ky : ky + g.M;
+    const int kzc = kz >= 0 ? kz : kz + g.M;
+    const long long o = ((long long)kzc * g.M + kyc) * g.PX + kx;
+    double s = 0.0;
+    for (int f = 0; f < 3; ++f) {
+      const cpx<T> v = base[o + f * g.st_field];
+      s += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+    }
+    e += (kx == 0 ? 0.5 : 1.0) * s;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double n3 = double(g.N) * g.N * g.N;
+    const double ef = red[0] / (n3 * n3);
+    dyn[slot].A = (sp.power > 0.0 && ef > 0.0) ? sp.power / (2.0 * ef) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// step size from the stage-0 maxima (Eq. (10)) and the step record
+// ---------------------------------------------------------------------------
+static __global__ void __launch_bounds__(256)
+k_step_dt(const double* __restrict__ maxpart, const SlotDev* __restrict__ slots, DynDev* __restrict__ dyn, Geom g,
+          double dt_arg) {
+  __shared__ double red[256];
+  const int slot = blockIdx.x;
+  if (!slots[slot].active) return;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < g.nblk_x; i += 256) {
+    const double v = maxpart[(long long)slot * g.nblk_x + i];
+    mx = (v > mx || v != v) ? v : mx;
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double a = red[threadIdx.x], b = red[threadIdx.x + o];
+      red[threadIdx.x] = (b > a || b != b) ? b : a;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    DynDev& d = dyn[slot];
+    const double m = red[0];
+    const double dx = 6.283185307179586476925286766559 / g.N;
+    double dt = dt_arg;
+    int fl = d.flags;
+    if (!(m == m) || m > 1.79769313486231570e308) fl |= PSDNS_FLAG_NONFINITE;
+    if (dt_arg < 0.0) dt = (m > 0.0 && m == m) ? (-dt_arg) * dx / m : 0.0;
+    if (dt * m / dx > 1.0) fl |= PSDNS_FLAG_CFL;
+    d.dt = dt;
+    d.max_u = m;
+    d.t += dt;
+    d.steps += 1;
+    d.flags = fl;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// initial condition (Sec. 2.3, Rogallo construction; SplitMix64 phases)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counter) {
+  uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__device__ __forceinline__ double unit_double(uint64_t x) { return double(x >> 11) * (1.0 / 9007199254740992.0); }
+
+// Coefficient vector of the canonical mode (kx, ky, kz) before the energy scaling.
+static __device__ void rogallo_mode(int kx, int ky, int kz, int N, uint64_t seed, double kp, double (&re)[3],
+                             double (&im)[3]) {
+  const double fx = kx, fy = ky, fz = kz;
+  const double k2 = fx * fx + fy * fy + fz * fz;
+  const double kmag = sqrt(k2);
+  const double q = kmag / kp;
+  const double spec = kmag * kmag * kmag * kmag * exp(-2.0 * q * q);
+  const double amp = sqrt(spec / (4.0 * 3.14159265358979323846 * kmag * kmag));
+  const double kperp = sqrt(fx * fx + fy * fy);
+  double e1[3], e2[3];
+  if (kperp == 0.0) {
+    e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0;
+  } else {
+    e1[0] = fy / kperp; e1[1] = -fx / kperp; e1[2] = 0.0;
+  }
+  e2[0] = (fy * e1[2] - fz * e1[1]) / kmag;
+  e2[1] = (fz * e1[0] - fx * e1[2]) / kmag;
+  e2[2] = (fx * e1[1] - fy * e1[0]) / kmag;
+  const int NX = N / 2 + 1;
+  const uint64_t iz = (uint64_t)((kz % N + N) % N), iy = (uint64_t)((ky % N + N) % N);
+  const uint64_t lin = (iz * (uint64_t)N + iy) * (uint64_t)NX + (uint64_t)kx;
+  const double two_pi = 6.283185307179586476925286766559;
+  const double th1 = two_pi * unit_double(splitmix64_at(seed, 3 * lin + 0));
+  const double th2 = two_pi * unit_double(splitmix64_at(seed, 3 * lin + 1));
+  const double psi = two_pi * unit_double(splitmix64_at(seed, 3 * lin + 2));
+  const double ca = cos(psi), sa = sin(psi);
+  const double ar = cos(th1) * ca, ai = sin(th1) * ca;
+  const double br = cos(th2) * sa, bi = sin(th2) * sa;
+  const double scale = double(N) * N * N * amp;
+  for (int c = 0; c < 3; ++c) {
+    re[c] = scale * (ar * e1[c] + br * e2[c]);
+    im[c] = scale * (ai * e1[c] + bi * e2[c]);
+  }
+}
+
+// coefficient of any retained mode (mirror modes of the kx = 0 plane by conjugation)
+static __device__ void init_coeff(int kx, int ky, int kz, int N, uint64_t seed, double kp, double (&re)[3],
+                           double (&im)[3]) {
+  if (kx == 0 && ky == 0 && kz == 0) {
+    for (int c = 0; c < 3; ++c) re[c] = im[c] = 0.0;
+    return;
+  }
+  const bool canon = kx > 0 || (kx == 0 && ky > 0) || (kx == 0 && ky == 0 && kz > 0);
+  if (canon) {
+    rogallo_mode(kx, ky, kz, N, seed, kp, re, im);
+  } else {
+    rogallo_mode(0, -ky, -kz, N, seed, kp, re, im);
+    for (int c = 0; c < 3; ++c) im[c] = -im[c];
+  }
+}
+
+static __global__ void __launch_bounds__(256)
+k_init_energy(Geom g, uint64_t seed, double kp, double* __restrict__ part) {
+  __shared__ double red[256];
+  const long long nmodes = (long long)g.M * g.M * g.KX;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  double e = 0.0;
+  if (i < nmodes) {
+    const int kx = (int)(i % g.KX);
+    const int kyc = (int)((i / g.KX) % g.M);
+    const int kzc = (int)(i / ((long long)g.KX * g.M));
+    double re[3], im[3];
+    init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, re, im);
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) s += re[c] * re[c] + im[c] * im[c];
+    e = (kx == 0 ? 0.5 : 1.0) * s;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+static __global__ void __launch_bounds__(256)
+k_init_scale(const double* __restrict__ part, int nblocks, double energy, int N, DynDev* __restrict__ d) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double n3 = double(N) * N * N;
+    const double k = red[0] / (n3 * n3);
+    d->scratch = k > 0.0 ? sqrt(energy / k) : 0.0;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_init_write(cpx<T>* __restrict__ st, Geom g, int slot, uint64_t seed, double kp, const DynDev* __restrict__ d) {
+  const long long nmodes = (long long)g.M * g.M * g.KX;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nmodes) return;
+  const int kx = (int)(i % g.KX);
+  const int kyc = (int)((i / g.KX) % g.M);
+  const int kzc = (int)(i / ((long long)g.KX * g.M));
+  double re[3], im[3];
+  init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, re, im);
+  const double sc = d->scratch;
+  const long long o = ((long long)kzc * g.M + kyc) * g.PX + kx;
+  cpx<T>* base = st + (long long)slot * g.F * g.st_field;
+  for (int c = 0; c < 3; ++c) base[o + c * g.st_field] = {T(sc * re[c]), T(sc * im[c])};
+  for (int s = 0; s < g.S; ++s) base[o + (3 + s) * g.st_field] = czero<T>();
+}
+
+// ---------------------------------------------------------------------------
+// canonical <-> compact conversion of one slot
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill_zero(cpx<T>* __restrict__ p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = czero<T>();
+}
+
+template <typename T, bool TO_CANON>
+__global__ void __launch_bounds__(256)
+k_convert(cpx<T>* __restrict__ st, cpx<T>* __restrict__ canon, Geom g, int slot) {
+  const long long per = (long long)g.M * g.M * g.KX;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= per * g.F) return;
+  const int f = (int)(i / per);
+  const long long r = i % per;
+  const int kx = (int)(r % g.KX);
+  const int kyc = (int)((r / g.KX) % g.M);
+  const int kzc = (int)(r / ((long long)g.KX * g.M));
+  const int N = g.N, NX = N / 2 + 1;
+  const int iy = (wave_of_compact(kyc, g.K, g.M) + N) % N;
+  const int iz = (wave_of_compact(kzc, g.K, g.M) + N) % N;
+  const long long oc = (((long long)f * N + iz) * N + iy) * NX + kx;
+  const long long os = (long long)slot * g.F * g.st_field + (long long)f * g.st_field +
+                       ((long long)kzc * g.M + kyc) * g.PX + kx;
+  if (TO_CANON)
+    canon[oc] = st[os];
+  else
+    st[os] = canon[oc];
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+struct TimedLaunch {
+  Timer* t;
+  int kid;
+  hipStream_t s;
+  TimedLaunch(Timer* t_, int k, hipStream_t s_) : t(t_), kid(k), s(s_) {
+    if (t) t->begin(kid, s);
+  }
+  ~TimedLaunch() {
+    if (t) t->end(kid, s);
+  }
+};
+
+template <int N, typename T>
+struct Engine {
+  using C = Cfg<N, T>;
+
+  static void rhs_stage(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
+                        double dt_arg, hipStream_t s) {
+    const Geom& g = x.g;
+    const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
+    const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
+    cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
+    cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
+    const int ntile = (g.KX + C::W - 1) / C::W;
+    {
+      TimedLaunch tl(x.timer, KID_FORCE, s);
+      k_forcing_amplitude<T><<<g.batch, 256, 0, s>>>(sin, x.slots, x.dyn, g);
+    }
+    {
+      TimedLaunch tl(x.timer, KID_ZINV, s);
+      k_z_inverse<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(sin, A, tw, x.slots, g);
+    }
+    {
+      TimedLaunch tl(x.timer, KID_YINV, s);
+      k_y_inverse<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, x.slots, g);
+    }
+    {
+      TimedLaunch tl(x.timer, KID_XPASS, s);
+      k_x_pass<N, T><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, g, want_max);
+    }
+    if (stage == 0) {
+      TimedLaunch tl(x.timer, KID_DT, s);
+      k_step_dt<<<g.batch, 256, 0, s>>>(x.part, x.slots, x.dyn, g, dt_arg);
+    }
+    {
+      TimedLaunch tl(x.timer, KID_YFWD, s);
+      k_y_forward<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(B, A, tw, x.slots, g);
+    }
+    StageArgs<T> sa;
+    sa.yn = static_cast<cpx<T>*>(state);
+    sa.acc = static_cast<cpx<T>*>(x.acc);
+    sa.ys = static_cast<cpx<T>*>(x.ystage);
+    sa.sin = sin;
+    sa.rhs = static_cast<cpx<T>*>(rhs_out);
+    sa.stage = stage;
+    {
+      TimedLaunch tl(x.timer, KID_ZFWD, s);
+      k_z_forward_update<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+    }
+  }
+
+  static void init_field(const Ctx& x, void* state, int slot, uint64_t seed, double kp, double energy,
+                         hipStream_t s) {
+    const Geom& g = x.g;
+    const long long nmodes = (long long)g.M * g.M * g.KX;
+    const int nb = (int)((nmodes + 255) / 256);
+    TimedLaunch tl(x.timer, KID_AUX, s);
+    k_init_energy<<<nb, 256, 0, s>>>(g, seed, kp, x.part);
+    k_init_scale<<<1, 256, 0, s>>>(x.part, nb, energy, g.N, x.dyn + slot);
+    k_init_write<T><<<nb, 256, 0, s>>>(static_cast<cpx<T>*>(state), g, slot, seed, kp, x.dyn + slot);
+  }
+
+  static void get_state(const Ctx& x, const void* state, int slot, void* canon, hipStream_t s) {
+    const Geom& g = x.g;
+    const long long ncan = (long long)g.F * N * N * (N / 2 + 1);
+    TimedLaunch tl(x.timer, KID_AUX, s);
+    k_fill_zero<T><<<(unsigned)((ncan + 255) / 256), 256, 0, s>>>(static_cast<cpx<T>*>(canon), ncan);
+    const long long n = (long long)g.F * g.M * g.M * g.KX;
+    k_convert<T, true><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+        const_cast<cpx<T>*>(static_cast<const cpx<T>*>(state)), static_cast<cpx<T>*>(canon), g, slot);
+  }
+
+  static void set_state(const Ctx& x, void* state, int slot, const void* canon, hipStream_t s) {
+    const Geom& g = x.g;
+    const long long n = (long long)g.F * g.M * g.M * g.KX;
+    TimedLaunch tl(x.timer, KID_AUX, s);
+    k_convert<T, false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
+        static_cast<cpx<T>*>(state), const_cast<cpx<T>*>(static_cast<const cpx<T>*>(canon)), g, slot);
+  }
+
+  static Ops ops() {
+    Ops o;
+    o.ec = C::EC;
+    o.ex = C::EX;
+    o.rhs_stage = &rhs_stage;
+    o.init_field = &init_field;
+    o.get_state = &get_state;
+    o.set_state = &set_state;
+    return o;
+  }
+};
+
+}  // namespace psdns

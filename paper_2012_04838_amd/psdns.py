@@ -1,0 +1,237 @@
+"""Thin ctypes binding of libpsdns.so (the C ABI in include/psdns.h).
+
+Only argument marshalling lives here: every step of the computation runs in
+the HIP kernels of the library.  PyTorch supplies device memory (tensors) and
+the HIP stream of the current device.  If the library is not built, importing
+fails loudly; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpsdns.so")
+MAX_SCALARS = 4
+
+FLAG_NONFINITE = 1
+FLAG_CFL = 2
+
+_c_int32 = ctypes.c_int32
+_c_void_p = ctypes.c_void_p
+
+
+class PlanParams(ctypes.Structure):
+    _fields_ = [("n", _c_int32), ("n_scalars", _c_int32), ("precision", _c_int32), ("batch", _c_int32)]
+
+
+class SlotParams(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_double), ("power", ctypes.c_double), ("k_force", ctypes.c_double),
+                ("schmidt", ctypes.c_double * MAX_SCALARS),
+                ("mean_grad", (ctypes.c_double * 3) * MAX_SCALARS)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("max_u", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("flags", _c_int32), ("active", _c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [(name, _c_int32) for name in ("n", "k_max", "m", "kx_count", "kx_pitch", "n_scalars",
+                                             "precision", "batch", "n_shells", "spectra_doubles")] + \
+               [("state_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
+                ("elems_col", _c_int32), ("elems_x", _c_int32)]
+
+
+class KernelTiming(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", _c_int32), ("total_ms", ctypes.c_double)]
+
+
+class PsdnsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+_SIGS = {
+    "psdns_state_bytes": (ctypes.c_size_t, [ctypes.POINTER(PlanParams)]),
+    "psdns_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PlanParams)]),
+    "psdns_plan_create": (ctypes.c_int, [ctypes.POINTER(PlanParams), ctypes.POINTER(_c_void_p)]),
+    "psdns_plan_destroy": (ctypes.c_int, [_c_void_p]),
+    "psdns_plan_get_info": (ctypes.c_int, [_c_void_p, ctypes.POINTER(PlanInfo)]),
+    "psdns_set_slot": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(SlotParams), _c_int32]),
+    "psdns_init_field": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.c_uint64,
+                                        ctypes.c_double, ctypes.c_double, _c_void_p]),
+    "psdns_rhs": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "psdns_step": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, ctypes.c_double, _c_int32, _c_void_p]),
+    "psdns_read_step_info": (ctypes.c_int, [_c_void_p, _c_void_p, ctypes.POINTER(StepInfo), _c_void_p]),
+    "psdns_clear_step_info": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "psdns_get_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
+    "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
+    "psdns_set_timing": (ctypes.c_int, [_c_void_p, _c_int32]),
+    "psdns_get_timing": (ctypes.c_int, [_c_void_p, ctypes.POINTER(KernelTiming), _c_int32,
+                                        ctypes.POINTER(_c_int32)]),
+    "psdns_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load libpsdns.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run `python -m paper_2012_04838_amd.build` first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        msg = lib().psdns_last_error().decode(errors="replace")
+        raise PsdnsError(f"psdns error {status}: {msg}")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def plan_params(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> PlanParams:
+    return PlanParams(n, n_scalars, precision, batch)
+
+
+def state_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> int:
+    p = plan_params(n, n_scalars, precision, batch)
+    return int(lib().psdns_state_bytes(ctypes.byref(p)))
+
+
+def workspace_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> int:
+    p = plan_params(n, n_scalars, precision, batch)
+    return int(lib().psdns_workspace_bytes(ctypes.byref(p)))
+
+
+class Plan:
+    """A plan for N^3 grids with S scalars, a precision (32/64) and `batch` slots.
+
+    Device buffers are torch tensors the caller keeps alive: `new_state()` and
+    `new_workspace()` allocate them with the sizes the library reports.
+    """
+
+    def __init__(self, n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1):
+        self.n, self.n_scalars, self.precision, self.batch = n, n_scalars, precision, batch
+        self._p = plan_params(n, n_scalars, precision, batch)
+        h = ctypes.c_void_p()
+        _check(lib().psdns_plan_create(ctypes.byref(self._p), ctypes.byref(h)))
+        self._h = h
+        info = PlanInfo()
+        _check(lib().psdns_plan_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            lib().psdns_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- buffers
+    @property
+    def n_fields(self) -> int:
+        return 3 + self.n_scalars
+
+    @property
+    def complex_dtype(self):
+        torch = _torch()
+        return torch.complex64 if self.precision == 32 else torch.complex128
+
+    def new_state(self):
+        torch = _torch()
+        return torch.zeros(int(self.info.state_bytes), dtype=torch.uint8, device="cuda")
+
+    def new_workspace(self):
+        torch = _torch()
+        return torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")
+
+    def canonical_shape(self):
+        n = self.n
+        return (self.n_fields, n, n, n // 2 + 1)
+
+    # ---------------------------------------------------------------- calls
+    def set_slot(self, slot: int, nu: float, power: float = 0.0, k_force: float = 2.0,
+                 schmidt: Sequence[float] = (), mean_grad: Sequence[Sequence[float]] = (),
+                 active: bool = True) -> None:
+        sp = SlotParams()
+        sp.nu, sp.power, sp.k_force = nu, power, k_force
+        for i in range(MAX_SCALARS):
+            sp.schmidt[i] = schmidt[i] if i < len(schmidt) else 1.0
+            g = mean_grad[i] if i < len(mean_grad) else (0.0, 0.0, 0.0)
+            for d in range(3):
+                sp.mean_grad[i][d] = g[d]
+        _check(lib().psdns_set_slot(self._h, slot, ctypes.byref(sp), 1 if active else 0))
+
+    def init_field(self, state, ws, slot: int, seed: int, k_peak: float, kinetic_energy: float = 1.0) -> None:
+        _check(lib().psdns_init_field(self._h, _ptr(state), _ptr(ws), slot, seed, k_peak, kinetic_energy,
+                                      _stream()))
+
+    def rhs(self, state, out, ws) -> None:
+        _check(lib().psdns_rhs(self._h, _ptr(state), _ptr(out), _ptr(ws), _stream()))
+
+    def step(self, state, ws, dt: float, nsteps: int = 1) -> None:
+        """dt > 0: fixed step; dt < 0: CFL target -dt (Eq. (10))."""
+        _check(lib().psdns_step(self._h, _ptr(state), _ptr(ws), dt, nsteps, _stream()))
+
+    def read_step_info(self, ws):
+        arr = (StepInfo * self.batch)()
+        _check(lib().psdns_read_step_info(self._h, _ptr(ws), arr, _stream()))
+        return [dict(t=a.t, dt=a.dt, max_u=a.max_u, steps=a.steps, flags=a.flags, active=a.active) for a in arr]
+
+    def clear_step_info(self, ws) -> None:
+        _check(lib().psdns_clear_step_info(self._h, _ptr(ws), _stream()))
+
+    def get_state(self, state, slot: int = 0):
+        """Canonical [field][kz][ky][kx] complex tensor (device) of one slot."""
+        torch = _torch()
+        out = torch.empty(self.canonical_shape(), dtype=self.complex_dtype, device="cuda")
+        _check(lib().psdns_get_state(self._h, _ptr(state), slot, _ptr(out), _stream()))
+        return out
+
+    def set_state(self, state, canonical, slot: int = 0) -> None:
+        torch = _torch()
+        c = canonical
+        if not isinstance(c, torch.Tensor):
+            c = torch.from_numpy(np.ascontiguousarray(c))
+        c = c.to(device="cuda", dtype=self.complex_dtype).contiguous()
+        if tuple(c.shape) != self.canonical_shape():
+            raise ValueError(f"canonical shape {tuple(c.shape)} != {self.canonical_shape()}")
+        _check(lib().psdns_set_state(self._h, _ptr(state), slot, _ptr(c), _stream()))
+        torch.cuda.current_stream().synchronize()  # keep c alive until the copy ran
+
+    def set_timing(self, enable: bool) -> None:
+        _check(lib().psdns_set_timing(self._h, 1 if enable else 0))
+
+    def get_timing(self):
+        arr = (KernelTiming * 16)()
+        cnt = _c_int32()
+        _check(lib().psdns_get_timing(self._h, arr, 16, ctypes.byref(cnt)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}

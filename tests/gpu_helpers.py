@@ -1,0 +1,51 @@
+"""Helpers shared by the GPU tests: run the library on canonical numpy states."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as ora
+
+
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    return torch
+
+
+def make_plan(N, S, prec, batch=1):
+    from paper_2012_04838_amd import psdns
+    return psdns.Plan(N, S, prec, batch)
+
+
+def set_params(plan, slot, prm: "ora.Params", active=True):
+    plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing else 0.0), k_force=prm.k_force,
+                  schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad], active=active)
+
+
+def to_numpy(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def gpu_rhs(state_np, prm, prec=64):
+    torch = torch_mod()
+    N = state_np.shape[-3]
+    S = state_np.shape[0] - 3
+    plan = make_plan(N, S, prec)
+    set_params(plan, 0, prm)
+    st = plan.new_state()
+    ws = plan.new_workspace()
+    out = plan.new_state()
+    plan.set_state(st, state_np, 0)
+    plan.rhs(st, out, ws)
+    res = to_numpy(plan.get_state(out, 0))
+    torch.cuda.synchronize()
+    return res
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+def retained(x):
+    N = x.shape[-3]
+    return np.where(ora.retained_mask(N), x, 0.0)
