@@ -22,16 +22,42 @@
 
 namespace psdns {
 
+// Tuning knobs (elements per thread, minimum waves per SIMD for the register
+// allocator; 0 leaves the allocator free).
+#ifndef PSDNS_EC32
+#define PSDNS_EC32 16
+#endif
+#ifndef PSDNS_EC64
+#define PSDNS_EC64 8
+#endif
+#ifndef PSDNS_COL_WAVES
+#define PSDNS_COL_WAVES 0
+#endif
+#ifndef PSDNS_X_WAVES
+#define PSDNS_X_WAVES 0
+#endif
+#if PSDNS_COL_WAVES > 0
+#define PSDNS_COL_BOUNDS(...) __launch_bounds__((__VA_ARGS__), PSDNS_COL_WAVES)
+#else
+#define PSDNS_COL_BOUNDS(...) __launch_bounds__((__VA_ARGS__))
+#endif
+#if PSDNS_X_WAVES > 0
+#define PSDNS_X_BOUNDS(...) __launch_bounds__((__VA_ARGS__), PSDNS_X_WAVES)
+#else
+#define PSDNS_X_BOUNDS(...) __launch_bounds__((__VA_ARGS__))
+#endif
+
 template <int N, typename T>
 struct Cfg {
   // columns per block: one 128-byte row of complex values
   static constexpr int W = 128 / (int)sizeof(cpx<T>);
   // elements per thread of the column passes (z, y) and of the x pass
-  static constexpr int EC0 = sizeof(T) == 4 ? 16 : 8;
+  static constexpr int EC0 = sizeof(T) == 4 ? PSDNS_EC32 : PSDNS_EC64;
   static constexpr int EC = N < EC0 ? N : EC0;
   static constexpr int TC = N / EC;
   static constexpr int COL_THREADS = W * TC;
-  static constexpr int EX0 = 8;
+  // x pass: a line never spans two wavefronts (TX <= 64)
+  static constexpr int EX0 = N > 512 ? N / 64 : 8;
   static constexpr int EX = N < EX0 ? N : EX0;
   static constexpr int TX = N / EX;
   static constexpr int LX0 = 256 / TX;
@@ -58,14 +84,17 @@ __device__ __forceinline__ cpx<T> czero() { return {T(0), T(0)}; }
 // (all carry the 1/N^3 of Eq. (5) so that physical values are the true ones).
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
-k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw,
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   __shared__ cpx<T> smem[W * N];
+  __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   if (!slots[slot].active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
   const int kx = blockIdx.x * W + c;
@@ -135,14 +164,17 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
 //           6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s   (x still spectral)
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
-k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw,
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   __shared__ cpx<T> smem[W * N];
+  __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   if (!slots[slot].active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
   const int kx = blockIdx.x * W + c;
@@ -212,58 +244,121 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
 }
 
 // ---------------------------------------------------------------------------
-// x pass: one (z, y) line per TX threads.  Two real fields f, g travel as one
-// complex line h = f + i g through an N-point complex transform.
+// x pass: one (z, y) line per TX lanes; a line never leaves its wavefront, so
+// the exchanges inside a line only need wave-level ordering.  Two real fields
+// f, g travel as one complex line h = f + i g through an N-point complex
+// transform.  Lane j loads the unique half-spectrum entries kx = j + TX q of a
+// line once; the conjugate-mirrored entries it needs (negative kx) come from
+// the partner lane (kx = TX - j mod TX) by a cross-lane permute, and the
+// forward post-processing pairs Z[k] with Z[N-k] the same way.
 // Output (in place, first F fields of B): 0 c1, 1 c2, 2 c3 with c = u x omega,
-// 3+s a_s = u.grad phi_s + g_s.u, all forward transformed along x, kx <= K.
+// 3+s a_s = u.grad phi_s + g_s.u, forward transformed along x, kx <= K.
 // ---------------------------------------------------------------------------
+template <int B_, int E_, class Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (B_ < E_) {
+    fn(std::integral_constant<int, B_>{});
+    static_for<B_ + 1, E_>(fn);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
+  return {__shfl(v.x, src), __shfl(v.y, src)};
+}
+
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::X_THREADS))
-k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots,
+__global__ void PSDNS_X_BOUNDS(Cfg<N, T>::X_THREADS)
+k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
          double* __restrict__ maxpart, Geom g, int want_max) {
   using C = Cfg<N, T>;
   constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
+  constexpr int K = (N - 1) / 3;
+  constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
+  static_assert(TT <= 64 && 64 % TT == 0, "a line must stay inside one wavefront");
+  static_assert(NQ < E, "retained band must be shorter than the line");
   __shared__ cpx<T> smem[L * LP];
+  __shared__ cpx<T> stw[N];
   __shared__ double red[C::X_THREADS];
   const int slot = blockIdx.y;
   if (!slots[slot].active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
   const int li = threadIdx.x / TT;
   const int j = threadIdx.x % TT;
+  const int lane = threadIdx.x & 63;
+  const int partner = (lane - j) + ((TT - j) & (TT - 1));
   const long long line = (long long)blockIdx.x * L + li;  // z * N + y
   const LdsLine<T> lds{smem + li * LP};
   cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
-  const int K = g.K;
 
-  int kap[E];     // |kx| of position n, or -1 if truncated
-  bool neg[E];    // position holds a negative kx (value is the conjugate)
+  // r[q] = entry kx = j + TT q of field f (zero beyond K); at kx = 0 only the real
+  // part is kept, as a complex-to-real transform does.
+  auto load = [&](int f, cpx<T> (&r)[NQ]) {
+    const cpx<T>* p = base + (long long)f * g.b_field;
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int n = j + TT * m;
-    kap[m] = n <= K ? n : (n >= N - K ? N - n : -1);
-    neg[m] = n > K;
-  }
-  auto hv = [&](int f, int m) -> cpx<T> {
-    return kap[m] >= 0 ? base[(long long)f * g.b_field + kap[m]] : czero<T>();
+    for (int q = 0; q < NQ; ++q) {
+      const int kx = j + TT * q;
+      r[q] = kx <= K ? p[kx] : czero<T>();
+    }
+    if (j == 0) r[0].y = T(0);
   };
-  // full-spectrum value at position m from the half-spectrum value v at |kx|
-  auto full = [&](cpx<T> v, int m) -> cpx<T> {
-    if (kap[m] == 0) return {v.x, T(0)};
-    return neg[m] ? conj(v) : v;
+  // h at positions n = j + TT m from the half-spectrum entries of f (va) and g (vb):
+  // n <= K: va + i vb;  n >= N - K: conj(va) + i conj(vb) of kx = N - n;  else 0
+  auto build = [&](const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) {
+    static_for<0, E>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      const int n = j + TT * m;
+      cpx<T> a = czero<T>(), b = czero<T>();
+      if constexpr (TT * m <= K) {
+        if (n <= K) {
+          a = va[m];
+          b = vb[m];
+        }
+      }
+      if constexpr (TT * m + TT - 1 >= N - K) {
+        constexpr int q1 = E - m - 1;  // slot of kx = N - n at the partner lane (j != 0)
+        constexpr int q0 = E - m;      // own slot when j == 0
+        cpx<T> pa = czero<T>(), pb = czero<T>();
+        if constexpr (q1 < NQ) {
+          pa = shfl_c(va[q1], partner);
+          pb = shfl_c(vb[q1], partner);
+        }
+        if (j == 0) {
+          if constexpr (q0 < NQ) {
+            pa = va[q0];
+            pb = vb[q0];
+          } else {
+            pa = czero<T>();
+            pb = czero<T>();
+          }
+        }
+        if (n >= N - K) {
+          a = conj(pa);
+          b = conj(pb);
+        }
+      }
+      h[m] = a + mul_i(b);
+    });
   };
-  auto pack = [&](cpx<T> f, cpx<T> gg) -> cpx<T> { return f + mul_i(gg); };
+  auto kxq = [&](int q) { return T(j + TT * q); };
 
-  cpx<T> h[E], r2[E], r3[E];
+  cpx<T> r0[NQ], r1[NQ], r2[NQ], r3[NQ], r4[NQ], r5[NQ];
+  load(1, r1);
+  load(2, r2);
+  load(4, r4);
+  load(5, r5);
+  load(3, r3);
+  load(0, r0);
+  cpx<T> h[E], va[NQ], vb[NQ];
   // omega2 = dz u1 - dx u3, omega3 = dx u2 - dy u1
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    r2[m] = hv(1, m);
-    r3[m] = hv(2, m);
-    const T kk = T(kap[m]);
-    const cpx<T> w2 = hv(4, m) - mul_is(r3[m], kk);
-    const cpx<T> w3 = mul_is(r2[m], kk) - hv(5, m);
-    h[m] = pack(full(w2, m), full(w3, m));
+  for (int q = 0; q < NQ; ++q) {
+    va[q] = r4[q] - mul_is(r2[q], kxq(q));
+    vb[q] = mul_is(r1[q], kxq(q)) - r5[q];
   }
-  fft<N, E, true>(h, lds, j, tw);
+  build(va, vb, h);
+  fft<N, E, true, WaveSync>(h, lds, j, tw);
   T w2p[E], w3p[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -271,9 +366,8 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     w3p[m] = h[m].y;
   }
   // u3, omega1
-#pragma unroll
-  for (int m = 0; m < E; ++m) h[m] = pack(full(r3[m], m), full(hv(3, m), m));
-  fft<N, E, true>(h, lds, j, tw);
+  build(r2, r3, h);
+  fft<N, E, true, WaveSync>(h, lds, j, tw);
   T u3p[E], w1p[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -281,9 +375,21 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     w1p[m] = h[m].y;
   }
   // u1, u2
-#pragma unroll
-  for (int m = 0; m < E; ++m) h[m] = pack(full(hv(0, m), m), full(r2[m], m));
-  fft<N, E, true>(h, lds, j, tw);
+  build(r0, r1, h);
+  const int S = g.S;
+  // first scalar pair's entries go in flight before the next transforms
+  cpx<T> s0[NQ], s1[NQ], s2[NQ], s3[NQ], s4[NQ], s5[NQ];
+  if (S > 0) {
+    load(6, s0);
+    load(7, s1);
+    load(8, s2);
+  }
+  if (S > 1) {
+    load(9, s3);
+    load(10, s4);
+    load(11, s5);
+  }
+  fft<N, E, true, WaveSync>(h, lds, j, tw);
   T u1p[E], u2p[E], c1[E], c2[E], c3[E];
   double mx = 0.0;
 #pragma unroll
@@ -293,96 +399,96 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     c1[m] = u2p[m] * w3p[m] - u3p[m] * w2p[m];
     c2[m] = u3p[m] * w1p[m] - u1p[m] * w3p[m];
     c3[m] = u1p[m] * w2p[m] - u2p[m] * w1p[m];
-    const double s = fabs((double)u1p[m]) + fabs((double)u2p[m]) + fabs((double)u3p[m]);
-    mx = (s > mx || s != s) ? s : mx;  // keeps NaN
+    const double sm = fabs((double)u1p[m]) + fabs((double)u2p[m]) + fabs((double)u3p[m]);
+    mx = (sm > mx || sm != sm) ? sm : mx;  // keeps NaN
   }
 
-  // forward transform of the real pair (p, q) and store of fields fp, fq (kx <= K)
+  // forward transform of the real pair (p, q); store fields fp, fq at kx <= K
   auto forward_pair = [&](const T (&p)[E], const T (&q)[E], int fp, int fq) {
 #pragma unroll
     for (int m = 0; m < E; ++m) h[m] = {p[m], q[m]};
-    fft<N, E, false>(h, lds, j, tw);
-#pragma unroll
-    for (int m = 0; m < E; ++m) lds.st(j + TT * m, h[m]);
-    __syncthreads();
-    for (int k = j; k <= K; k += TT) {
-      const cpx<T> zk = lds.ld(k);
-      const cpx<T> zm = conj(lds.ld((N - k) & (N - 1)));
-      const cpx<T> P = T(0.5) * (zk + zm);
-      const cpx<T> Q = mul_mi(T(0.5) * (zk - zm));
-      base[(long long)fp * g.b_field + k] = P;
-      if (fq >= 0) base[(long long)fq * g.b_field + k] = Q;
-    }
-    __syncthreads();
+    fft<N, E, false, WaveSync>(h, lds, j, tw);
+    static_for<0, NQ>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      cpx<T> zm = shfl_c(h[E - s - 1], partner);
+      if (j == 0) zm = h[(E - s) % E];
+      const cpx<T> zk = h[s];
+      const cpx<T> zc = conj(zm);
+      const int kx = j + TT * s;
+      if (kx <= K) {
+        base[(long long)fp * g.b_field + kx] = T(0.5) * (zk + zc);
+        if (fq >= 0) base[(long long)fq * g.b_field + kx] = mul_mi(T(0.5) * (zk - zc));
+      }
+    });
   };
-
-  const SlotDev& sp = slots[slot];
-  const int S = g.S;
-  // scalars: a_s = u.grad phi_s + g_s.u
-  T as0[E], as1[E];
-  auto scalar_xy = [&](int s, T (&acc)[E]) {
-    const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
+  T zero[E];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const cpx<T> phi = hv(6 + 3 * s, m);
-      const cpx<T> d1 = mul_is(phi, T(kap[m]));
-      h[m] = pack(full(d1, m), full(hv(7 + 3 * s, m), m));
-    }
-    fft<N, E, true>(h, lds, j, tw);
-#pragma unroll
-    for (int m = 0; m < E; ++m)
-      acc[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
-  };
-  auto scalar_z = [&](int s0, int s1, T (&acc0)[E], T (&acc1)[E]) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const cpx<T> b = s1 >= 0 ? full(hv(8 + 3 * s1, m), m) : czero<T>();
-      h[m] = pack(full(hv(8 + 3 * s0, m), m), b);
-    }
-    fft<N, E, true>(h, lds, j, tw);
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      acc0[m] += u3p[m] * h[m].x;
-      if (s1 >= 0) acc1[m] += u3p[m] * h[m].y;
-    }
-  };
+  for (int m = 0; m < E; ++m) zero[m] = T(0);
 
   forward_pair(c1, c2, 0, 1);
   if (S == 0) {
-    T zero[E];
-#pragma unroll
-    for (int m = 0; m < E; ++m) zero[m] = T(0);
     forward_pair(c3, zero, 2, -1);
   } else {
-    // scalars in pairs (s, s+1); the first output pair is (c3, a_0)
+    const SlotDev& sp = slots[slot];
+    T as0[E], as1[E];
+    // scalars in pairs (s, s+1): a_s = u.grad phi_s + g_s.u
     for (int s = 0; s < S; s += 2) {
       const bool two = s + 1 < S;
-      scalar_xy(s, as0);
-      if (two) scalar_xy(s + 1, as1);
-      scalar_z(s, two ? s + 1 : -1, as0, as1);
+      if (s > 0) {
+        load(6 + 3 * s, s0);
+        load(7 + 3 * s, s1);
+        load(8 + 3 * s, s2);
+        if (two) {
+          load(9 + 3 * s, s3);
+          load(10 + 3 * s, s4);
+          load(11 + 3 * s, s5);
+        }
+      }
+      {
+        const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) va[q] = mul_is(s0[q], kxq(q));
+        build(va, s1, h);
+        fft<N, E, true, WaveSync>(h, lds, j, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+          as0[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
+      }
+      if (two) {
+        const T g0 = T(sp.g[s + 1][0]), g1 = T(sp.g[s + 1][1]), g2 = T(sp.g[s + 1][2]);
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) va[q] = mul_is(s3[q], kxq(q));
+        build(va, s4, h);
+        fft<N, E, true, WaveSync>(h, lds, j, tw);
+#pragma unroll
+        for (int m = 0; m < E; ++m)
+          as1[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
+      }
+      // z-derivatives of both scalars share one transform
+      if (!two) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) s5[q] = czero<T>();
+      }
+      build(s2, s5, h);
+      fft<N, E, true, WaveSync>(h, lds, j, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        as0[m] += u3p[m] * h[m].x;
+        as1[m] = two ? as1[m] + u3p[m] * h[m].y : as1[m];
+      }
       if (s == 0) {
         forward_pair(c3, as0, 2, 3);
         if (two) {
-          // a_1 waits for a partner (a_2) when S > 2, else it goes alone
           if (S > 2) {
 #pragma unroll
-            for (int m = 0; m < E; ++m) c3[m] = as1[m];  // c3 is free now: park a_1
+            for (int m = 0; m < E; ++m) c3[m] = as1[m];  // park a_1 until a_2 exists
           } else {
-            T zero[E];
-#pragma unroll
-            for (int m = 0; m < E; ++m) zero[m] = T(0);
             forward_pair(as1, zero, 4, -1);
           }
         }
       } else {
-        // s >= 2: parked a_{s-1} pairs with a_s; a_{s+1} (if any) goes with zero or is parked
         forward_pair(c3, as0, 3 + s - 1, 3 + s);
-        if (two) {
-          T zero[E];
-#pragma unroll
-          for (int m = 0; m < E; ++m) zero[m] = T(0);
-          forward_pair(as1, zero, 3 + s + 1, -1);
-        }
+        if (two) forward_pair(as1, zero, 3 + s + 1, -1);
       }
     }
   }
@@ -405,14 +511,17 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
 // y forward: columns along y at fixed (z, kx-tile); keeps |ky| <= K.
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
-k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw,
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   __shared__ cpx<T> smem[W * N];
+  __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   if (!slots[slot].active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
   const int kx = blockIdx.x * W + c;
@@ -489,15 +598,18 @@ __device__ __forceinline__ void rk_update(const StageArgs<T>& a, long long o, cp
 }
 
 template <int N, typename T>
-__global__ void __launch_bounds__((Cfg<N, T>::COL_THREADS))
-k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw,
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   __shared__ cpx<T> smem[W * N];
+  __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   const SlotDev& sp = slots[slot];
   if (!sp.active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
   const int kx = blockIdx.x * W + c;

@@ -145,9 +145,23 @@ struct LinePad {
   static constexpr int value = N + N / 16;
 };
 
+// Exchange synchronisation: the whole block (lines spread over several
+// wavefronts) or one wavefront (every line owned by lanes of a single wave;
+// LDS operations of a wave execute in order, so only compiler ordering is needed).
+struct BlockSync {
+  static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+struct WaveSync {
+  static __device__ __forceinline__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // One Stockham stage (and, recursively, the ones after it).
 // NS = product of the radices already applied.
-template <int N, int E, bool INV, int NS, typename T, class Lds>
+template <int N, int E, bool INV, int NS, class Sync, typename T, class Lds>
 __device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j,
                                           const cpx<T>* __restrict__ tw) {
   if constexpr (NS < N) {
@@ -181,20 +195,28 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j,
       }
     }
     if constexpr (!LAST) {
-      __syncthreads();
+      Sync::sync();
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = lds.ld(j + TT * m);
-      __syncthreads();
-      fft_stage<N, E, INV, NS * R>(v, lds, j, tw);
+      Sync::sync();
+      fft_stage<N, E, INV, NS * R, Sync>(v, lds, j, tw);
     }
   }
 }
 
-// Full N-point transform of the strided register line. Every thread of the
-// block must call it (it contains block barriers when N > E).
-template <int N, int E, bool INV, typename T, class Lds>
+// Full N-point transform of the strided register line.  With BlockSync every
+// thread of the block must call it; with WaveSync every lane of the wave.
+// tw points to w_N^m, m = 0..N-1 (normally a copy staged in LDS).
+template <int N, int E, bool INV, class Sync = BlockSync, typename T, class Lds>
 __device__ __forceinline__ void fft(cpx<T> (&v)[E], const Lds& lds, int j, const cpx<T>* __restrict__ tw) {
-  fft_stage<N, E, INV, 1>(v, lds, j, tw);
+  fft_stage<N, E, INV, 1, Sync>(v, lds, j, tw);
+}
+
+// Copy the N twiddles into LDS (block-wide; ends with a block barrier).
+template <int N, typename T>
+__device__ __forceinline__ void stage_twiddles(cpx<T>* dst, const cpx<T>* __restrict__ src) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
 }
 
 }  // namespace psdns

@@ -14,7 +14,7 @@ from typing import Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libpsdns.so")
+LIB_PATH = os.environ.get("PSDNS_LIB") or os.path.join(_PKG, "libpsdns.so")
 MAX_SCALARS = 4
 
 FLAG_NONFINITE = 1
