@@ -88,6 +88,30 @@ def run_gpu(n, s, prec, steps, warmup, seed=3):
     return {"ms_total": ms, "wall_s": wall, "timing": timing, "info": info, "finite": ok}
 
 
+def copy_reference(gbytes: float, reps: int = 5):
+    """Plain device-to-device copy of a known size: measured copy bandwidth, and the
+    reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    n = int(gbytes * 1e9) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = 2 * 4 * n
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(n, s):
     """One oracle right-hand-side evaluation at the benchmark size (a quarter of an RK4
     step; the integrating-factor update adds well under 5%), scaled to steps/s."""
@@ -113,6 +137,8 @@ def main():
     ap.add_argument("--scalars", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-gb", type=float, default=1.0,
+                    help="size of the copy-bandwidth reference (0 disables)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -125,6 +151,7 @@ def main():
         sys.exit(1)
     n, s = args.n, args.scalars
     n3 = float(n) ** 3
+    copy = copy_reference(args.copy_gb) if args.copy_gb > 0 else None
     r32 = run_gpu(n, s, 32, args.steps, args.warmup)
     print(f"[bench] fp32 done: {r32['ms_total'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     r64 = None
@@ -166,6 +193,7 @@ def main():
                           "achieved_GBs": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9,
                           "frac": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "kernels_fp32": per_kernel,
+        "copy_reference": copy,
         "finite": r32["finite"],
     }
     if r64 is not None:
@@ -174,6 +202,11 @@ def main():
                        "step_frac": step_bytes(n, s, 64) / (ms64 * 1e-3) / 1e9 / PEAK_HBM_GBS,
                        "finite": r64["finite"]}
         out["fp32_over_fp64"] = ms64 / ms32
+        kb64 = kernel_bytes(n, s, 64)
+        t64 = r64["timing"]
+        out["kernels_fp64"] = {k: {"launches": t64[k][0], "avg_ms": t64[k][1] / max(t64[k][0], 1),
+                                   "alg_GBs": (kb64[k] / (t64[k][1] / t64[k][0] * 1e-3) / 1e9)
+                                   if k in kb64 and t64[k][0] else None} for k in t64 if t64[k][0]}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, s)
     print(json.dumps(out), flush=True)

@@ -25,7 +25,7 @@ namespace psdns {
 // Tuning knobs (elements per thread, minimum waves per SIMD for the register
 // allocator; 0 leaves the allocator free).
 #ifndef PSDNS_EC32
-#define PSDNS_EC32 16
+#define PSDNS_EC32 8
 #endif
 #ifndef PSDNS_EC64
 #define PSDNS_EC64 8
@@ -106,19 +106,16 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   const cpx<T>* in = st + (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
   cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
 
-  int kc[E];
-  T kz[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int n = j + TT * m;
-    kc[m] = valid ? compact_of(n, N, g.K, g.M) : -1;
-    kz[m] = T(wave_of(n, N));
-  }
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
   cpx<T> a[E], d[E];
   auto load = [&](int f) {
     const cpx<T>* p = in + (long long)f * g.st_field;
 #pragma unroll
-    for (int m = 0; m < E; ++m) a[m] = kc[m] >= 0 ? scale * p[kc[m] * rows] : czero<T>();
+    for (int m = 0; m < E; ++m) {
+      const int kc = compact_of(j + TT * m, N, K, M);
+      a[m] = (valid && kc >= 0) ? scale * p[kc * rows] : czero<T>();
+    }
   };
   auto store = [&](int f, cpx<T> (&v)[E]) {
     if (!valid) return;
@@ -128,7 +125,7 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   };
   auto deriv = [&]() {
 #pragma unroll
-    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kz[m]);
+    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], T(wave_of(j + TT * m, N)));
   };
   // u1 and dz u1
   load(0);
@@ -184,19 +181,17 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)z * g.M * g.PX + kx;
   cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
 
-  int kc[E];
-  T ky[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int n = j + TT * m;
-    kc[m] = valid ? compact_of(n, N, g.K, g.M) : -1;
-    ky[m] = T(wave_of(n, N));
-  }
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  auto kyv = [&](int m) { return T(wave_of(j + TT * m, N)); };
   cpx<T> a[E], d[E];
   auto load = [&](int f, cpx<T> (&v)[E]) {
     const cpx<T>* p = in + (long long)f * g.a_field;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = kc[m] >= 0 ? p[kc[m] * g.PX] : czero<T>();
+    for (int m = 0; m < E; ++m) {
+      const int kc = compact_of(j + TT * m, N, K, M);
+      v[m] = (valid && kc >= 0) ? p[kc * g.PX] : czero<T>();
+    }
   };
   auto store = [&](int f, cpx<T> (&v)[E]) {
     if (!valid) return;
@@ -207,7 +202,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   // u1 and dy u1
   load(0, a);
 #pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], ky[m]);
+  for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m));
   fft<N, E, true>(a, lds, j, tw);
   store(0, a);
   fft<N, E, true>(d, lds, j, tw);
@@ -220,7 +215,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   load(2, a);
   load(4, d);
 #pragma unroll
-  for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], ky[m]) - d[m];
+  for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m)) - d[m];
   fft<N, E, true>(a, lds, j, tw);
   store(2, a);
   fft<N, E, true>(d, lds, j, tw);
@@ -232,7 +227,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   for (int s = 0; s < g.S; ++s) {
     load(5 + 2 * s, a);
 #pragma unroll
-    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], ky[m]);
+    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m));
     fft<N, E, true>(a, lds, j, tw);
     store(6 + 3 * s, a);
     fft<N, E, true>(d, lds, j, tw);
@@ -283,9 +278,17 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   const int slot = blockIdx.y;
   if (!slots[slot].active) return;
   stage_twiddles<N>(stw, tw_g);
-  const cpx<T>* tw = stw;
   const int li = threadIdx.x / TT;
   const int j = threadIdx.x % TT;
+  // FP32: the lane's twiddles live in registers for all nine transforms of the
+  // line; FP64 keeps them in LDS to leave registers for the line data.
+  constexpr bool kRegTw = sizeof(T) == 4;
+  using TwT = std::conditional_t<kRegTw, TwReg<N, E, T>, const cpx<T>*>;
+  TwT tw;
+  if constexpr (kRegTw)
+    tw = tw_fill<N, E>(j, stw);
+  else
+    tw = stw;
   const int lane = threadIdx.x & 63;
   const int partner = (lane - j) + ((TT - j) & (TT - 1));
   const long long line = (long long)blockIdx.x * L + li;  // z * N + y
@@ -379,19 +382,21 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   const int S = g.S;
   // first scalar pair's entries go in flight before the next transforms
   cpx<T> s0[NQ], s1[NQ], s2[NQ], s3[NQ], s4[NQ], s5[NQ];
-  if (S > 0) {
-    load(6, s0);
-    load(7, s1);
-    load(8, s2);
-  }
-  if (S > 1) {
-    load(9, s3);
-    load(10, s4);
-    load(11, s5);
-  }
+  auto load_scalar_pair = [&](int s) {
+    load(6 + 3 * s, s0);
+    load(7 + 3 * s, s1);
+    load(8 + 3 * s, s2);
+    if (s + 1 < S) {
+      load(9 + 3 * s, s3);
+      load(10 + 3 * s, s4);
+      load(11 + 3 * s, s5);
+    }
+  };
+  constexpr bool kPrefetchScalars = sizeof(T) == 4;
+  if (kPrefetchScalars && S > 0) load_scalar_pair(0);
   fft<N, E, true, WaveSync>(h, lds, j, tw);
   T u1p[E], u2p[E], c1[E], c2[E], c3[E];
-  double mx = 0.0;
+  T mx = T(0);
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     u1p[m] = h[m].x;
@@ -399,7 +404,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     c1[m] = u2p[m] * w3p[m] - u3p[m] * w2p[m];
     c2[m] = u3p[m] * w1p[m] - u1p[m] * w3p[m];
     c3[m] = u1p[m] * w2p[m] - u2p[m] * w1p[m];
-    const double sm = fabs((double)u1p[m]) + fabs((double)u2p[m]) + fabs((double)u3p[m]);
+    const T sm = fabs(u1p[m]) + fabs(u2p[m]) + fabs(u3p[m]);
     mx = (sm > mx || sm != sm) ? sm : mx;  // keeps NaN
   }
 
@@ -434,16 +439,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     // scalars in pairs (s, s+1): a_s = u.grad phi_s + g_s.u
     for (int s = 0; s < S; s += 2) {
       const bool two = s + 1 < S;
-      if (s > 0) {
-        load(6 + 3 * s, s0);
-        load(7 + 3 * s, s1);
-        load(8 + 3 * s, s2);
-        if (two) {
-          load(9 + 3 * s, s3);
-          load(10 + 3 * s, s4);
-          load(11 + 3 * s, s5);
-        }
-      }
+      if (s > 0 || !kPrefetchScalars) load_scalar_pair(s);
       {
         const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
 #pragma unroll
@@ -494,7 +490,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   }
 
   if (want_max) {
-    red[threadIdx.x] = mx;
+    red[threadIdx.x] = (double)mx;
     __syncthreads();
     for (int o = C::X_THREADS / 2; o > 0; o >>= 1) {
       if ((int)threadIdx.x < o) {
@@ -530,9 +526,8 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   const LdsCol<T, W> lds{smem + c};
   const cpx<T>* in = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
   cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)z * g.M * g.PX + kx;
-  int kc[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) kc[m] = valid ? compact_of(j + TT * m, N, g.K, g.M) : -1;
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
   cpx<T> a[E];
   for (int f = 0; f < g.F; ++f) {
     const cpx<T>* p = in + (long long)f * g.b_field;
@@ -541,8 +536,10 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
     fft<N, E, false>(a, lds, j, tw);
     cpx<T>* q = out + (long long)f * g.a_field;
 #pragma unroll
-    for (int m = 0; m < E; ++m)
-      if (kc[m] >= 0) q[kc[m] * g.PX] = a[m];
+    for (int m = 0; m < E; ++m) {
+      const int kc = compact_of(j + TT * m, N, K, M);
+      if (valid && kc >= 0) q[kc * g.PX] = a[m];
+    }
   }
 }
 
@@ -623,15 +620,14 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T
   const double h = dyn[slot].dt;
   const double A = dyn[slot].A;
 
-  int kc[E];
-  double k2[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int n = j + TT * m;
-    kc[m] = valid ? compact_of(n, N, g.K, g.M) : -1;
-    const int kz = wave_of(n, N);
-    k2[m] = double(kx) * kx + double(ky) * ky + double(kz) * kz;
-  }
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  const int kxy2 = kx * kx + ky * ky;
+  auto kcm = [&](int m) { return valid ? compact_of(j + TT * m, N, K, M) : -1; };
+  auto k2m = [&](int m) {
+    const int kz = wave_of(j + TT * m, N);
+    return double(kxy2 + kz * kz);
+  };
   auto load_fwd = [&](int f, cpx<T> (&v)[E]) {
     const cpx<T>* p = in + (long long)f * g.a_field;
 #pragma unroll
@@ -648,27 +644,29 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T
     const double nu = sp.nu;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if (kc[m] < 0) continue;
+      const int kcm_ = kcm(m);
+      if (kcm_ < 0) continue;
+      const double k2m_ = k2m(m);
       const int n = j + TT * m;
       const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
-      const long long o = sbase + (long long)kc[m] * rows;
+      const long long o = sbase + (long long)kcm_ * rows;
       cpx<T> F1, F2, F3;
-      if (k2[m] == 0.0) {
+      if (k2m_ == 0.0) {
         F1 = F2 = F3 = czero<T>();
       } else {
-        const T ik2 = T(1.0 / k2[m]);
+        const T ik2 = T(1.0 / k2m_);
         const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
         F1 = c1[m] - (kxt * ik2) * kdc;
         F2 = c2[m] - (kyt * ik2) * kdc;
         F3 = c3[m] - (kzt * ik2) * kdc;
-        if (A != 0.0 && k2[m] <= sp.kf2) {
+        if (A != 0.0 && k2m_ <= sp.kf2) {
           const T At = T(A);
           F1 = F1 + At * sa.sin[o];
           F2 = F2 + At * sa.sin[o + g.st_field];
           F3 = F3 + At * sa.sin[o + 2 * g.st_field];
         }
       }
-      const double lk2 = nu * k2[m];
+      const double lk2 = nu * k2m_;
       rk_update(sa, o, F1, lk2, h);
       rk_update(sa, o + g.st_field, F2, lk2, h);
       rk_update(sa, o + 2 * g.st_field, F3, lk2, h);
@@ -681,10 +679,12 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T
     const double dif = sp.diff[3 + s];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      if (kc[m] < 0) continue;
-      const long long o = sbase + (long long)(3 + s) * g.st_field + (long long)kc[m] * rows;
-      const cpx<T> F = k2[m] == 0.0 ? czero<T>() : czero<T>() - a[m];
-      rk_update(sa, o, F, dif * k2[m], h);
+      const int kcm_ = kcm(m);
+      if (kcm_ < 0) continue;
+      const double k2m_ = k2m(m);
+      const long long o = sbase + (long long)(3 + s) * g.st_field + (long long)kcm_ * rows;
+      const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
+      rk_update(sa, o, F, dif * k2m_, h);
     }
   }
 }

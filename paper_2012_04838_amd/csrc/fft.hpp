@@ -159,11 +159,67 @@ struct WaveSync {
   }
 };
 
+// Number of stage twiddles one thread applies (all stages after the first).
+template <int N, int E, int NS = 1>
+__host__ __device__ constexpr int tw_count() {
+  if constexpr (NS >= N) {
+    return 0;
+  } else {
+    constexpr int R = (NS * E <= N) ? E : N / NS;
+    constexpr int NB = E / R;
+    return (NS > 1 ? NB * (R - 1) : 0) + tw_count<N, E, NS * R>();
+  }
+}
+
+// The twiddles of one thread kept in registers: identical for every line the
+// thread transforms, so they are read from the table once.
+template <int N, int E, typename T>
+struct TwReg {
+  static constexpr int C = tw_count<N, E>() > 0 ? tw_count<N, E>() : 1;
+  cpx<T> w[C];
+};
+
+template <int N, int E, int NS, int OFF, typename T>
+__device__ __forceinline__ void tw_fill_stage(TwReg<N, E, T>& t, int j, const cpx<T>* __restrict__ tw) {
+  if constexpr (NS < N) {
+    constexpr int TT = N / E;
+    constexpr int R = (NS * E <= N) ? E : N / NS;
+    constexpr int NB = E / R;
+    if constexpr (NS > 1) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int kv = (j + TT * b) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) t.w[OFF + b * (R - 1) + r - 1] = tw[r * kv * (N / (NS * R))];
+      }
+      tw_fill_stage<N, E, NS * R, OFF + NB * (R - 1)>(t, j, tw);
+    } else {
+      tw_fill_stage<N, E, NS * R, OFF>(t, j, tw);
+    }
+  }
+}
+
+template <int N, int E, typename T>
+__device__ __forceinline__ TwReg<N, E, T> tw_fill(int j, const cpx<T>* __restrict__ tw) {
+  TwReg<N, E, T> t;
+  tw_fill_stage<N, E, 1, 0>(t, j, tw);
+  return t;
+}
+
+// stage twiddle of butterfly b, element r: from a table (pointer) or from registers
+template <int N, int E, int OFF, int R, typename T>
+__device__ __forceinline__ cpx<T> tw_get(const cpx<T>* __restrict__ tw, int b, int r, int idx) {
+  return tw[idx];
+}
+template <int N, int E, int OFF, int R, typename T>
+__device__ __forceinline__ cpx<T> tw_get(const TwReg<N, E, T>& t, int b, int r, int idx) {
+  return t.w[OFF + b * (R - 1) + r - 1];
+}
+
 // One Stockham stage (and, recursively, the ones after it).
-// NS = product of the radices already applied.
-template <int N, int E, bool INV, int NS, class Sync, typename T, class Lds>
-__device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j,
-                                          const cpx<T>* __restrict__ tw) {
+// NS = product of the radices already applied; OFF = twiddles used so far.
+template <int N, int E, bool INV, int NS, int OFF, class Sync, typename T, class Lds, class Tw>
+__device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j, const Tw& tw) {
   if constexpr (NS < N) {
     constexpr int TT = N / E;
     constexpr int R = (NS * E <= N) ? E : N / NS;
@@ -179,7 +235,7 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j,
       if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          cpx<T> w = tw[r * kv * (N / (NS * R))];
+          cpx<T> w = tw_get<N, E, OFF, R, T>(tw, b, r, r * kv * (N / (NS * R)));
           if (INV) w.y = -w.y;
           a[r] = cmul(a[r], w);
         }
@@ -199,17 +255,18 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j,
 #pragma unroll
       for (int m = 0; m < E; ++m) v[m] = lds.ld(j + TT * m);
       Sync::sync();
-      fft_stage<N, E, INV, NS * R, Sync>(v, lds, j, tw);
+      fft_stage<N, E, INV, NS * R, (NS > 1 ? OFF + NB * (R - 1) : OFF), Sync>(v, lds, j, tw);
     }
   }
 }
 
 // Full N-point transform of the strided register line.  With BlockSync every
 // thread of the block must call it; with WaveSync every lane of the wave.
-// tw points to w_N^m, m = 0..N-1 (normally a copy staged in LDS).
-template <int N, int E, bool INV, class Sync = BlockSync, typename T, class Lds>
-__device__ __forceinline__ void fft(cpx<T> (&v)[E], const Lds& lds, int j, const cpx<T>* __restrict__ tw) {
-  fft_stage<N, E, INV, 1, Sync>(v, lds, j, tw);
+// tw is either a pointer to w_N^m, m = 0..N-1 (normally a copy staged in LDS),
+// or the thread's TwReg.
+template <int N, int E, bool INV, class Sync = BlockSync, typename T, class Lds, class Tw>
+__device__ __forceinline__ void fft(cpx<T> (&v)[E], const Lds& lds, int j, const Tw& tw) {
+  fft_stage<N, E, INV, 1, 0, Sync>(v, lds, j, tw);
 }
 
 // Copy the N twiddles into LDS (block-wide; ends with a block barrier).
