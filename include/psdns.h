@@ -146,6 +146,29 @@ psdns_status psdns_get_state(psdns_plan* plan, const void* state, int32_t slot, 
 psdns_status psdns_set_state(psdns_plan* plan, void* state, int32_t slot, const void* canonical_in,
                              void* hip_stream);
 
+/* Spectra and statistics of every slot (Table 1; Eqs. (11)-(13)), accumulated in FP64 with
+ * a fixed summation order (bitwise reproducible).  `out` is a device buffer of
+ * batch * psdns_plan_info.spectra_doubles doubles; with ns = n_shells and S scalars the
+ * record of one slot is
+ *   [0, ns)                     E(s) = sum over nint|k| = s of |u_hat|^2/2 / N^6 (sums to K)
+ *   [ns*(1+j), ns*(2+j))        E_phi_j(s), same with phi_j (sums to <phi_j^2>/2)
+ *   b = ns*(1+S): b+0 K = <u.u>/2, b+1 eps = 2 nu <S:S>, b+2 u_rms = sqrt(2K/3),
+ *                 b+3 lambda = u_rms sqrt(15 nu/eps), b+4 Re_lambda = lambda u_rms/nu,
+ *                 b+5 eta = (nu^3/eps)^(1/4), b+6 l_o = u_rms^3/eps, b+7 T_e = l_o/u_rms
+ *   b+8+4j:       <phi_j^2>, chi_j = 2 D_j <|grad phi_j|^2>, production -2 g_j.<phi_j u>,
+ *                 production/chi_j   (Eq. (13))
+ *   p = b+8+4S:   p+0..2 <(du_i/dx_i)^2>, p+3..5 <(du_i/dx_i)^3>, p+6..8 <(du_i/dx_i)^4>,
+ *                 p+9..11 skewness S_{u_i,i} (Eq. (11)), p+12..14 flatness K_{u_i,i} (Eq. (12)),
+ *                 p+15 max(|u1|+|u2|+|u3|) (Eq. (10)),
+ *                 p+16+3j <(dphi_j/dx2)^2>, skewness, flatness of dphi_j/dx2
+ * flags: PSDNS_SPECTRA_SHELLS fills [0, p); PSDNS_SPECTRA_MOMENTS fills [p, end) (three
+ * extra inverse transforms per velocity component and scalar); other entries are NaN.
+ * Uses the workspace transform buffers; asynchronous on the stream. */
+#define PSDNS_SPECTRA_SHELLS 1
+#define PSDNS_SPECTRA_MOMENTS 2
+psdns_status psdns_spectra(psdns_plan* plan, const void* state, void* ws, double* out, int32_t flags,
+                           void* hip_stream);
+
 /* Per-kernel timing with HIP events on the launch stream (off by default). */
 typedef struct {
   char name[32];

@@ -90,11 +90,23 @@ int lines_per_xblock(int n, int ex) {
   return l;
 }
 
+// blocks per slot of the moments kernels (fixed, so their partial sums have a fixed order)
+int moment_blocks(int n) {
+  const long long lines = (long long)n * n;
+  return (int)(lines < 1024 ? lines : 1024);
+}
+
+int shell_count(int K) { return (int)std::lround(std::sqrt(3.0) * K) + 1; }
+
+// doubles per slot of the psdns_spectra record
+int spectra_record(int ns, int S) { return ns * (1 + S) + 8 + 4 * S + 16 + 3 * S; }
+
 struct Layout {
   Geom g;
   size_t csize;  // bytes per complex
-  size_t off_dyn, off_part, off_ystage, off_acc, off_abuf, off_bbuf, ws_bytes, st_bytes;
-  long long part_len;
+  size_t off_dyn, off_part, off_stat, off_ystage, off_acc, off_abuf, off_bbuf, ws_bytes, st_bytes;
+  long long part_len, stat_len;
+  int nbm, rec;
 };
 
 Layout make_layout(const psdns_plan_params* p, int ex) {
@@ -114,6 +126,9 @@ Layout make_layout(const psdns_plan_params* p, int ex) {
   g.a_field = (long long)g.N * g.M * g.PX;
   g.b_field = (long long)g.N * g.N * g.PX;
   g.nblk_x = (int)((long long)g.N * g.N / lines_per_xblock(g.N, ex));
+  g.ns = shell_count(g.K);
+  L.nbm = moment_blocks(g.N);
+  L.rec = spectra_record(g.ns, g.S);
   L.csize = p->precision == 32 ? 8 : 16;
   const size_t B = (size_t)g.batch;
   const long long n_init = ((long long)g.M * g.M * g.KX + 255) / 256;
@@ -124,6 +139,9 @@ Layout make_layout(const psdns_plan_params* p, int ex) {
   off = align_up(off + B * sizeof(DynDev), 256);
   L.off_part = off;
   off = align_up(off + (size_t)L.part_len * sizeof(double), 256);
+  L.off_stat = off;
+  L.stat_len = (long long)B * g.ns * (2 + 3 * g.S) + 2LL * B * L.nbm * (3 * 6 + 1);
+  off = align_up(off + (size_t)L.stat_len * sizeof(double), 256);
   L.off_ystage = off;
   off = align_up(off + B * g.F * (size_t)g.st_field * L.csize, 256);
   L.off_acc = off;
@@ -203,6 +221,9 @@ Ctx make_ctx(psdns_plan* plan, void* ws) {
   c.dyn = reinterpret_cast<DynDev*>(w + plan->L.off_dyn);
   c.part = reinterpret_cast<double*>(w + plan->L.off_part);
   c.part_len = plan->L.part_len;
+  c.stat = reinterpret_cast<double*>(w + plan->L.off_stat);
+  c.nbm = plan->L.nbm;
+  c.spectra_rec = plan->L.rec;
   c.ystage = w + plan->L.off_ystage;
   c.acc = w + plan->L.off_acc;
   c.abuf = w + plan->L.off_abuf;
@@ -331,8 +352,8 @@ psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
   out->n_scalars = g.S;
   out->precision = plan->p.precision;
   out->batch = g.batch;
-  out->n_shells = (int)std::lround(std::sqrt(3.0) * g.K) + 1;
-  out->spectra_doubles = 0;
+  out->n_shells = g.ns;
+  out->spectra_doubles = plan->L.rec;
   out->state_bytes = (int64_t)plan->L.st_bytes;
   out->workspace_bytes = (int64_t)plan->L.ws_bytes;
   out->elems_col = plan->ops.ec;
@@ -410,6 +431,19 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
     }
     HIP_TRY(hipGetLastError());
   }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_spectra(psdns_plan* plan, const void* state, void* ws, double* out, int32_t flags,
+                           void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !ws || !out) return fail(PSDNS_E_INVAL, "state, ws and out must be device pointers");
+  if (flags & ~3) return fail(PSDNS_E_INVAL, "flags must be a combination of PSDNS_SPECTRA_SHELLS and PSDNS_SPECTRA_MOMENTS");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  Ctx c = make_ctx(plan, ws);
+  plan->ops.spectra(c, state, out, flags, s);
+  HIP_TRY(hipGetLastError());
   return PSDNS_OK;
 }
 

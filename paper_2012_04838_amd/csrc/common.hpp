@@ -25,6 +25,7 @@ struct Geom {
   long long a_field;      // per field after the z pass: N*M*PX   ([z][ky_c][kx])
   long long b_field;      // per field after the y pass: N*N*PX   ([z][y][kx])
   int nblk_x;             // x-pass blocks per slot (partial maxima)
+  int ns;                 // spectral shells 0 .. ns-1, ns = nint(sqrt(3) K) + 1
 };
 
 // Static per-slot parameters, uploaded by psdns_set_slot.
@@ -80,6 +81,9 @@ struct Ctx {
   void* acc;               // [batch][F][M][M][PX]
   double* part;            // x-pass partial maxima [batch][nblk_x] and reduction scratch
   long long part_len;      // doubles available at part
+  double* stat;            // statistics partials (shell sums, moment partials)
+  int nbm;                 // blocks of the moments kernels per slot
+  int spectra_rec;         // doubles per slot of the spectra record
   Timer* timer;            // may be null
 };
 
@@ -94,6 +98,7 @@ struct Ops {
                      hipStream_t);
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);
   void (*set_state)(const Ctx&, void* state, int slot, const void* canon, hipStream_t);
+  void (*spectra)(const Ctx&, const void* state, double* out, int flags, hipStream_t);
 };
 
 template <int N>

@@ -262,53 +262,32 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
   return {__shfl(v.x, src), __shfl(v.y, src)};
 }
 
+// Lane-level helpers of the x pass: which unique half-spectrum entries a lane
+// loads, and how it assembles its strided positions of h = f + i g.
 template <int N, typename T>
-__global__ void PSDNS_X_BOUNDS(Cfg<N, T>::X_THREADS)
-k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
-         double* __restrict__ maxpart, Geom g, int want_max) {
-  using C = Cfg<N, T>;
-  constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
-  constexpr int K = (N - 1) / 3;
-  constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
+struct XLine {
+  static constexpr int E = Cfg<N, T>::EX, TT = Cfg<N, T>::TX;
+  static constexpr int K = (N - 1) / 3;
+  static constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
   static_assert(TT <= 64 && 64 % TT == 0, "a line must stay inside one wavefront");
   static_assert(NQ < E, "retained band must be shorter than the line");
-  __shared__ cpx<T> smem[L * LP];
-  __shared__ cpx<T> stw[N];
-  __shared__ double red[C::X_THREADS];
-  const int slot = blockIdx.y;
-  if (!slots[slot].active) return;
-  stage_twiddles<N>(stw, tw_g);
-  const int li = threadIdx.x / TT;
-  const int j = threadIdx.x % TT;
-  // FP32: the lane's twiddles live in registers for all nine transforms of the
-  // line; FP64 keeps them in LDS to leave registers for the line data.
-  constexpr bool kRegTw = sizeof(T) == 4;
-  using TwT = std::conditional_t<kRegTw, TwReg<N, E, T>, const cpx<T>*>;
-  TwT tw;
-  if constexpr (kRegTw)
-    tw = tw_fill<N, E>(j, stw);
-  else
-    tw = stw;
-  const int lane = threadIdx.x & 63;
-  const int partner = (lane - j) + ((TT - j) & (TT - 1));
-  const long long line = (long long)blockIdx.x * L + li;  // z * N + y
-  const LdsLine<T> lds{smem + li * LP};
-  cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
-
-  // r[q] = entry kx = j + TT q of field f (zero beyond K); at kx = 0 only the real
-  // part is kept, as a complex-to-real transform does.
-  auto load = [&](int f, cpx<T> (&r)[NQ]) {
-    const cpx<T>* p = base + (long long)f * g.b_field;
+  int j, partner;
+  __device__ __forceinline__ explicit XLine(int tid)
+      : j(tid % TT), partner(((tid & 63) - tid % TT) + ((TT - tid % TT) & (TT - 1))) {}
+  __device__ __forceinline__ T kx(int q) const { return T(j + TT * q); }
+  // r[q] = entry kx = j + TT q of the line at p (zero beyond K); at kx = 0 only the
+  // real part is kept, as a complex-to-real transform does.
+  __device__ __forceinline__ void load(const cpx<T>* p, cpx<T> (&r)[NQ]) const {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int kx = j + TT * q;
-      r[q] = kx <= K ? p[kx] : czero<T>();
+      const int k = j + TT * q;
+      r[q] = k <= K ? p[k] : czero<T>();
     }
     if (j == 0) r[0].y = T(0);
-  };
+  }
   // h at positions n = j + TT m from the half-spectrum entries of f (va) and g (vb):
   // n <= K: va + i vb;  n >= N - K: conj(va) + i conj(vb) of kx = N - n;  else 0
-  auto build = [&](const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) {
+  __device__ __forceinline__ void build(const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) const {
     static_for<0, E>([&](auto mc) {
       constexpr int m = decltype(mc)::value;
       const int n = j + TT * m;
@@ -343,7 +322,45 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       }
       h[m] = a + mul_i(b);
     });
-  };
+  }
+};
+
+template <int N, typename T>
+__global__ void PSDNS_X_BOUNDS(Cfg<N, T>::X_THREADS)
+k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
+         double* __restrict__ maxpart, Geom g, int want_max) {
+  using C = Cfg<N, T>;
+  constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
+  constexpr int K = (N - 1) / 3;
+  constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
+  static_assert(TT <= 64 && 64 % TT == 0, "a line must stay inside one wavefront");
+  static_assert(NQ < E, "retained band must be shorter than the line");
+  __shared__ cpx<T> smem[L * LP];
+  __shared__ cpx<T> stw[N];
+  __shared__ double red[C::X_THREADS];
+  const int slot = blockIdx.y;
+  if (!slots[slot].active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const int li = threadIdx.x / TT;
+  const int j = threadIdx.x % TT;
+  // FP32: the lane's twiddles live in registers for all nine transforms of the
+  // line; FP64 keeps them in LDS to leave registers for the line data.
+  constexpr bool kRegTw = sizeof(T) == 4;
+  using TwT = std::conditional_t<kRegTw, TwReg<N, E, T>, const cpx<T>*>;
+  TwT tw;
+  if constexpr (kRegTw)
+    tw = tw_fill<N, E>(j, stw);
+  else
+    tw = stw;
+  const int lane = threadIdx.x & 63;
+  const int partner = (lane - j) + ((TT - j) & (TT - 1));
+  const long long line = (long long)blockIdx.x * L + li;  // z * N + y
+  const LdsLine<T> lds{smem + li * LP};
+  cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
+
+  const XLine<N, T> xl(threadIdx.x);
+  auto load = [&](int f, cpx<T> (&r)[NQ]) { xl.load(base + (long long)f * g.b_field, r); };
+  auto build = [&](const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) { xl.build(va, vb, h); };
   auto kxq = [&](int q) { return T(j + TT * q); };
 
   cpx<T> r0[NQ], r1[NQ], r2[NQ], r3[NQ], r4[NQ], r5[NQ];
@@ -933,6 +950,356 @@ k_convert(cpx<T>* __restrict__ st, cpx<T>* __restrict__ canon, Geom g, int slot)
 }
 
 // ---------------------------------------------------------------------------
+// spectra and statistics (Table 1, Eqs. (11)-(13)), all accumulated in FP64
+// with a fixed summation order (bitwise reproducible, no floating atomics)
+// ---------------------------------------------------------------------------
+// per shell: [0] sum w |u|^2/2, [1] sum w (|k|^2 |u|^2 + |k.u|^2),
+// per scalar s: [2+3s] sum w |phi|^2/2, [3+3s] sum w |k|^2 |phi|^2, [4+3s] sum w Re(conj(phi) g_s.u)
+__host__ __device__ inline int shell_quantities(int S) { return 2 + 3 * S; }
+
+__device__ __forceinline__ int isqrt_floor(long long v) {
+  if (v <= 0) return 0;
+  long long r = (long long)sqrt((double)v);
+  while (r * r > v) --r;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return (int)r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_shell_sums(const cpx<T>* __restrict__ st, const SlotDev* __restrict__ slots, Geom g, double* __restrict__ part,
+             int ns) {
+  constexpr int MAXQ = 2 + 3 * kMaxScalars;
+  __shared__ double red[MAXQ][256];
+  const int sh = blockIdx.x;
+  const int slot = blockIdx.y;
+  const SlotDev& sp = slots[slot];
+  const int S = g.S, Q = shell_quantities(S), K = g.K, M = g.M;
+  const long long lo = sh == 0 ? 0 : (long long)sh * sh - sh + 1;  // nint(|k|) = sh <=> lo <= |k|^2 <= hi
+  const long long hi = (long long)sh * sh + sh;
+  int R = isqrt_floor(hi);
+  if (R > K) R = K;
+  const int span = 2 * R + 1;
+  double acc[MAXQ];
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q) acc[q] = 0.0;
+  const cpx<T>* base = st + (long long)slot * g.F * g.st_field;
+  for (int p = threadIdx.x; p < span * span; p += 256) {
+    const int kz = p / span - R, ky = p % span - R;
+    const long long r2 = (long long)kz * kz + (long long)ky * ky;
+    if (r2 > hi) continue;
+    int x0 = lo - r2 > 0 ? isqrt_floor(lo - r2 - 1) + 1 : 0;  // smallest kx with kx^2 >= lo - r2
+    int x1 = isqrt_floor(hi - r2);
+    if (x1 > K) x1 = K;
+    const int kzc = kz >= 0 ? kz : kz + M, kyc = ky >= 0 ? ky : ky + M;
+    const long long row = ((long long)kzc * M + kyc) * g.PX;
+    for (int kx = x0; kx <= x1; ++kx) {
+      const long long o = row + kx;
+      const double w = kx == 0 ? 1.0 : 2.0;
+      const double k2 = double(r2) + double(kx) * kx;
+      const cpx<T> a = base[o], b = base[o + g.st_field], c = base[o + 2 * g.st_field];
+      const double u1r = a.x, u1i = a.y, u2r = b.x, u2i = b.y, u3r = c.x, u3i = c.y;
+      const double uu = u1r * u1r + u1i * u1i + u2r * u2r + u2i * u2i + u3r * u3r + u3i * u3i;
+      const double kur = kx * u1r + ky * u2r + kz * u3r, kui = kx * u1i + ky * u2i + kz * u3i;
+      acc[0] += 0.5 * w * uu;
+      acc[1] += w * (k2 * uu + kur * kur + kui * kui);
+#pragma unroll
+      for (int s = 0; s < kMaxScalars; ++s) {
+        if (s >= S) break;
+        const cpx<T> f = base[o + (3 + s) * g.st_field];
+        const double fr = f.x, fi = f.y, ff = fr * fr + fi * fi;
+        const double gur = sp.g[s][0] * u1r + sp.g[s][1] * u2r + sp.g[s][2] * u3r;
+        const double gui = sp.g[s][0] * u1i + sp.g[s][1] * u2i + sp.g[s][2] * u3i;
+        acc[2 + 3 * s] += 0.5 * w * ff;
+        acc[3 + 3 * s] += w * k2 * ff;
+        acc[4 + 3 * s] += w * (fr * gur + fi * gui);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < MAXQ; ++q)
+    if (q < Q) red[q][threadIdx.x] = acc[q];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o)
+      for (int q = 0; q < Q; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + o];
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < Q) part[((long long)slot * ns + sh) * Q + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Inverse z transform of up to 8 derived fields i k_axis * (field) of the state
+// (axis 0: none, 1: x, 2: y, 3: z); same layout and scaling as k_z_inverse.
+struct DerivSpec {
+  int nf;
+  int field[8];
+  int axis[8];
+};
+
+template <int N, typename T>
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_stats_z(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g, Geom g,
+          DerivSpec spec) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3, M = 2 * K + 1;
+  __shared__ cpx<T> smem[W * N];
+  __shared__ cpx<T> stw[N];
+  const int slot = blockIdx.z;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
+  const int c = threadIdx.x % W, j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c, kyc = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const int ky = wave_of_compact(kyc, K, M);
+  const LdsCol<T, W> lds{smem + c};
+  const T scale = T(1) / (T(N) * T(N) * T(N));
+  const long long rows = (long long)M * g.PX;
+  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
+  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
+  cpx<T> a[E];
+  for (int f = 0; f < spec.nf; ++f) {
+    const cpx<T>* p = in + (long long)spec.field[f] * g.st_field;
+    const int ax = spec.axis[f];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int kc = compact_of(j + TT * m, N, K, M);
+      cpx<T> v = (valid && kc >= 0) ? scale * p[kc * rows] : czero<T>();
+      const T kk = ax == 1 ? T(kx) : ax == 2 ? T(ky) : T(wave_of(j + TT * m, N));
+      a[m] = ax == 0 ? v : mul_is(v, kk);
+    }
+    fft<N, E, true>(a, lds, j, tw);
+    if (valid) {
+      cpx<T>* q = out + (long long)f * g.a_field;
+#pragma unroll
+      for (int m = 0; m < E; ++m) q[(long long)(j + TT * m) * rows] = a[m];
+    }
+  }
+}
+
+// Plain inverse y transform of nf fields (A layout -> B layout).
+template <int N, typename T>
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_stats_y(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, Geom g,
+          int nf) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3, M = 2 * K + 1;
+  __shared__ cpx<T> smem[W * N];
+  __shared__ cpx<T> stw[N];
+  const int slot = blockIdx.z;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
+  const int c = threadIdx.x % W, j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c, z = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const LdsCol<T, W> lds{smem + c};
+  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)z * M * g.PX + kx;
+  cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
+  cpx<T> a[E];
+  for (int f = 0; f < nf; ++f) {
+    const cpx<T>* p = in + (long long)f * g.a_field;
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int kc = compact_of(j + TT * m, N, K, M);
+      a[m] = (valid && kc >= 0) ? p[kc * g.PX] : czero<T>();
+    }
+    fft<N, E, true>(a, lds, j, tw);
+    if (valid) {
+      cpx<T>* q = out + (long long)f * g.b_field;
+#pragma unroll
+      for (int m = 0; m < E; ++m) q[(long long)(j + TT * m) * g.PX] = a[m];
+    }
+  }
+}
+
+// x inverse of nf (<= 6) B fields per line; FP64 sums of f^2, f^3, f^4 for the
+// fields [mom0, nf) and max |u1|+|u2|+|u3| when fields 0..2 are the velocity
+// (with_max).  Fixed grid with a fixed line assignment; one partial record per block:
+// [3 * (nf - mom0)] moments then the max.
+template <int N, typename T>
+__global__ void PSDNS_X_BOUNDS(Cfg<N, T>::X_THREADS)
+k_x_moments(const cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, Geom g, int nf, int mom0,
+            int with_max, double* __restrict__ part) {
+  using C = Cfg<N, T>;
+  using XL = XLine<N, T>;
+  constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP, NQ = XL::NQ;
+  __shared__ cpx<T> smem[L * LP];
+  __shared__ cpx<T> stw[N];
+  __shared__ double red[C::X_THREADS];
+  const int slot = blockIdx.y;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
+  const XL xl(threadIdx.x);
+  const int li = threadIdx.x / TT, j = xl.j;
+  const LdsLine<T> lds{smem + li * LP};
+  double mom[6][3];
+#pragma unroll
+  for (int f = 0; f < 6; ++f) mom[f][0] = mom[f][1] = mom[f][2] = 0.0;
+  double mx = 0.0;
+  const long long nlines = (long long)N * N;
+  for (long long l0 = (long long)blockIdx.x * L; l0 < nlines; l0 += (long long)gridDim.x * L) {
+    const cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + (l0 + li) * g.PX;
+    T u12x[E], u12y[E];
+#pragma unroll
+    for (int f = 0; f < 6; f += 2) {
+      if (f >= nf) break;
+      cpx<T> ra[NQ], rb[NQ], h[E];
+      xl.load(base + (long long)f * g.b_field, ra);
+      if (f + 1 < nf) {
+        xl.load(base + (long long)(f + 1) * g.b_field, rb);
+      } else {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) rb[q] = czero<T>();
+      }
+      xl.build(ra, rb, h);
+      fft<N, E, true, WaveSync>(h, lds, j, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const double vx = h[m].x, vy = h[m].y;
+        if (f >= mom0) {
+          const double v2 = vx * vx;
+          mom[f][0] += v2;
+          mom[f][1] += v2 * vx;
+          mom[f][2] += v2 * v2;
+        }
+        if (f + 1 < nf && f + 1 >= mom0) {
+          const double v2 = vy * vy;
+          mom[f + 1][0] += v2;
+          mom[f + 1][1] += v2 * vy;
+          mom[f + 1][2] += v2 * v2;
+        }
+        if (with_max && f == 0) {
+          u12x[m] = h[m].x;
+          u12y[m] = h[m].y;
+        }
+        if (with_max && f == 2) {
+          const double sm = fabs((double)u12x[m]) + fabs((double)u12y[m]) + fabs(vx);
+          mx = (sm > mx || sm != sm) ? sm : mx;
+        }
+      }
+    }
+  }
+  const int nm = nf - mom0;
+  double* out = part + ((long long)slot * gridDim.x + blockIdx.x) * (3 * 6 + 1);
+  for (int q = 0; q < 3 * nm + 1; ++q) {
+    double v;
+    if (q < 3 * nm) {
+      // select mom[mom0 + q / 3][q % 3] without dynamic register indexing
+      v = 0.0;
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          if (f == mom0 + q / 3 && r == q % 3) v = mom[f][r];
+    } else {
+      v = mx;
+    }
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = C::X_THREADS / 2; o > 0; o >>= 1) {
+      if ((int)threadIdx.x < o) {
+        const double a = red[threadIdx.x], b = red[threadIdx.x + o];
+        red[threadIdx.x] = q < 3 * nm ? a + b : ((b > a || b != b) ? b : a);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = red[0];
+    __syncthreads();
+  }
+}
+
+// Final record of one slot (layout in include/psdns.h).
+static __global__ void __launch_bounds__(256)
+k_spectra_finalize(const double* __restrict__ shells, const double* __restrict__ mom1, const double* __restrict__ mom2,
+                   int nbm, const SlotDev* __restrict__ slots, Geom g, int ns, int flags, double* __restrict__ out,
+                   int rec) {
+  const int slot = blockIdx.x;
+  const SlotDev& sp = slots[slot];
+  const int S = g.S, Q = shell_quantities(S);
+  double* o = out + (long long)slot * rec;
+  const double nan = __builtin_nan("");
+  const double n3 = double(g.N) * g.N * g.N, n6 = n3 * n3;
+  const int base = ns * (1 + S);
+  const int pb = base + 8 + 4 * S;
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < rec; ++i) o[i] = nan;
+  }
+  __syncthreads();
+  if ((flags & 1) && threadIdx.x == 0) {
+    const double* sh = shells + (long long)slot * ns * Q;
+    double K = 0.0, diss = 0.0;
+    for (int s = 0; s < ns; ++s) {
+      o[s] = sh[s * Q + 0] / n6;
+      K += sh[s * Q + 0];
+      diss += sh[s * Q + 1];
+    }
+    K /= n6;
+    const double eps = sp.nu * diss / n6;
+    const double urms = sqrt(2.0 * K / 3.0);
+    o[base + 0] = K;
+    o[base + 1] = eps;
+    o[base + 2] = urms;
+    if (eps > 0.0) {
+      const double lam = urms * sqrt(15.0 * sp.nu / eps);
+      o[base + 3] = lam;
+      o[base + 4] = lam * urms / sp.nu;
+      o[base + 5] = pow(sp.nu * sp.nu * sp.nu / eps, 0.25);
+      o[base + 6] = urms * urms * urms / eps;
+      o[base + 7] = urms > 0.0 ? (urms * urms * urms / eps) / urms : nan;
+    }
+    for (int s = 0; s < S; ++s) {
+      double var = 0.0, chi = 0.0, prod = 0.0;
+      for (int h = 0; h < ns; ++h) {
+        o[ns * (1 + s) + h] = sh[h * Q + 2 + 3 * s] / n6;
+        var += sh[h * Q + 2 + 3 * s];
+        chi += sh[h * Q + 3 + 3 * s];
+        prod += sh[h * Q + 4 + 3 * s];
+      }
+      const double d = sp.diff[3 + s];
+      o[base + 8 + 4 * s + 0] = 2.0 * var / n6;
+      o[base + 8 + 4 * s + 1] = 2.0 * d * chi / n6;
+      o[base + 8 + 4 * s + 2] = -2.0 * prod / n6;
+      o[base + 8 + 4 * s + 3] = (-2.0 * prod / n6) / (2.0 * d * chi / n6);
+    }
+  }
+  if ((flags & 2) && threadIdx.x == 0) {
+    // round 1: fields u1 u2 u3 | du1/dx1 du2/dx2 (moments of the last two) + max
+    // round 2: du3/dx3, dphi_s/dx2 (moments of all)
+    double m1[2][3] = {{0, 0, 0}, {0, 0, 0}}, mx = 0.0;
+    double m2[1 + kMaxScalars][3] = {};
+    const int r1 = 3 * 2 + 1, r2 = 3 * (1 + S) + 1;
+    for (int b = 0; b < nbm; ++b) {
+      const double* p = mom1 + ((long long)slot * nbm + b) * (3 * 6 + 1);
+      for (int f = 0; f < 2; ++f)
+        for (int r = 0; r < 3; ++r) m1[f][r] += p[3 * f + r];
+      const double v = p[r1 - 1];
+      mx = (v > mx || v != v) ? v : mx;
+      const double* q = mom2 + ((long long)slot * nbm + b) * (3 * 6 + 1);
+      for (int f = 0; f < 1 + S; ++f)
+        for (int r = 0; r < 3; ++r) m2[f][r] += q[3 * f + r];
+      (void)r2;
+    }
+    const double* mm[3] = {m1[0], m1[1], m2[0]};
+    for (int i = 0; i < 3; ++i) {
+      const double a2 = mm[i][0] / n3, a3 = mm[i][1] / n3, a4 = mm[i][2] / n3;
+      o[pb + i] = a2;
+      o[pb + 3 + i] = a3;
+      o[pb + 6 + i] = a4;
+      o[pb + 9 + i] = a2 > 0 ? a3 / pow(a2, 1.5) : nan;
+      o[pb + 12 + i] = a2 > 0 ? a4 / (a2 * a2) : nan;
+    }
+    o[pb + 15] = mx;
+    for (int s = 0; s < S; ++s) {
+      const double a2 = m2[1 + s][0] / n3, a3 = m2[1 + s][1] / n3, a4 = m2[1 + s][2] / n3;
+      o[pb + 16 + 3 * s] = a2;
+      o[pb + 17 + 3 * s] = a2 > 0 ? a3 / pow(a2, 1.5) : nan;
+      o[pb + 18 + 3 * s] = a2 > 0 ? a4 / (a2 * a2) : nan;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 struct TimedLaunch {
@@ -1025,6 +1392,46 @@ struct Engine {
         static_cast<cpx<T>*>(state), const_cast<cpx<T>*>(static_cast<const cpx<T>*>(canon)), g, slot);
   }
 
+  static void spectra(const Ctx& x, const void* state, double* out, int flags, hipStream_t s) {
+    const Geom& g = x.g;
+    const cpx<T>* st = static_cast<const cpx<T>*>(state);
+    const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
+    cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
+    cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
+    const int ns = g.ns, Q = shell_quantities(g.S);
+    double* shells = x.stat;
+    double* mom1 = shells + (long long)g.batch * ns * Q;
+    double* mom2 = mom1 + (long long)g.batch * x.nbm * (3 * 6 + 1);
+    const int ntile = (g.KX + C::W - 1) / C::W;
+    TimedLaunch tl(x.timer, KID_AUX, s);
+    if (flags & 1) k_shell_sums<T><<<dim3(ns, g.batch), 256, 0, s>>>(st, x.slots, g, shells, ns);
+    if (flags & 2) {
+      DerivSpec d1{};
+      d1.nf = 5;
+      const int f1[5] = {0, 1, 2, 0, 1}, a1[5] = {0, 0, 0, 1, 2};
+      for (int i = 0; i < 5; ++i) {
+        d1.field[i] = f1[i];
+        d1.axis[i] = a1[i];
+      }
+      k_stats_z<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(st, A, tw, g, d1);
+      k_stats_y<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, g, 5);
+      k_x_moments<N, T><<<dim3(x.nbm, g.batch), C::X_THREADS, 0, s>>>(B, tw, g, 5, 3, 1, mom1);
+      DerivSpec d2{};
+      d2.nf = 1 + g.S;
+      d2.field[0] = 2;
+      d2.axis[0] = 3;
+      for (int i = 0; i < g.S; ++i) {
+        d2.field[1 + i] = 3 + i;
+        d2.axis[1 + i] = 2;
+      }
+      k_stats_z<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(st, A, tw, g, d2);
+      k_stats_y<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, g, 1 + g.S);
+      k_x_moments<N, T><<<dim3(x.nbm, g.batch), C::X_THREADS, 0, s>>>(B, tw, g, 1 + g.S, 0, 0, mom2);
+    }
+    k_spectra_finalize<<<g.batch, 256, 0, s>>>(shells, mom1, mom2, x.nbm, x.slots, g, ns, flags, out,
+                                               x.spectra_rec);
+  }
+
   static Ops ops() {
     Ops o;
     o.ec = C::EC;
@@ -1033,6 +1440,7 @@ struct Engine {
     o.init_field = &init_field;
     o.get_state = &get_state;
     o.set_state = &set_state;
+    o.spectra = &spectra;
     return o;
   }
 };

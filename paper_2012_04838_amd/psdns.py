@@ -19,6 +19,8 @@ MAX_SCALARS = 4
 
 FLAG_NONFINITE = 1
 FLAG_CFL = 2
+SPECTRA_SHELLS = 1
+SPECTRA_MOMENTS = 2
 
 _c_int32 = ctypes.c_int32
 _c_void_p = ctypes.c_void_p
@@ -71,6 +73,7 @@ _SIGS = {
     "psdns_clear_step_info": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p]),
     "psdns_get_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
+    "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_set_timing": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_get_timing": (ctypes.c_int, [_c_void_p, ctypes.POINTER(KernelTiming), _c_int32,
                                         ctypes.POINTER(_c_int32)]),
@@ -227,6 +230,18 @@ class Plan:
         _check(lib().psdns_set_state(self._h, _ptr(state), slot, _ptr(c), _stream()))
         torch.cuda.current_stream().synchronize()  # keep c alive until the copy ran
 
+    def spectra_raw(self, state, ws, flags: int = SPECTRA_SHELLS | SPECTRA_MOMENTS):
+        """Device tensor [batch][spectra_doubles] of FP64 records (layout in include/psdns.h)."""
+        torch = _torch()
+        out = torch.empty((self.batch, int(self.info.spectra_doubles)), dtype=torch.float64, device="cuda")
+        _check(lib().psdns_spectra(self._h, _ptr(state), _ptr(ws), _ptr(out), flags, _stream()))
+        return out
+
+    def spectra(self, state, ws, flags: int = SPECTRA_SHELLS | SPECTRA_MOMENTS):
+        """Per-slot dicts of shell spectra and statistics (copies to the host)."""
+        raw = self.spectra_raw(state, ws, flags).cpu().numpy()
+        return [parse_spectra(r, int(self.info.n_shells), self.n_scalars) for r in raw]
+
     def set_timing(self, enable: bool) -> None:
         _check(lib().psdns_set_timing(self._h, 1 if enable else 0))
 
@@ -235,3 +250,19 @@ class Plan:
         cnt = _c_int32()
         _check(lib().psdns_get_timing(self._h, arr, 16, ctypes.byref(cnt)))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
+
+
+def parse_spectra(r, ns: int, S: int) -> dict:
+    """Named view of one psdns_spectra record."""
+    b = ns * (1 + S)
+    p = b + 8 + 4 * S
+    d = {"E": r[:ns].copy(), "E_phi": r[ns:b].reshape(S, ns).copy()}
+    for i, k in enumerate(("K", "eps", "u_rms", "lam", "Re_lambda", "eta", "l_o", "T_e")):
+        d[k] = float(r[b + i])
+    sc = r[b + 8:b + 8 + 4 * S].reshape(S, 4) if S else np.zeros((0, 4))
+    d.update(phi_var=sc[:, 0].copy(), chi=sc[:, 1].copy(), production=sc[:, 2].copy(), prod_over_chi=sc[:, 3].copy())
+    d.update(vgt_m2=r[p:p + 3].copy(), vgt_m3=r[p + 3:p + 6].copy(), vgt_m4=r[p + 6:p + 9].copy(),
+             vgt_skew=r[p + 9:p + 12].copy(), vgt_flat=r[p + 12:p + 15].copy(), max_abs_u_sum=float(r[p + 15]))
+    ph = r[p + 16:p + 16 + 3 * S].reshape(S, 3) if S else np.zeros((0, 3))
+    d.update(phi2_m2=ph[:, 0].copy(), phi2_skew=ph[:, 1].copy(), phi2_flat=ph[:, 2].copy())
+    return d

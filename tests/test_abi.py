@@ -1,0 +1,63 @@
+"""Host-side checks of the C ABI that need no GPU: every function declared in
+include/psdns.h is exported, and argument validation fails cleanly."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2012_04838_amd import psdns
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "psdns.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(psdns_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    L = psdns.lib()
+    names = declared_functions()
+    assert len(names) >= 15
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    # every declared function has a binding signature
+    assert set(names) <= set(psdns._SIGS), set(names) - set(psdns._SIGS)
+
+
+def test_sizes_reject_invalid_params():
+    assert psdns.state_bytes(100, 0, 64) == 0
+    assert psdns.state_bytes(512, 5, 64) == 0
+    assert psdns.state_bytes(512, 2, 16) == 0
+    assert psdns.workspace_bytes(2048, 0, 32) == 0
+
+
+def test_sizes_follow_the_compact_layout():
+    for n, s, prec in [(32, 1, 64), (512, 2, 32), (1024, 1, 64)]:
+        K = (n - 1) // 3
+        M, PX = 2 * K + 1, ((K + 1 + 15) // 16) * 16
+        cs = 8 if prec == 32 else 16
+        assert psdns.state_bytes(n, s, prec) == (3 + s) * M * M * PX * cs
+        ws = psdns.workspace_bytes(n, s, prec)
+        assert ws >= ((5 + 2 * s) * n * M * PX + (6 + 3 * s) * n * n * PX + 2 * (3 + s) * M * M * PX) * cs
+        assert psdns.state_bytes(n, s, prec, batch=3) == 3 * psdns.state_bytes(n, s, prec)
+
+
+def test_plan_create_validates_before_touching_the_device():
+    L = psdns.lib()
+    h = ctypes.c_void_p()
+    p = psdns.plan_params(96, 0, 64, 1)
+    assert L.psdns_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert b"power of two" in L.psdns_last_error()
+    assert L.psdns_plan_create(None, ctypes.byref(h)) == -1
+    assert L.psdns_plan_destroy(None) == 0
+    assert L.psdns_step(None, None, None, 0.1, 1, None) == -1
+
+
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024])
+def test_every_size_has_device_code(n):
+    # sizes are reported for every supported grid in both precisions
+    for prec in (32, 64):
+        assert psdns.workspace_bytes(n, 1, prec) > 0
