@@ -33,7 +33,8 @@ import numpy as np
 import scipy.fft as sfft
 
 # Threads handed to scipy.fft (a plain library primitive; no blocking or fusion).
-FFT_WORKERS = int(os.environ.get("PSDNS_ORACLE_FFT_WORKERS", os.cpu_count() or 1))
+FFT_WORKERS = int(os.environ.get("PSDNS_ORACLE_FFT_WORKERS",
+                                 os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
 
 
 # --------------------------------------------------------------------------
@@ -537,19 +538,16 @@ def full_spectrum_dict(state: np.ndarray):
     F = state.shape[0]
     full = np.zeros((F, M, M, M), dtype=np.complex128)
     r = np.arange(-K, K + 1)
-    iz = r % N
-    iy = r % N
-    # kx >= 0 part straight from storage
-    for a, kxv in enumerate(range(0, K + 1)):
-        full[:, :, :, K + kxv] = state[:, iz][:, :, iy][:, :, :, kxv]
-    # kx < 0 part: conj of the partner at (-kx, -ky, -kz)
-    for kxv in range(1, K + 1):
-        part = state[:, (-r) % N][:, :, (-r) % N][:, :, :, kxv]
-        full[:, :, :, K - kxv] = np.conj(part)
+    # kx >= 0 straight from storage
+    pos = state[:, :, :, : K + 1][:, r % N][:, :, r % N]
+    full[:, :, :, K:] = pos
+    # kx < 0: conj of the stored partner at (-kx, -ky, -kz)
+    neg = state[:, :, :, 1: K + 1][:, (-r) % N][:, :, (-r) % N]
+    full[:, :, :, :K] = np.conj(neg[:, :, :, ::-1])
     return full
 
 
-def galerkin_mode(state: np.ndarray, prm: Params, k: Sequence[int]) -> np.ndarray:
+def galerkin_mode(state: np.ndarray, prm: Params, k: Sequence[int], full: np.ndarray | None = None) -> np.ndarray:
     """Nonlinear RHS Nl(y) at one retained mode k, straight from its definition as a
     truncated Galerkin convolution (no FFT):
 
@@ -563,15 +561,22 @@ def galerkin_mode(state: np.ndarray, prm: Params, k: Sequence[int]) -> np.ndarra
     N = state.shape[-3]
     K = kmax_retained(N)
     S = state.shape[0] - 3
-    full = full_spectrum_dict(state)
+    if full is None:
+        full = full_spectrum_dict(state)
     kx0, ky0, kz0 = (int(v) for v in k)
-    r = np.arange(-K, K + 1)
-    PZ, PY, PX = np.meshgrid(r, r, r, indexing="ij")
-    QZ, QY, QX = kz0 - PZ, ky0 - PY, kx0 - PX
-    ok = (np.abs(QX) <= K) & (np.abs(QY) <= K) & (np.abs(QZ) <= K)
-    up = full[:3][:, ok]
-    qx, qy, qz = QX[ok], QY[ok], QZ[ok]
-    uq = full[:, QZ[ok] + K, QY[ok] + K, QX[ok] + K]
+    # p ranges over the retained cube with q = k - p retained too: a box per axis
+    def box(k0):
+        lo, hi = max(-K, k0 - K), min(K, k0 + K)
+        return np.arange(lo, hi + 1)
+    pz, py, px = box(kz0), box(ky0), box(kx0)
+    up = full[:3, pz[0] + K:pz[-1] + K + 1, py[0] + K:py[-1] + K + 1, px[0] + K:px[-1] + K + 1]
+    # q = k - p runs backwards as p runs forwards along each axis
+    uq = full[:, kz0 - pz[-1] + K:kz0 - pz[0] + K + 1,
+              ky0 - py[-1] + K:ky0 - py[0] + K + 1,
+              kx0 - px[-1] + K:kx0 - px[0] + K + 1][:, ::-1, ::-1, ::-1]
+    qz = (kz0 - pz)[:, None, None]
+    qy = (ky0 - py)[None, :, None]
+    qx = (kx0 - px)[None, None, :]
     # omega_hat_q = i q x u_hat_q
     w1 = 1j * (qy * uq[2] - qz * uq[1])
     w2 = 1j * (qz * uq[0] - qx * uq[2])

@@ -47,15 +47,26 @@ namespace psdns {
 #define PSDNS_X_BOUNDS(...) __launch_bounds__((__VA_ARGS__))
 #endif
 
+#ifndef PSDNS_COL_BYTES
+#define PSDNS_COL_BYTES 128
+#endif
+#ifndef PSDNS_COL_MAXT
+#define PSDNS_COL_MAXT 1024
+#endif
+
 template <int N, typename T>
 struct Cfg {
-  // columns per block: one 128-byte row of complex values
-  static constexpr int W = 128 / (int)sizeof(cpx<T>);
+  // columns per block: one row segment of PSDNS_COL_BYTES bytes of complex values
+  static constexpr int W = PSDNS_COL_BYTES / (int)sizeof(cpx<T>);
   // elements per thread of the column passes (z, y) and of the x pass
   static constexpr int EC0 = sizeof(T) == 4 ? PSDNS_EC32 : PSDNS_EC64;
-  static constexpr int EC = N < EC0 ? N : EC0;
+  // at least N * W / 1024 elements per thread, so a block stays within 1024 threads
+  static constexpr int EC1 = EC0 * PSDNS_COL_MAXT < N * W ? N * W / PSDNS_COL_MAXT : EC0;
+  static constexpr int EC = N < EC1 ? N : EC1;
   static constexpr int TC = N / EC;
   static constexpr int COL_THREADS = W * TC;
+  static_assert(COL_THREADS <= 1024, "column block too large");
+  static_assert((W * N + N) * sizeof(cpx<T>) <= 160 * 1024, "column pass LDS exceeds 160 KB");
   // x pass: a line never spans two wavefronts (TX <= 64)
   static constexpr int EX0 = N > 512 ? N / 64 : 8;
   static constexpr int EX = N < EX0 ? N : EX0;

@@ -1,0 +1,102 @@
+"""Full-size checks in the benchmark's launch configuration (512^3, S = 2, FP32):
+sampled right-hand-side modes against the oracle's FFT-free Galerkin convolution
+(FP64, computed mode by mode), and properties that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle as ora
+from tests.gpu_helpers import make_plan, set_params, torch_mod
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N, S = 512, 2
+PRM = ora.Params(nu=7e-4, schmidt=(0.7, 1.0), mean_grad=((0.0, 1.0, 0.0), (0.0, 1.0, 0.0)), power=0.1,
+                 k_force=2.0)
+
+
+@pytest.fixture(scope="module")
+def bench_state():
+    torch = torch_mod()
+    plan = make_plan(N, S, 32)
+    set_params(plan, 0, PRM)
+    st, out, ws = plan.new_state(), plan.new_state(), plan.new_workspace()
+    plan.init_field(st, ws, 0, seed=3, k_peak=8.0, kinetic_energy=1.0)
+    # give the scalars structure: one RK4 step (CFL 0.5) from phi = 0
+    plan.step(st, ws, -0.5, 1)
+    plan.rhs(st, out, ws)
+    y = plan.get_state(st, 0).cpu().numpy().astype(np.complex128)
+    F = plan.get_state(out, 0).cpu().numpy().astype(np.complex128)
+    sp = plan.spectra(st, ws, 1)[0]
+    torch.cuda.synchronize()
+    del st, out, ws
+    torch.cuda.empty_cache()
+    return y, F, sp
+
+
+def test_sampled_modes_match_galerkin_oracle(bench_state):
+    y, F, _ = bench_state
+    K = ora.kmax_retained(N)
+    # nonlinear part of the GPU result: remove the viscous/diffusive term exactly
+    k2 = ora.k_squared(N)
+    L = np.stack([-d * k2 for d in PRM.diffusivities()])
+    Fnl = F - L * y
+    scale = np.max(np.abs(Fnl[:3])), np.max(np.abs(Fnl[3:]))
+    full = ora.full_spectrum_dict(y)
+    for k in [(1, 0, 0), (5, -7, 3), (40, 13, -22), (K, -K, K)]:
+        ref = ora.galerkin_mode(y, PRM, k, full)
+        got = ora.mode_value(Fnl, k)
+        print(f"[fullsize] mode {k}: max |gpu - galerkin| = {np.max(np.abs(got - ref)):.3e}", flush=True)
+        assert np.max(np.abs(got[:3] - ref[:3])) < 2e-5 * scale[0], (k, got[:3], ref[:3])
+        assert np.max(np.abs(got[3:] - ref[3:])) < 2e-5 * scale[1], (k, got[3:], ref[3:])
+
+
+def test_rhs_is_solenoidal(bench_state):
+    y, F, _ = bench_state
+    kx, ky, kz = ora.kgrid(N)
+    div = kx * F[0] + ky * F[1] + kz * F[2]
+    kmag = np.sqrt(ora.k_squared(N))
+    assert np.max(np.abs(div)) < 1e-5 * np.max(kmag * np.sqrt(np.sum(np.abs(F[:3]) ** 2, axis=0)))
+
+
+def test_energy_budget_at_full_size(bench_state):
+    y, F, sp = bench_state
+    w = ora.half_weights(N)
+    n6 = float(N) ** 6
+    dK = float(np.sum(w * np.real(np.conj(y[:3]) * F[:3]))) / n6
+    assert abs(dK - (PRM.power - sp["eps"])) < 1e-4 * (PRM.power + sp["eps"])
+
+
+def test_1024_fp32_single_realization_properties():
+    """1024^3 FP32, S = 1 (nu = 3e-4, Sc = 1, G = 1, CFL 0.5), all stages resident in HBM:
+    the right-hand side stays solenoidal and satisfies dK/dt = P - eps; two steps run
+    without non-finite or CFL flags."""
+    torch = torch_mod()
+    n, s = 1024, 1
+    prm = ora.Params(nu=3e-4, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1, k_force=2.0)
+    plan = make_plan(n, s, 32)
+    set_params(plan, 0, prm)
+    st, out, ws = plan.new_state(), plan.new_state(), plan.new_workspace()
+    plan.init_field(st, ws, 0, seed=4, k_peak=8.0, kinetic_energy=1.0)
+    plan.rhs(st, out, ws)
+    sp = plan.spectra(st, ws, 1)[0]
+    y = plan.get_state(st, 0)
+    F = plan.get_state(out, 0)
+    k1 = torch.arange(n, device="cuda", dtype=torch.float64)
+    k1 = torch.where(k1 <= n // 2, k1, k1 - n)
+    kx = torch.arange(n // 2 + 1, device="cuda", dtype=torch.float64)[None, None, :]
+    ky, kz = k1[None, :, None], k1[:, None, None]
+    w = torch.full((n // 2 + 1,), 2.0, device="cuda", dtype=torch.float64)
+    w[0] = 1.0
+    dK = 0.0
+    for c in range(3):
+        dK += float(torch.sum(w * torch.real(torch.conj(y[c].to(torch.complex128)) * F[c].to(torch.complex128))))
+    dK /= float(n) ** 6
+    assert abs(dK - (prm.power - sp["eps"])) < 1e-4 * (prm.power + sp["eps"]), (dK, prm.power - sp["eps"])
+    div = kx * F[0] + ky * F[1] + kz * F[2]
+    fmag = torch.sqrt(kx ** 2 + ky ** 2 + kz ** 2) * torch.sqrt(sum(torch.abs(F[c]) ** 2 for c in range(3)))
+    assert float(torch.max(torch.abs(div))) < 1e-5 * float(torch.max(fmag))
+    del y, F, div, fmag
+    plan.step(st, ws, -0.5, 2)
+    info = plan.read_step_info(ws)[0]
+    assert info["flags"] == 0 and info["steps"] == 2 and np.isfinite(info["max_u"])
+    torch.cuda.synchronize()
