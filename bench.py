@@ -45,12 +45,17 @@ def kernel_bytes(n: int, s: int, prec: int) -> dict:
         "y_forward": cs * (F * b_ + F * a_),
         # average over the four stages of the state traffic (3, 4, 4, 2 field-sized passes)
         "z_forward_update": cs * (F * a_ + 3.25 * F * hc),
+        # fused with the next stage's z inverse: no full y_stage write/read; state traffic
+        # (reads 1, 2, 2, 1; writes 1, 1, 1, 1) plus the inverse output
+        "z_forward_update_inverse": cs * (F * a_ + 2.5 * F * hc + FA * a_),
     }
 
 
 def step_bytes(n: int, s: int, prec: int) -> float:
+    """Algorithmic bytes of one RK4 step in the steady state of a multi-step call: every
+    stage ends with the fused z-forward/update/z-inverse pass."""
     kb = kernel_bytes(n, s, prec)
-    return 4.0 * sum(kb.values())
+    return 4.0 * (kb["y_inverse"] + kb["x_pass"] + kb["y_forward"] + kb["z_forward_update_inverse"])
 
 
 def run_gpu(n, s, prec, steps, warmup, seed=3):

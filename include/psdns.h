@@ -134,6 +134,14 @@ psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws,
 psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps,
                         void* hip_stream);
 
+/* Step through a captured HIP graph (off by default).  When enabled, psdns_step on a
+ * non-default stream captures the launches of one RK4 step the first time it sees a given
+ * (state, ws, dt) and then replays that graph once per step; a different state, workspace
+ * or dt re-captures.  Slot parameters and active flags are read by the kernels at replay
+ * time, so psdns_set_slot needs no re-capture.  Steps on the default (NULL) stream are
+ * launched directly.  Timing events are not recorded for replayed steps. */
+psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable);
+
 /* Copy the per-slot stepping records to host memory `out[batch]` (synchronises the stream). */
 psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_info* out, void* hip_stream);
 /* Reset t, steps and flags of every slot (asynchronous). */

@@ -122,7 +122,8 @@ Layout make_layout(const psdns_plan_params* p, int ex) {
   g.FA = 5 + 2 * g.S;
   g.FB = 6 + 3 * g.S;
   g.batch = p->batch;
-  g.st_field = (long long)g.M * g.M * g.PX;
+  const int Mp = (g.M + kStateZTile - 1) / kStateZTile * kStateZTile;
+  g.st_field = (long long)Mp * g.M * g.PX;
   g.a_field = (long long)g.N * g.M * g.PX;
   g.b_field = (long long)g.N * g.N * g.PX;
   g.nblk_x = (int)((long long)g.N * g.N / lines_per_xblock(g.N, ex));
@@ -155,8 +156,9 @@ Layout make_layout(const psdns_plan_params* p, int ex) {
   return L;
 }
 
-const char* kKernelNames[KID_COUNT] = {"forcing_amplitude", "z_inverse", "y_inverse", "x_pass",
-                                       "step_dt",           "y_forward", "z_forward_update", "aux"};
+const char* kKernelNames[KID_COUNT] = {"forcing_amplitude", "z_inverse",        "y_inverse",
+                                       "x_pass",            "step_dt",          "y_forward",
+                                       "z_forward_update",  "aux",              "z_forward_update_inverse"};
 
 struct EventTimer : Timer {
   struct Rec {
@@ -208,6 +210,12 @@ struct psdns_plan {
   EventTimer* timer = nullptr;
   double acc_ms[KID_COUNT] = {0};
   int acc_n[KID_COUNT] = {0};
+  // captured graph of one RK4 step (psdns_set_graph)
+  bool use_graph = false;
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_state = nullptr;
+  const void* graph_ws = nullptr;
+  double graph_dt = 0.0;
 };
 
 namespace {
@@ -333,6 +341,7 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
 
 psdns_status psdns_plan_destroy(psdns_plan* plan) {
   if (!plan) return PSDNS_OK;
+  if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
   delete plan->timer;
   if (plan->tw) hipFree(plan->tw);
   if (plan->slots_dev) hipFree(plan->slots_dev);
@@ -411,7 +420,7 @@ psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
-  plan->ops.rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, s);
+  plan->ops.rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, kStageZinv, s);
   HIP_TRY(hipGetLastError());
   return PSDNS_OK;
 }
@@ -424,12 +433,65 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
-  for (int n = 0; n < nsteps; ++n) {
+  // Every stage's last pass also inverts the next stage input along z (it is in its
+  // registers already), so only the first stage of a call runs the standalone z pass;
+  // the very last stage of a direct call skips the unneeded inverse.
+  auto one_step = [&](const Ctx& cx, bool first, bool last) {
     for (int stage = 0; stage < 4; ++stage) {
-      const void* sin = stage == 0 ? state : c.ystage;
-      plan->ops.rhs_stage(c, state, sin, stage, nullptr, stage == 0, dt, s);
+      const void* sin = stage == 0 ? state : cx.ystage;
+      int fl = kStageFuse;
+      if (first && stage == 0) fl |= kStageZinv;
+      if (last && stage == 3) fl &= ~kStageFuse;
+      plan->ops.rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
     }
+  };
+  if (plan->use_graph && s != nullptr && nsteps > 0) {
+    if (!plan->graph_exec || plan->graph_state != state || plan->graph_ws != ws || plan->graph_dt != dt) {
+      if (plan->graph_exec) {
+        HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
+        plan->graph_exec = nullptr;
+      }
+      Ctx cc = c;
+      cc.timer = nullptr;  // no event records inside a captured graph
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      one_step(cc, false, false);
+      hipGraph_t graph = nullptr;
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "kernel launch during graph capture");
+      }
+      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        plan->graph_exec = nullptr;
+        return hip_fail(ie, "hipGraphInstantiate");
+      }
+      plan->graph_state = state;
+      plan->graph_ws = ws;
+      plan->graph_dt = dt;
+    }
+    // the captured step expects the z inverse of y_n: run it once, then replay
+    plan->ops.rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
     HIP_TRY(hipGetLastError());
+    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
+    return PSDNS_OK;
+  }
+  for (int n = 0; n < nsteps; ++n) {
+    one_step(c, n == 0, n == nsteps - 1);
+    HIP_TRY(hipGetLastError());
+  }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable) {
+  if (psdns_status s = check_plan(plan)) return s;
+  plan->use_graph = enable != 0;
+  if (!plan->use_graph && plan->graph_exec) {
+    HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
+    plan->graph_exec = nullptr;
   }
   return PSDNS_OK;
 }

@@ -21,12 +21,34 @@ struct Geom {
   int FA;                 // fields after the z pass: 5 + 2S
   int FB;                 // fields after the y pass: 6 + 3S
   int batch;              // realizations (slots)
-  long long st_field;     // complex entries per field in the compact state: M*M*PX
-  long long a_field;      // per field after the z pass: N*M*PX   ([z][ky_c][kx])
+  long long st_field;     // complex entries per field in the compact state: Mp*M*PX (Mp = M rounded up to the kz tile)
+  long long a_field;      // per field after the z pass: N*M*PX   (rows at a_row(z, ky_c))
   long long b_field;      // per field after the y pass: N*N*PX   ([z][y][kx])
   int nblk_x;             // x-pass blocks per slot (partial maxima)
   int ns;                 // spectral shells 0 .. ns-1, ns = nint(sqrt(3) K) + 1
 };
+
+// Row placement of the compact state and of the arrays after the z pass.  TZ
+// consecutive kz (resp. z) rows of one ky row are stored contiguously, so the
+// z passes walk short strides while the y passes still see rows PX apart.
+#ifndef PSDNS_SZT
+#define PSDNS_SZT 1
+#endif
+#ifndef PSDNS_AZT
+#define PSDNS_AZT 1
+#endif
+constexpr int kStateZTile = PSDNS_SZT;
+constexpr int kAZTile = PSDNS_AZT;
+
+// offset (complex entries) of row (kz_c, ky_c) inside one state field
+__host__ __device__ inline long long st_row(int kzc, int kyc, int M, int PX) {
+  return ((long long)(kzc / kStateZTile) * M + kyc) * ((long long)kStateZTile * PX) +
+         (long long)(kzc % kStateZTile) * PX;
+}
+// offset of row (z, ky_c) inside one field after the z pass
+__host__ __device__ inline long long a_row(int z, int kyc, int M, int PX) {
+  return ((long long)(z / kAZTile) * M + kyc) * ((long long)kAZTile * PX) + (long long)(z % kAZTile) * PX;
+}
 
 // Static per-slot parameters, uploaded by psdns_set_slot.
 struct SlotDev {
@@ -60,8 +82,14 @@ enum KernelId {
   KID_YFWD,
   KID_ZFWD,
   KID_AUX,
+  KID_ZFWDI,
   KID_COUNT
 };
+
+// rhs_stage flags
+constexpr int kStageZinv = 1;  // run the standalone z inverse of the stage input first
+constexpr int kStageFuse = 2;  // the z-forward/update pass also inverts the next stage input
+constexpr int kStagePrologue = 4;  // only the standalone z inverse (before replaying fused steps)
 
 // Optional per-launch timing with HIP events (see psdns_set_timing).
 struct Timer {
@@ -93,7 +121,7 @@ struct Ops {
   // One evaluation of the nonlinear right-hand side at stage_in followed by the
   // stage update (stage 0..3) or, for stage < 0, the full dy/dt into rhs_out.
   void (*rhs_stage)(const Ctx&, void* state, const void* stage_in, int stage, void* rhs_out,
-                    int want_max, double dt_arg, hipStream_t);
+                    int want_max, double dt_arg, int flags, hipStream_t);
   void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, double energy,
                      hipStream_t);
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);

@@ -113,9 +113,8 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
   const T scale = T(1) / (T(N) * T(N) * T(N));
-  const long long rows = (long long)g.M * g.PX;  // stride between kz rows (state) and z rows (A)
-  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
-  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
+  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + kx;
+  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + kx;
 
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
@@ -125,14 +124,14 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kc = compact_of(j + TT * m, N, K, M);
-      a[m] = (valid && kc >= 0) ? scale * p[kc * rows] : czero<T>();
+      a[m] = (valid && kc >= 0) ? scale * p[st_row(kc, kyc, M, g.PX)] : czero<T>();
     }
   };
   auto store = [&](int f, cpx<T> (&v)[E]) {
     if (!valid) return;
     cpx<T>* p = out + (long long)f * g.a_field;
 #pragma unroll
-    for (int m = 0; m < E; ++m) p[(long long)(j + TT * m) * rows] = v[m];
+    for (int m = 0; m < E; ++m) p[a_row(j + TT * m, kyc, M, g.PX)] = v[m];
   };
   auto deriv = [&]() {
 #pragma unroll
@@ -189,11 +188,12 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   const int z = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)z * g.M * g.PX + kx;
-  cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
-
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
+  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX) + kx;
+  cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
+  const long long krow = (long long)kAZTile * g.PX;  // stride between ky rows at fixed z
+
   auto kyv = [&](int m) { return T(wave_of(j + TT * m, N)); };
   cpx<T> a[E], d[E];
   auto load = [&](int f, cpx<T> (&v)[E]) {
@@ -201,7 +201,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kc = compact_of(j + TT * m, N, K, M);
-      v[m] = (valid && kc >= 0) ? p[kc * g.PX] : czero<T>();
+      v[m] = (valid && kc >= 0) ? p[kc * krow] : czero<T>();
     }
   };
   auto store = [&](int f, cpx<T> (&v)[E]) {
@@ -552,10 +552,11 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   const int z = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  const cpx<T>* in = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
-  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)z * g.M * g.PX + kx;
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
+  const cpx<T>* in = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
+  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX) + kx;
+  const long long krow = (long long)kAZTile * g.PX;
   cpx<T> a[E];
   for (int f = 0; f < g.F; ++f) {
     const cpx<T>* p = in + (long long)f * g.b_field;
@@ -566,7 +567,7 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kc = compact_of(j + TT * m, N, K, M);
-      if (valid && kc >= 0) q[kc * g.PX] = a[m];
+      if (valid && kc >= 0) q[kc * krow] = a[m];
     }
   }
 }
@@ -585,46 +586,60 @@ struct StageArgs {
   int stage;
 };
 
+// Stage update of one mode.  Returns the input of the next stage (y_stage for
+// stages 0-2, y_{n+1} after stage 3); y_stage is stored only when write_ys.
 template <typename T>
-__device__ __forceinline__ void rk_update(const StageArgs<T>& a, long long o, cpx<T> F, double lk2, double h) {
+__device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long o, cpx<T> F, double lk2, double h,
+                                            bool write_ys = true) {
   // lk2 = D |k|^2; exponential factors in FP64, then cast
   if (a.stage < 0) {
     const cpx<T> y = a.sin[o];
     a.rhs[o] = F - T(lk2) * y;
-    return;
+    return czero<T>();
   }
   const double ehd = exp(-0.5 * lk2 * h);
   const T eh = T(ehd), e1 = T(ehd * ehd);
   const T th = T(h);
+  cpx<T> nxt;
   switch (a.stage) {
     case 0: {
       const cpx<T> y = a.yn[o];
       a.acc[o] = e1 * (y + (th / T(6)) * F);
-      a.ys[o] = eh * (y + (th / T(2)) * F);
+      nxt = eh * (y + (th / T(2)) * F);
       break;
     }
     case 1: {
       const cpx<T> y = a.yn[o];
       a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
-      a.ys[o] = eh * y + (th / T(2)) * F;
+      nxt = eh * y + (th / T(2)) * F;
       break;
     }
     case 2: {
       const cpx<T> y = a.yn[o];
       a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
-      a.ys[o] = e1 * y + (th * eh) * F;
+      nxt = e1 * y + (th * eh) * F;
       break;
     }
     default: {
-      a.yn[o] = a.acc[o] + (th / T(6)) * F;
-      break;
+      nxt = a.acc[o] + (th / T(6)) * F;
+      a.yn[o] = nxt;
+      return nxt;
     }
   }
+  if (write_ys) a.ys[o] = nxt;
+  return nxt;
 }
 
-template <int N, typename T>
+// FUSE: after the update, the next stage input (held in registers, in the same
+// strided kz ownership the inverse transform starts from) is transformed back
+// along z and written as the A fields of the next evaluation (the work of
+// k_z_inverse); y_stage is then stored only on the forced band, where the next
+// forcing amplitude and forcing term read it.  Fields go scalars first, in
+// reverse order, then velocity, so that no A field is overwritten before this
+// block has read its forward data.
+template <int N, typename T, bool FUSE>
 __global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
-k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
+k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
@@ -641,12 +656,12 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T
   const int kyc = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  const long long rows = (long long)g.M * g.PX;
-  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
-  const long long sbase = (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
+  cpx<T>* io = abuf + (long long)slot * g.FA * g.a_field + kx;
+  const long long sbase = (long long)slot * g.F * g.st_field + kx;
   const int ky = wave_of_compact(kyc, g.K, g.M);
   const double h = dyn[slot].dt;
   const double A = dyn[slot].A;
+  const T scale = T(1) / (T(N) * T(N) * T(N));
 
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
@@ -657,12 +672,54 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T
     return double(kxy2 + kz * kz);
   };
   auto load_fwd = [&](int f, cpx<T> (&v)[E]) {
-    const cpx<T>* p = in + (long long)f * g.a_field;
+    const cpx<T>* p = io + (long long)f * g.a_field;
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? p[(long long)(j + TT * m) * rows] : czero<T>();
+    for (int m = 0; m < E; ++m) v[m] = valid ? p[a_row(j + TT * m, kyc, M, g.PX)] : czero<T>();
     fft<N, E, false>(v, lds, j, tw);
   };
+  // inverse z of the next stage input (scaled by 1/N^3) into A field f, and of i kz * it into fd
+  auto inverse_out = [&](cpx<T> (&v)[E], int f, int fd) {
+    cpx<T> d[E];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      v[m] = scale * v[m];
+      d[m] = mul_is(v[m], T(wave_of(j + TT * m, N)));
+    }
+    fft<N, E, true>(v, lds, j, tw);
+    if (valid) {
+      cpx<T>* q = io + (long long)f * g.a_field;
+#pragma unroll
+      for (int m = 0; m < E; ++m) q[a_row(j + TT * m, kyc, M, g.PX)] = v[m];
+    }
+    if (fd >= 0) {
+      fft<N, E, true>(d, lds, j, tw);
+      if (valid) {
+        cpx<T>* q = io + (long long)fd * g.a_field;
+#pragma unroll
+        for (int m = 0; m < E; ++m) q[a_row(j + TT * m, kyc, M, g.PX)] = d[m];
+      }
+    }
+  };
 
+  // scalars: F = -a_hat (a already holds u.grad phi + g.u)
+  for (int s = g.S - 1; s >= 0; --s) {
+    cpx<T> a[E];
+    load_fwd(3 + s, a);
+    const double dif = sp.diff[3 + s];
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int kcm_ = kcm(m);
+      cpx<T> nxt = czero<T>();
+      if (kcm_ >= 0) {
+        const double k2m_ = k2m(m);
+        const long long o = sbase + (long long)(3 + s) * g.st_field + st_row(kcm_, kyc, M, g.PX);
+        const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
+        nxt = rk_update(sa, o, F, dif * k2m_, h, !FUSE);
+      }
+      a[m] = nxt;
+    }
+    if constexpr (FUSE) inverse_out(a, 5 + 2 * s, 6 + 2 * s);
+  }
   // velocity: F = P(k) c_hat + A 1_band u_hat
   {
     cpx<T> c1[E], c2[E], c3[E];
@@ -673,46 +730,43 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kcm_ = kcm(m);
-      if (kcm_ < 0) continue;
-      const double k2m_ = k2m(m);
-      const int n = j + TT * m;
-      const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
-      const long long o = sbase + (long long)kcm_ * rows;
-      cpx<T> F1, F2, F3;
-      if (k2m_ == 0.0) {
-        F1 = F2 = F3 = czero<T>();
-      } else {
-        const T ik2 = T(1.0 / k2m_);
-        const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
-        F1 = c1[m] - (kxt * ik2) * kdc;
-        F2 = c2[m] - (kyt * ik2) * kdc;
-        F3 = c3[m] - (kzt * ik2) * kdc;
-        if (A != 0.0 && k2m_ <= sp.kf2) {
-          const T At = T(A);
-          F1 = F1 + At * sa.sin[o];
-          F2 = F2 + At * sa.sin[o + g.st_field];
-          F3 = F3 + At * sa.sin[o + 2 * g.st_field];
+      cpx<T> n1 = czero<T>(), n2 = czero<T>(), n3 = czero<T>();
+      if (kcm_ >= 0) {
+        const double k2m_ = k2m(m);
+        const int n = j + TT * m;
+        const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
+        const long long o = sbase + st_row(kcm_, kyc, M, g.PX);
+        cpx<T> F1, F2, F3;
+        const bool band = k2m_ > 0.0 && k2m_ <= sp.kf2;
+        if (k2m_ == 0.0) {
+          F1 = F2 = F3 = czero<T>();
+        } else {
+          const T ik2 = T(1.0 / k2m_);
+          const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
+          F1 = c1[m] - (kxt * ik2) * kdc;
+          F2 = c2[m] - (kyt * ik2) * kdc;
+          F3 = c3[m] - (kzt * ik2) * kdc;
+          if (A != 0.0 && band) {
+            const T At = T(A);
+            F1 = F1 + At * sa.sin[o];
+            F2 = F2 + At * sa.sin[o + g.st_field];
+            F3 = F3 + At * sa.sin[o + 2 * g.st_field];
+          }
         }
+        const double lk2 = nu * k2m_;
+        const bool wys = !FUSE || band;
+        n1 = rk_update(sa, o, F1, lk2, h, wys);
+        n2 = rk_update(sa, o + g.st_field, F2, lk2, h, wys);
+        n3 = rk_update(sa, o + 2 * g.st_field, F3, lk2, h, wys);
       }
-      const double lk2 = nu * k2m_;
-      rk_update(sa, o, F1, lk2, h);
-      rk_update(sa, o + g.st_field, F2, lk2, h);
-      rk_update(sa, o + 2 * g.st_field, F3, lk2, h);
+      c1[m] = n1;
+      c2[m] = n2;
+      c3[m] = n3;
     }
-  }
-  // scalars: F = -a_hat (a already holds u.grad phi + g.u)
-  for (int s = 0; s < g.S; ++s) {
-    cpx<T> a[E];
-    load_fwd(3 + s, a);
-    const double dif = sp.diff[3 + s];
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int kcm_ = kcm(m);
-      if (kcm_ < 0) continue;
-      const double k2m_ = k2m(m);
-      const long long o = sbase + (long long)(3 + s) * g.st_field + (long long)kcm_ * rows;
-      const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
-      rk_update(sa, o, F, dif * k2m_, h);
+    if constexpr (FUSE) {
+      inverse_out(c1, 0, 3);
+      inverse_out(c2, 1, 4);
+      inverse_out(c3, 2, -1);
     }
   }
 }
@@ -743,7 +797,7 @@ k_forcing_amplitude(const cpx<T>* __restrict__ sin, const SlotDev* __restrict__ 
     if (k2 == 0.0 || k2 > sp.kf2) continue;
     const int kyc = ky >= 0 ? ky : ky + g.M;
     const int kzc = kz >= 0 ? kz : kz + g.M;
-    const long long o = ((long long)kzc * g.M + kyc) * g.PX + kx;
+    const long long o = st_row(kzc, kyc, g.M, g.PX) + kx;
     double s = 0.0;
     for (int f = 0; f < 3; ++f) {
       const cpx<T> v = base[o + f * g.st_field];
@@ -922,7 +976,7 @@ k_init_write(cpx<T>* __restrict__ st, Geom g, int slot, uint64_t seed, double kp
   double re[3], im[3];
   init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, re, im);
   const double sc = d->scratch;
-  const long long o = ((long long)kzc * g.M + kyc) * g.PX + kx;
+  const long long o = st_row(kzc, kyc, g.M, g.PX) + kx;
   cpx<T>* base = st + (long long)slot * g.F * g.st_field;
   for (int c = 0; c < 3; ++c) base[o + c * g.st_field] = {T(sc * re[c]), T(sc * im[c])};
   for (int s = 0; s < g.S; ++s) base[o + (3 + s) * g.st_field] = czero<T>();
@@ -953,7 +1007,7 @@ k_convert(cpx<T>* __restrict__ st, cpx<T>* __restrict__ canon, Geom g, int slot)
   const int iz = (wave_of_compact(kzc, g.K, g.M) + N) % N;
   const long long oc = (((long long)f * N + iz) * N + iy) * NX + kx;
   const long long os = (long long)slot * g.F * g.st_field + (long long)f * g.st_field +
-                       ((long long)kzc * g.M + kyc) * g.PX + kx;
+                       st_row(kzc, kyc, g.M, g.PX) + kx;
   if (TO_CANON)
     canon[oc] = st[os];
   else
@@ -1003,7 +1057,7 @@ k_shell_sums(const cpx<T>* __restrict__ st, const SlotDev* __restrict__ slots, G
     int x1 = isqrt_floor(hi - r2);
     if (x1 > K) x1 = K;
     const int kzc = kz >= 0 ? kz : kz + M, kyc = ky >= 0 ? ky : ky + M;
-    const long long row = ((long long)kzc * M + kyc) * g.PX;
+    const long long row = st_row(kzc, kyc, M, g.PX);
     for (int kx = x0; kx <= x1; ++kx) {
       const long long o = row + kx;
       const double w = kx == 0 ? 1.0 : 2.0;
@@ -1065,9 +1119,8 @@ k_stats_z(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>
   const int ky = wave_of_compact(kyc, K, M);
   const LdsCol<T, W> lds{smem + c};
   const T scale = T(1) / (T(N) * T(N) * T(N));
-  const long long rows = (long long)M * g.PX;
-  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + (long long)kyc * g.PX + kx;
-  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + (long long)kyc * g.PX + kx;
+  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + kx;
+  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + kx;
   cpx<T> a[E];
   for (int f = 0; f < spec.nf; ++f) {
     const cpx<T>* p = in + (long long)spec.field[f] * g.st_field;
@@ -1075,7 +1128,7 @@ k_stats_z(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kc = compact_of(j + TT * m, N, K, M);
-      cpx<T> v = (valid && kc >= 0) ? scale * p[kc * rows] : czero<T>();
+      cpx<T> v = (valid && kc >= 0) ? scale * p[st_row(kc, kyc, M, g.PX)] : czero<T>();
       const T kk = ax == 1 ? T(kx) : ax == 2 ? T(ky) : T(wave_of(j + TT * m, N));
       a[m] = ax == 0 ? v : mul_is(v, kk);
     }
@@ -1083,7 +1136,7 @@ k_stats_z(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>
     if (valid) {
       cpx<T>* q = out + (long long)f * g.a_field;
 #pragma unroll
-      for (int m = 0; m < E; ++m) q[(long long)(j + TT * m) * rows] = a[m];
+      for (int m = 0; m < E; ++m) q[a_row(j + TT * m, kyc, M, g.PX)] = a[m];
     }
   }
 }
@@ -1105,7 +1158,8 @@ k_stats_y(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<
   const int kx = blockIdx.x * W + c, z = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + (long long)z * M * g.PX + kx;
+  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX) + kx;
+  const long long krow = (long long)kAZTile * g.PX;
   cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
   cpx<T> a[E];
   for (int f = 0; f < nf; ++f) {
@@ -1113,7 +1167,7 @@ k_stats_y(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kc = compact_of(j + TT * m, N, K, M);
-      a[m] = (valid && kc >= 0) ? p[kc * g.PX] : czero<T>();
+      a[m] = (valid && kc >= 0) ? p[kc * krow] : czero<T>();
     }
     fft<N, E, true>(a, lds, j, tw);
     if (valid) {
@@ -1329,22 +1383,25 @@ template <int N, typename T>
 struct Engine {
   using C = Cfg<N, T>;
 
+  // flags: kStageZinv launches the standalone z inverse of stage_in first; kStageFuse makes
+  // the last pass also produce the z-inverse of the next stage input.
   static void rhs_stage(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
-                        double dt_arg, hipStream_t s) {
+                        double dt_arg, int flags, hipStream_t s) {
     const Geom& g = x.g;
     const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
     const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
     cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
     cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
     const int ntile = (g.KX + C::W - 1) / C::W;
-    {
+    if (!(flags & kStagePrologue)) {
       TimedLaunch tl(x.timer, KID_FORCE, s);
       k_forcing_amplitude<T><<<g.batch, 256, 0, s>>>(sin, x.slots, x.dyn, g);
     }
-    {
+    if (flags & kStageZinv) {
       TimedLaunch tl(x.timer, KID_ZINV, s);
       k_z_inverse<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(sin, A, tw, x.slots, g);
     }
+    if (flags & kStagePrologue) return;
     {
       TimedLaunch tl(x.timer, KID_YINV, s);
       k_y_inverse<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, x.slots, g);
@@ -1368,9 +1425,14 @@ struct Engine {
     sa.sin = sin;
     sa.rhs = static_cast<cpx<T>*>(rhs_out);
     sa.stage = stage;
-    {
+    if (flags & kStageFuse) {
+      TimedLaunch tl(x.timer, KID_ZFWDI, s);
+      k_z_forward_update<N, T, true>
+          <<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+    } else {
       TimedLaunch tl(x.timer, KID_ZFWD, s);
-      k_z_forward_update<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+      k_z_forward_update<N, T, false>
+          <<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     }
   }
 

@@ -74,6 +74,7 @@ _SIGS = {
     "psdns_get_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
+    "psdns_set_graph": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_set_timing": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_get_timing": (ctypes.c_int, [_c_void_p, ctypes.POINTER(KernelTiming), _c_int32,
                                         ctypes.POINTER(_c_int32)]),
@@ -241,6 +242,10 @@ class Plan:
         """Per-slot dicts of shell spectra and statistics (copies to the host)."""
         raw = self.spectra_raw(state, ws, flags).cpu().numpy()
         return [parse_spectra(r, int(self.info.n_shells), self.n_scalars) for r in raw]
+
+    def set_graph(self, enable: bool) -> None:
+        """Replay RK4 steps from a captured HIP graph (non-default streams only)."""
+        _check(lib().psdns_set_graph(self._h, 1 if enable else 0))
 
     def set_timing(self, enable: bool) -> None:
         _check(lib().psdns_set_timing(self._h, 1 if enable else 0))

@@ -1,0 +1,66 @@
+"""Serving loop: every request's result is the same alone and inside a mixed,
+continuously batched workload; admission respects the HBM budget; slots are reused."""
+import copy
+
+import numpy as np
+import pytest
+
+from paper_2012_04838_amd import psdns
+from paper_2012_04838_amd.serve import Request, Server, make_mix, summarize, viscosity_for
+from tests.gpu_helpers import torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def test_result_same_alone_and_in_mix():
+    torch = torch_mod()
+    mix = make_mix(14, rate=200.0, seed=3, sizes=(32, 64), weights=(0.5, 0.5), steps=(3, 12), scalars=(0, 1, 2))
+    picked = [0, 5, 9, 13]
+    for i in picked:
+        mix[i].keep_state = True
+    srv = Server(capacity=lambda n: 3)  # small groups force slot reuse and waiting
+    done = srv.run(copy.deepcopy(mix))
+    srv.close()
+    assert len(done) == len(mix)
+    by_id = {r.rid: r for r in done}
+    for i in picked:
+        alone = copy.deepcopy(mix[i])
+        alone.arrival = 0.0
+        s2 = Server(capacity=lambda n: 1)
+        res = s2.run([alone])[0]
+        s2.close()
+        a, b = res.state, by_id[i].state
+        assert a is not None and b is not None
+        assert np.array_equal(a, b), (i, np.max(np.abs(a - b)))
+        assert res.spectra["K"] == by_id[i].spectra["K"]
+    torch.cuda.synchronize()
+
+
+def test_admission_respects_budget_and_reuses_slots():
+    torch = torch_mod()
+    per = psdns.state_bytes(64, 1, 32, 2) + psdns.workspace_bytes(64, 1, 32, 2)
+    reqs = [Request(rid=i, n=64, n_scalars=1, steps=4, seed=10 + i, nu=viscosity_for(64)) for i in range(5)]
+    srv = Server(hbm_budget=int(1.5 * per), capacity=lambda n: 2)
+    done = srv.run(reqs)
+    assert len(done) == 5
+    assert len(srv.groups) == 1 and srv.reserved() <= srv.budget
+    # with two slots, at most two requests were ever admitted before the first finished
+    admits = sorted(r.t_admit for r in done)
+    finishes = sorted(r.t_done for r in done)
+    assert admits[2] >= finishes[0]
+    # a request that cannot fit the budget waits instead of over-committing
+    big = Request(rid=99, n=128, n_scalars=0, steps=1, seed=1, nu=viscosity_for(128))
+    srv.waiting.append(big)
+    srv._admit()
+    assert big in srv.waiting and (128, 0) not in srv.groups
+    srv.close()
+    s = summarize(done, 1.0, srv.steps_done)
+    assert s["p99_s"] >= s["p50_s"] > 0
+    torch.cuda.synchronize()
+
+
+def test_viscosity_for_matches_kmax_eta():
+    for n in (64, 128, 256, 512):
+        nu = viscosity_for(n)
+        eta = (nu ** 3 / 0.1) ** 0.25
+        assert abs(eta * n / 3.0 - 1.5) < 1e-12
