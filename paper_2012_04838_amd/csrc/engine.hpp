@@ -54,19 +54,37 @@ namespace psdns {
 #define PSDNS_COL_MAXT 1024
 #endif
 
-template <int N, typename T>
-struct Cfg {
-  // columns per block: one row segment of PSDNS_COL_BYTES bytes of complex values
+// elements per thread of the fused z-forward/update/z-inverse pass
+#ifndef PSDNS_EF32
+#define PSDNS_EF32 8
+#endif
+#ifndef PSDNS_EF64
+#define PSDNS_EF64 8
+#endif
+
+// Geometry of a column pass: W columns (one row segment of PSDNS_COL_BYTES bytes)
+// per block, TC = N/EC threads per column, EC elements per thread.
+template <int N, typename T, int E_REQ>
+struct ColCfg {
   static constexpr int W = PSDNS_COL_BYTES / (int)sizeof(cpx<T>);
-  // elements per thread of the column passes (z, y) and of the x pass
-  static constexpr int EC0 = sizeof(T) == 4 ? PSDNS_EC32 : PSDNS_EC64;
-  // at least N * W / 1024 elements per thread, so a block stays within 1024 threads
-  static constexpr int EC1 = EC0 * PSDNS_COL_MAXT < N * W ? N * W / PSDNS_COL_MAXT : EC0;
+  // at least N * W / PSDNS_COL_MAXT elements per thread, so a block stays within the cap
+  static constexpr int EC1 = E_REQ * PSDNS_COL_MAXT < N * W ? N * W / PSDNS_COL_MAXT : E_REQ;
   static constexpr int EC = N < EC1 ? N : EC1;
   static constexpr int TC = N / EC;
-  static constexpr int COL_THREADS = W * TC;
-  static_assert(COL_THREADS <= 1024, "column block too large");
+  static constexpr int THREADS = W * TC;
+  static_assert(THREADS <= 1024, "column block too large");
   static_assert((W * N + N) * sizeof(cpx<T>) <= 160 * 1024, "column pass LDS exceeds 160 KB");
+};
+
+template <int N, typename T>
+struct Cfg {
+  using Col = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EC32 : PSDNS_EC64>;
+  using Fused = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EF32 : PSDNS_EF64>;
+  // columns per block and elements per thread of the column passes (z, y)
+  static constexpr int W = Col::W;
+  static constexpr int EC = Col::EC;
+  static constexpr int TC = Col::TC;
+  static constexpr int COL_THREADS = Col::THREADS;
   // x pass: a line never spans two wavefronts (TX <= 64)
   static constexpr int EX0 = N > 512 ? N / 64 : 8;
   static constexpr int EX = N < EX0 ? N : EX0;
@@ -366,7 +384,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   const int lane = threadIdx.x & 63;
   const int partner = (lane - j) + ((TT - j) & (TT - 1));
   const long long line = (long long)blockIdx.x * L + li;  // z * N + y
-  const LdsLine<T> lds{smem + li * LP};
+  const LdsLine<T, N, E> lds{smem + li * LP};
   cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
 
   const XLine<N, T> xl(threadIdx.x);
@@ -638,10 +656,10 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long o, 
 // reverse order, then velocity, so that no A field is overwritten before this
 // block has read its forward data.
 template <int N, typename T, bool FUSE>
-__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+__global__ void PSDNS_COL_BOUNDS(std::conditional_t<FUSE, typename Cfg<N, T>::Fused, typename Cfg<N, T>::Col>::THREADS)
 k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
-  using C = Cfg<N, T>;
+  using C = std::conditional_t<FUSE, typename Cfg<N, T>::Fused, typename Cfg<N, T>::Col>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   __shared__ cpx<T> smem[W * N];
   __shared__ cpx<T> stw[N];
@@ -1197,7 +1215,7 @@ k_x_moments(const cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, Ge
   const cpx<T>* tw = stw;
   const XL xl(threadIdx.x);
   const int li = threadIdx.x / TT, j = xl.j;
-  const LdsLine<T> lds{smem + li * LP};
+  const LdsLine<T, N, E> lds{smem + li * LP};
   double mom[6][3];
 #pragma unroll
   for (int f = 0; f < 6; ++f) mom[f][0] = mom[f][1] = mom[f][2] = 0.0;
@@ -1428,7 +1446,7 @@ struct Engine {
     if (flags & kStageFuse) {
       TimedLaunch tl(x.timer, KID_ZFWDI, s);
       k_z_forward_update<N, T, true>
-          <<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+          <<<dim3(ntile, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     } else {
       TimedLaunch tl(x.timer, KID_ZFWD, s);
       k_z_forward_update<N, T, false>

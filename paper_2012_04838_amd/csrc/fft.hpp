@@ -132,11 +132,16 @@ struct LdsCol {
   __device__ __forceinline__ void st(int p, cpx<T> v) const { base[p * W] = v; }
   __device__ __forceinline__ cpx<T> ld(int p) const { return base[p * W]; }
 };
-// Contiguous line: one padding element after every 16 breaks the radix-16 bank stride.
-template <typename T>
+// Contiguous line (one line per E-element lane group): element p is stored at
+// p ^ ((p >> log2 E) & min(31, N-1)).  The XOR swizzle keeps the Stockham writes
+// (stride E between lanes in the first stage, runs of E lanes later) and the
+// strided reads free of LDS bank conflicts for 32 and 64 banks of 4 bytes.
+template <typename T, int N, int E>
 struct LdsLine {
   cpx<T>* base;
-  static __device__ __forceinline__ int idx(int p) { return p + (p >> 4); }
+  static constexpr int kShift = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : E == 8 ? 3 : E == 16 ? 4 : E == 32 ? 5 : 6;
+  static constexpr int kMask = N - 1 < 31 ? N - 1 : 31;
+  static __device__ __forceinline__ int idx(int p) { return p ^ ((p >> kShift) & kMask); }
   __device__ __forceinline__ void st(int p, cpx<T> v) const { base[idx(p)] = v; }
   __device__ __forceinline__ cpx<T> ld(int p) const { return base[idx(p)]; }
 };
