@@ -117,6 +117,37 @@ def copy_reference(gbytes: float, reps: int = 5):
     return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9}
 
 
+def serve_mix(n_requests: int, load: float, seed: int = 0):
+    """Serving mix: Poisson arrivals of seeded DNS requests, N^3 in {64,128,256,512} with
+    weights 0.4/0.3/0.2/0.1, 0-2 scalars, 10-200 RK4 steps, nu from kmax*eta = 1.5, FP32,
+    continuous batching (paper_2012_04838_amd.serve).  The saturated capacity is measured
+    first with every request present at t = 0; the timed run offers `load` of it."""
+    import torch
+
+    from paper_2012_04838_amd import serve
+
+    sat = serve.make_mix(n_requests, 0.0, seed)
+    srv = serve.Server()
+    t = time.perf_counter()
+    srv.run(sat)
+    cap_wall = time.perf_counter() - t
+    cap = len(sat) / cap_wall
+    sat_rate = srv.steps_done / cap_wall
+    srv.close()
+    torch.cuda.empty_cache()
+    mix = serve.make_mix(n_requests, load * cap, seed)
+    srv = serve.Server()
+    t = time.perf_counter()
+    done = srv.run(mix)
+    res = serve.summarize(done, time.perf_counter() - t, srv.steps_done)
+    srv.close()
+    torch.cuda.empty_cache()
+    res.update(load=load, saturated_requests_per_s=cap, saturated_N3_steps_per_s=sat_rate,
+               workload="N^3 in {64,128,256,512} w 0.4/0.3/0.2/0.1, S in {0,1,2}, 10-200 steps, FP32, CFL 0.5, "
+                        "k_p = 4, nu: kmax*eta = 1.5, seeds 1000+i")
+    return res
+
+
 def cpu_baseline(n, s):
     """One oracle right-hand-side evaluation at the benchmark size (a quarter of an RK4
     step; the integrating-factor update adds well under 5%), scaled to steps/s."""
@@ -144,6 +175,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-gb", type=float, default=1.0,
                     help="size of the copy-bandwidth reference (0 disables)")
+    ap.add_argument("--serve-requests", type=int, default=40,
+                    help="requests of the serving mix (Poisson arrivals at --serve-load of the measured "
+                         "saturated capacity); 0 disables")
+    ap.add_argument("--serve-load", type=float, default=0.7)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -212,6 +247,10 @@ def main():
         out["kernels_fp64"] = {k: {"launches": t64[k][0], "avg_ms": t64[k][1] / max(t64[k][0], 1),
                                    "alg_GBs": (kb64[k] / (t64[k][1] / t64[k][0] * 1e-3) / 1e9)
                                    if k in kb64 and t64[k][0] else None} for k in t64 if t64[k][0]}
+    if args.serve_requests > 0:
+        out["serve"] = serve_mix(args.serve_requests, args.serve_load)
+        print(f"[bench] serve done: p50 {out['serve']['p50_s']:.3f} s p99 {out['serve']['p99_s']:.3f} s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(n, s)
     print(json.dumps(out), flush=True)

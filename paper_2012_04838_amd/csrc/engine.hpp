@@ -34,7 +34,7 @@ namespace psdns {
 #define PSDNS_COL_WAVES 0
 #endif
 #ifndef PSDNS_X_WAVES
-#define PSDNS_X_WAVES 0
+#define PSDNS_X_WAVES 2
 #endif
 #if PSDNS_COL_WAVES > 0
 #define PSDNS_COL_BOUNDS(...) __launch_bounds__((__VA_ARGS__), PSDNS_COL_WAVES)
