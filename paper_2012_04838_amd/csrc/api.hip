@@ -61,6 +61,16 @@ bool valid_params(const psdns_plan_params* p, std::string* why) {
     *why = "precision must be 32 or 64, got " + std::to_string(p->precision);
     return false;
   }
+  {
+    // the column passes address one field (one z plane for the y-pass arrays) with
+    // 32-bit byte offsets from a per-field buffer base
+    const long long k = (n - 1) / 3, m = 2 * k + 1, px = (k + 1 + 15) / 16 * 16;
+    const double field_bytes = (double)n * m * px * (p->precision == 32 ? 8 : 16);
+    if (field_bytes >= 4294967296.0) {
+      *why = "one transposed field would exceed 4 GiB";
+      return false;
+    }
+  }
   if (p->batch < 1 || p->batch > 65535) {
     *why = "batch must be in [1, 65535], got " + std::to_string(p->batch);
     return false;
@@ -122,8 +132,7 @@ Layout make_layout(const psdns_plan_params* p, int ex) {
   g.FA = 5 + 2 * g.S;
   g.FB = 6 + 3 * g.S;
   g.batch = p->batch;
-  const int Mp = (g.M + kStateZTile - 1) / kStateZTile * kStateZTile;
-  g.st_field = (long long)Mp * g.M * g.PX;
+  g.st_field = (long long)g.M * g.M * g.PX;
   g.a_field = (long long)g.N * g.M * g.PX;
   g.b_field = (long long)g.N * g.N * g.PX;
   g.nblk_x = (int)((long long)g.N * g.N / lines_per_xblock(g.N, ex));

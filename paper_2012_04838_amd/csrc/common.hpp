@@ -21,34 +21,19 @@ struct Geom {
   int FA;                 // fields after the z pass: 5 + 2S
   int FB;                 // fields after the y pass: 6 + 3S
   int batch;              // realizations (slots)
-  long long st_field;     // complex entries per field in the compact state: Mp*M*PX (Mp = M rounded up to the kz tile)
+  long long st_field;     // complex entries per field in the compact state: M*M*PX
   long long a_field;      // per field after the z pass: N*M*PX   (rows at a_row(z, ky_c))
   long long b_field;      // per field after the y pass: N*N*PX   ([z][y][kx])
   int nblk_x;             // x-pass blocks per slot (partial maxima)
   int ns;                 // spectral shells 0 .. ns-1, ns = nint(sqrt(3) K) + 1
 };
 
-// Row placement of the compact state and of the arrays after the z pass.  TZ
-// consecutive kz (resp. z) rows of one ky row are stored contiguously, so the
-// z passes walk short strides while the y passes still see rows PX apart.
-#ifndef PSDNS_SZT
-#define PSDNS_SZT 1
-#endif
-#ifndef PSDNS_AZT
-#define PSDNS_AZT 1
-#endif
-constexpr int kStateZTile = PSDNS_SZT;
-constexpr int kAZTile = PSDNS_AZT;
-
-// offset (complex entries) of row (kz_c, ky_c) inside one state field
+// Row placement: row (kz_c, ky_c) of a state field and row (z, ky_c) of a field
+// after the z pass both sit at (z M + ky_c) PX, so the two share their strides.
 __host__ __device__ inline long long st_row(int kzc, int kyc, int M, int PX) {
-  return ((long long)(kzc / kStateZTile) * M + kyc) * ((long long)kStateZTile * PX) +
-         (long long)(kzc % kStateZTile) * PX;
+  return ((long long)kzc * M + kyc) * PX;
 }
-// offset of row (z, ky_c) inside one field after the z pass
-__host__ __device__ inline long long a_row(int z, int kyc, int M, int PX) {
-  return ((long long)(z / kAZTile) * M + kyc) * ((long long)kAZTile * PX) + (long long)(z % kAZTile) * PX;
-}
+__host__ __device__ inline long long a_row(int z, int kyc, int M, int PX) { return ((long long)z * M + kyc) * PX; }
 
 // Static per-slot parameters, uploaded by psdns_set_slot.
 struct SlotDev {

@@ -19,6 +19,7 @@
 
 #include "common.hpp"
 #include "fft.hpp"
+#include "mem.hpp"
 
 namespace psdns {
 
@@ -62,11 +63,19 @@ namespace psdns {
 #define PSDNS_EF64 8
 #endif
 
-// Geometry of a column pass: W columns (one row segment of PSDNS_COL_BYTES bytes)
-// per block, TC = N/EC threads per column, EC elements per thread.
-template <int N, typename T, int E_REQ>
+// row segment of the z-forward/update pass (both variants), in bytes
+#ifndef PSDNS_FB32
+#define PSDNS_FB32 PSDNS_COL_BYTES
+#endif
+#ifndef PSDNS_FB64
+#define PSDNS_FB64 PSDNS_COL_BYTES
+#endif
+
+// Geometry of a column pass: W columns (one row segment of BYTES bytes) per block,
+// TC = N/EC threads per column, EC elements per thread.
+template <int N, typename T, int E_REQ, int BYTES = PSDNS_COL_BYTES>
 struct ColCfg {
-  static constexpr int W = PSDNS_COL_BYTES / (int)sizeof(cpx<T>);
+  static constexpr int W = BYTES / (int)sizeof(cpx<T>);
   // at least N * W / PSDNS_COL_MAXT elements per thread, so a block stays within the cap
   static constexpr int EC1 = E_REQ * PSDNS_COL_MAXT < N * W ? N * W / PSDNS_COL_MAXT : E_REQ;
   static constexpr int EC = N < EC1 ? N : EC1;
@@ -79,7 +88,7 @@ struct ColCfg {
 template <int N, typename T>
 struct Cfg {
   using Col = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EC32 : PSDNS_EC64>;
-  using Fused = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EF32 : PSDNS_EF64>;
+  using Fused = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EF32 : PSDNS_EF64, sizeof(T) == 4 ? PSDNS_FB32 : PSDNS_FB64>;
   // columns per block and elements per thread of the column passes (z, y)
   static constexpr int W = Col::W;
   static constexpr int EC = Col::EC;
@@ -111,6 +120,7 @@ __device__ __forceinline__ cpx<T> czero() { return {T(0), T(0)}; }
 // z inverse: columns along kz at fixed (ky, kx-tile).
 // A fields: 0 U1, 1 U2, 2 U3, 3 dz U1, 4 dz U2, 5+2s Phi_s, 6+2s dz Phi_s
 // (all carry the 1/N^3 of Eq. (5) so that physical values are the true ones).
+// The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
 template <int N, typename T>
 __global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
@@ -118,6 +128,9 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  constexpr uint32_t CS = sizeof(cpx<T>);
   __shared__ cpx<T> smem[W * N];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
@@ -131,55 +144,58 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
   const T scale = T(1) / (T(N) * T(N) * T(N));
-  const cpx<T>* in = st + (long long)slot * g.F * g.st_field + kx;
-  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + kx;
+  // state rows (kz_c, ky_c) and A rows (z, ky_c) are both M PX entries apart along z
+  const uint32_t rsb = (uint32_t)M * g.PX * CS;
+  const uint32_t voff = ((uint32_t)j * M * g.PX + (uint32_t)kyc * g.PX + (uint32_t)kx) * CS;
+  const cpx<T>* sslot = st + (long long)slot * g.F * g.st_field;
+  cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
 
-  constexpr int K = (N - 1) / 3;
-  constexpr int M = 2 * K + 1;
-  cpx<T> a[E], d[E];
-  auto load = [&](int f) {
-    const cpx<T>* p = in + (long long)f * g.st_field;
+  auto load = [&](int f, cpx<T> (&v)[E]) {
+    const Buf<T> b = make_buf<T>(sslot + (long long)f * g.st_field);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int kc = compact_of(j + TT * m, N, K, M);
-      a[m] = (valid && kc >= 0) ? scale * p[st_row(kc, kyc, M, g.PX)] : czero<T>();
+      uint32_t vo, so;
+      v[m] = (valid && compact_at<N, TT>(m, j, voff, rsb, vo, so)) ? bload(b, vo, so) : czero<T>();
     }
   };
-  auto store = [&](int f, cpx<T> (&v)[E]) {
+  auto store = [&](int f, const cpx<T> (&v)[E]) {
     if (!valid) return;
-    cpx<T>* p = out + (long long)f * g.a_field;
+    const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) p[a_row(j + TT * m, kyc, M, g.PX)] = v[m];
+    for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
-  auto deriv = [&]() {
+  cpx<T> a[E], d[E], nx[E];
+  // transform the field held in a (and its z derivative into fd when fd >= 0)
+  auto emit = [&](int f, int fd) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], T(wave_of(j + TT * m, N)));
-  };
-  // u1 and dz u1
-  load(0);
-  deriv();
-  fft<N, E, true>(a, lds, j, tw);
-  store(0, a);
-  fft<N, E, true>(d, lds, j, tw);
-  store(3, d);
-  // u2 and dz u2
-  load(1);
-  deriv();
-  fft<N, E, true>(a, lds, j, tw);
-  store(1, a);
-  fft<N, E, true>(d, lds, j, tw);
-  store(4, d);
-  // u3
-  load(2);
-  fft<N, E, true>(a, lds, j, tw);
-  store(2, a);
-  for (int s = 0; s < g.S; ++s) {
-    load(3 + s);
-    deriv();
+    for (int m = 0; m < E; ++m) {
+      a[m] = scale * a[m];
+      if (fd >= 0) d[m] = mul_is(a[m], T(wave_of(j + TT * m, N)));
+    }
     fft<N, E, true>(a, lds, j, tw);
-    store(5 + 2 * s, a);
-    fft<N, E, true>(d, lds, j, tw);
-    store(6 + 2 * s, d);
+    store(f, a);
+    if (fd >= 0) {
+      fft<N, E, true>(d, lds, j, tw);
+      store(fd, d);
+    }
+  };
+  auto take = [&]() {
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = nx[m];
+  };
+  load(0, a);
+  load(1, nx);
+  emit(0, 3);  // u1, dz u1
+  take();
+  load(2, nx);
+  emit(1, 4);  // u2, dz u2
+  take();
+  if (g.S > 0) load(3, nx);
+  emit(2, -1);  // u3
+  for (int s = 0; s < g.S; ++s) {
+    take();
+    if (s + 1 < g.S) load(4 + s, nx);
+    emit(5 + 2 * s, 6 + 2 * s);  // phi_s, dz phi_s
   }
 }
 
@@ -187,6 +203,7 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
 // y inverse: columns along ky at fixed (z, kx-tile).
 // B fields: 0 u1, 1 u2, 2 u3, 3 omega1 = dy u3 - dz u2, 4 dz u1, 5 dy u1,
 //           6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s   (x still spectral)
+// The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
 template <int N, typename T>
 __global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
@@ -194,6 +211,9 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  constexpr uint32_t CS = sizeof(cpx<T>);
   __shared__ cpx<T> smem[W * N];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
@@ -206,30 +226,35 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   const int z = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  constexpr int K = (N - 1) / 3;
-  constexpr int M = 2 * K + 1;
-  const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX) + kx;
-  cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
-  const long long krow = (long long)kAZTile * g.PX;  // stride between ky rows at fixed z
+  // A rows (z, ky_c) and B rows (z, y) are both PX entries apart at fixed z
+  const uint32_t rsb = (uint32_t)g.PX * CS;
+  const uint32_t voff = ((uint32_t)j * g.PX + (uint32_t)kx) * CS;
+  const cpx<T>* aplane = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX);
+  cpx<T>* bplane = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX;
 
   auto kyv = [&](int m) { return T(wave_of(j + TT * m, N)); };
-  cpx<T> a[E], d[E];
   auto load = [&](int f, cpx<T> (&v)[E]) {
-    const cpx<T>* p = in + (long long)f * g.a_field;
+    const Buf<T> b = make_buf<T>(aplane + (long long)f * g.a_field);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int kc = compact_of(j + TT * m, N, K, M);
-      v[m] = (valid && kc >= 0) ? p[kc * krow] : czero<T>();
+      uint32_t vo, so;
+      v[m] = (valid && compact_at<N, TT>(m, j, voff, rsb, vo, so)) ? bload(b, vo, so) : czero<T>();
     }
   };
-  auto store = [&](int f, cpx<T> (&v)[E]) {
+  auto store = [&](int f, const cpx<T> (&v)[E]) {
     if (!valid) return;
-    cpx<T>* p = out + (long long)f * g.b_field;
+    const Buf<T> b = make_buf<T>(bplane + (long long)f * g.b_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) p[(long long)(j + TT * m) * g.PX] = v[m];
+    for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
+  };
+  cpx<T> a[E], d[E], nx[E];
+  auto take = [&]() {
+#pragma unroll
+    for (int m = 0; m < E; ++m) a[m] = nx[m];
   };
   // u1 and dy u1
   load(0, a);
+  load(1, nx);
 #pragma unroll
   for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m));
   fft<N, E, true>(a, lds, j, tw);
@@ -237,12 +262,14 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   fft<N, E, true>(d, lds, j, tw);
   store(5, d);
   // u2
-  load(1, a);
+  take();
+  load(2, nx);
+  load(4, d);
   fft<N, E, true>(a, lds, j, tw);
   store(1, a);
   // u3 and omega1 = dy u3 - dz u2
-  load(2, a);
-  load(4, d);
+  take();
+  load(3, nx);
 #pragma unroll
   for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m)) - d[m];
   fft<N, E, true>(a, lds, j, tw);
@@ -250,18 +277,23 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   fft<N, E, true>(d, lds, j, tw);
   store(3, d);
   // dz u1
-  load(3, a);
+  take();
+  if (g.S > 0) load(5, nx);
   fft<N, E, true>(a, lds, j, tw);
   store(4, a);
   for (int s = 0; s < g.S; ++s) {
-    load(5 + 2 * s, a);
+    // phi_s and dy phi_s
+    take();
+    load(6 + 2 * s, nx);
 #pragma unroll
     for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m));
     fft<N, E, true>(a, lds, j, tw);
     store(6 + 3 * s, a);
     fft<N, E, true>(d, lds, j, tw);
     store(7 + 3 * s, d);
-    load(6 + 2 * s, a);
+    // dz phi_s
+    take();
+    if (s + 1 < g.S) load(7 + 2 * s, nx);
     fft<N, E, true>(a, lds, j, tw);
     store(8 + 3 * s, a);
   }
@@ -551,6 +583,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 
 // ---------------------------------------------------------------------------
 // y forward: columns along y at fixed (z, kx-tile); keeps |ky| <= K.
+// The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
 template <int N, typename T>
 __global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
@@ -558,6 +591,9 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  constexpr uint32_t CS = sizeof(cpx<T>);
   __shared__ cpx<T> smem[W * N];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
@@ -570,22 +606,31 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   const int z = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  constexpr int K = (N - 1) / 3;
-  constexpr int M = 2 * K + 1;
-  const cpx<T>* in = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
-  cpx<T>* out = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX) + kx;
-  const long long krow = (long long)kAZTile * g.PX;
-  cpx<T> a[E];
+  const uint32_t rsb = (uint32_t)g.PX * CS;
+  const uint32_t voff = ((uint32_t)j * g.PX + (uint32_t)kx) * CS;
+  const cpx<T>* bplane = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX;
+  cpx<T>* aplane = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX);
+  auto load = [&](int f, cpx<T> (&v)[E]) {
+    const Buf<T> b = make_buf<T>(bplane + (long long)f * g.b_field);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
+  };
+  cpx<T> a[E], nx[E];
+  load(0, a);
   for (int f = 0; f < g.F; ++f) {
-    const cpx<T>* p = in + (long long)f * g.b_field;
+    if (f > 0) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a[m] = valid ? p[(long long)(j + TT * m) * g.PX] : czero<T>();
+      for (int m = 0; m < E; ++m) a[m] = nx[m];
+    }
+    if (f + 1 < g.F) load(f + 1, nx);
     fft<N, E, false>(a, lds, j, tw);
-    cpx<T>* q = out + (long long)f * g.a_field;
+    if (valid) {
+      const Buf<T> b = make_buf<T>(aplane + (long long)f * g.a_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int kc = compact_of(j + TT * m, N, K, M);
-      if (valid && kc >= 0) q[kc * krow] = a[m];
+      for (int m = 0; m < E; ++m) {
+        uint32_t vo, so;
+        if (compact_at<N, TT>(m, j, voff, rsb, vo, so)) bstore(b, vo, so, a[m]);
+      }
     }
   }
 }
@@ -605,46 +650,49 @@ struct StageArgs {
 };
 
 // Stage update of one mode.  Returns the input of the next stage (y_stage for
-// stages 0-2, y_{n+1} after stage 3); y_stage is stored only when write_ys.
+// stages 0-2, y_{n+1} after stage 3); y_stage is stored only when write_ys.  The
+// mode sits at byte offsets (vo, so) inside the field that starts foff entries
+// into each state array.
 template <typename T>
-__device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long o, cpx<T> F, double lk2, double h,
-                                            bool write_ys = true) {
+__device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so, cpx<T> F,
+                                            double lk2, double h, bool write_ys = true) {
   // lk2 = D |k|^2; exponential factors in FP64, then cast
   if (a.stage < 0) {
-    const cpx<T> y = a.sin[o];
-    a.rhs[o] = F - T(lk2) * y;
+    const cpx<T> y = bload(make_buf<T>(a.sin + foff), vo, so);
+    bstore(make_buf<T>(a.rhs + foff), vo, so, F - T(lk2) * y);
     return czero<T>();
   }
+  const Buf<T> yn = make_buf<T>(a.yn + foff), acc = make_buf<T>(a.acc + foff);
   const double ehd = exp(-0.5 * lk2 * h);
   const T eh = T(ehd), e1 = T(ehd * ehd);
   const T th = T(h);
   cpx<T> nxt;
   switch (a.stage) {
     case 0: {
-      const cpx<T> y = a.yn[o];
-      a.acc[o] = e1 * (y + (th / T(6)) * F);
+      const cpx<T> y = bload(yn, vo, so);
+      bstore(acc, vo, so, e1 * (y + (th / T(6)) * F));
       nxt = eh * (y + (th / T(2)) * F);
       break;
     }
     case 1: {
-      const cpx<T> y = a.yn[o];
-      a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
+      const cpx<T> y = bload(yn, vo, so);
+      bstore(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
       nxt = eh * y + (th / T(2)) * F;
       break;
     }
     case 2: {
-      const cpx<T> y = a.yn[o];
-      a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
+      const cpx<T> y = bload(yn, vo, so);
+      bstore(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
       nxt = e1 * y + (th * eh) * F;
       break;
     }
     default: {
-      nxt = a.acc[o] + (th / T(6)) * F;
-      a.yn[o] = nxt;
+      nxt = bload(acc, vo, so) + (th / T(6)) * F;
+      bstore(yn, vo, so, nxt);
       return nxt;
     }
   }
-  if (write_ys) a.ys[o] = nxt;
+  if (write_ys) bstore(make_buf<T>(a.ys + foff), vo, so, nxt);
   return nxt;
 }
 
@@ -655,12 +703,19 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long o, 
 // forcing amplitude and forcing term read it.  Fields go scalars first, in
 // reverse order, then velocity, so that no A field is overwritten before this
 // block has read its forward data.
+//
+// Addressing: A rows (z, ky_c) and state rows (kz_c, ky_c) are both M PX entries
+// apart along z, so one per-thread byte offset (row j of the column) serves every
+// field of both; element m adds a uniform multiple of the row stride.
 template <int N, typename T, bool FUSE>
-__global__ void PSDNS_COL_BOUNDS(std::conditional_t<FUSE, typename Cfg<N, T>::Fused, typename Cfg<N, T>::Col>::THREADS)
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::Fused::THREADS)
 k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
-  using C = std::conditional_t<FUSE, typename Cfg<N, T>::Fused, typename Cfg<N, T>::Col>;
+  using C = typename Cfg<N, T>::Fused;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  constexpr uint32_t CS = sizeof(cpx<T>);
   __shared__ cpx<T> smem[W * N];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
@@ -674,26 +729,31 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   const int kyc = blockIdx.y;
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
-  cpx<T>* io = abuf + (long long)slot * g.FA * g.a_field + kx;
-  const long long sbase = (long long)slot * g.F * g.st_field + kx;
+  const uint32_t rsb = (uint32_t)M * g.PX * CS;                       // z row stride (bytes)
+  const uint32_t voff = ((uint32_t)j * M * g.PX + (uint32_t)kyc * g.PX + (uint32_t)kx) * CS;
+  const cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
+  const long long sslot = (long long)slot * g.F * g.st_field;
   const int ky = wave_of_compact(kyc, g.K, g.M);
   const double h = dyn[slot].dt;
   const double A = dyn[slot].A;
   const T scale = T(1) / (T(N) * T(N) * T(N));
 
-  constexpr int K = (N - 1) / 3;
-  constexpr int M = 2 * K + 1;
   const int kxy2 = kx * kx + ky * ky;
-  auto kcm = [&](int m) { return valid ? compact_of(j + TT * m, N, K, M) : -1; };
   auto k2m = [&](int m) {
     const int kz = wave_of(j + TT * m, N);
     return double(kxy2 + kz * kz);
   };
   auto load_fwd = [&](int f, cpx<T> (&v)[E]) {
-    const cpx<T>* p = io + (long long)f * g.a_field;
+    const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? p[a_row(j + TT * m, kyc, M, g.PX)] : czero<T>();
+    for (int m = 0; m < E; ++m) v[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
     fft<N, E, false>(v, lds, j, tw);
+  };
+  auto store_a = [&](int f, const cpx<T> (&v)[E]) {
+    if (!valid) return;
+    const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
+#pragma unroll
+    for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
   // inverse z of the next stage input (scaled by 1/N^3) into A field f, and of i kz * it into fd
   auto inverse_out = [&](cpx<T> (&v)[E], int f, int fd) {
@@ -704,19 +764,15 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       d[m] = mul_is(v[m], T(wave_of(j + TT * m, N)));
     }
     fft<N, E, true>(v, lds, j, tw);
-    if (valid) {
-      cpx<T>* q = io + (long long)f * g.a_field;
-#pragma unroll
-      for (int m = 0; m < E; ++m) q[a_row(j + TT * m, kyc, M, g.PX)] = v[m];
-    }
+    store_a(f, v);
     if (fd >= 0) {
       fft<N, E, true>(d, lds, j, tw);
-      if (valid) {
-        cpx<T>* q = io + (long long)fd * g.a_field;
-#pragma unroll
-        for (int m = 0; m < E; ++m) q[a_row(j + TT * m, kyc, M, g.PX)] = d[m];
-      }
+      store_a(fd, d);
     }
+  };
+  // state offsets of element m (false where truncated or outside the kx range)
+  auto state_at = [&](int m, uint32_t& vo, uint32_t& so) {
+    return valid && compact_at<N, TT>(m, j, voff, rsb, vo, so);
   };
 
   // scalars: F = -a_hat (a already holds u.grad phi + g.u)
@@ -724,15 +780,15 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     cpx<T> a[E];
     load_fwd(3 + s, a);
     const double dif = sp.diff[3 + s];
+    const long long foff = sslot + (long long)(3 + s) * g.st_field;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int kcm_ = kcm(m);
+      uint32_t vo, so;
       cpx<T> nxt = czero<T>();
-      if (kcm_ >= 0) {
+      if (state_at(m, vo, so)) {
         const double k2m_ = k2m(m);
-        const long long o = sbase + (long long)(3 + s) * g.st_field + st_row(kcm_, kyc, M, g.PX);
         const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
-        nxt = rk_update(sa, o, F, dif * k2m_, h, !FUSE);
+        nxt = rk_update(sa, foff, vo, so, F, dif * k2m_, h, !FUSE);
       }
       a[m] = nxt;
     }
@@ -745,15 +801,15 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     load_fwd(1, c2);
     load_fwd(2, c3);
     const double nu = sp.nu;
+    const long long f1 = sslot, f2 = sslot + g.st_field, f3 = sslot + 2 * g.st_field;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int kcm_ = kcm(m);
+      uint32_t vo, so;
       cpx<T> n1 = czero<T>(), n2 = czero<T>(), n3 = czero<T>();
-      if (kcm_ >= 0) {
+      if (state_at(m, vo, so)) {
         const double k2m_ = k2m(m);
         const int n = j + TT * m;
         const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
-        const long long o = sbase + st_row(kcm_, kyc, M, g.PX);
         cpx<T> F1, F2, F3;
         const bool band = k2m_ > 0.0 && k2m_ <= sp.kf2;
         if (k2m_ == 0.0) {
@@ -766,16 +822,16 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
           F3 = c3[m] - (kzt * ik2) * kdc;
           if (A != 0.0 && band) {
             const T At = T(A);
-            F1 = F1 + At * sa.sin[o];
-            F2 = F2 + At * sa.sin[o + g.st_field];
-            F3 = F3 + At * sa.sin[o + 2 * g.st_field];
+            F1 = F1 + At * bload(make_buf<T>(sa.sin + f1), vo, so);
+            F2 = F2 + At * bload(make_buf<T>(sa.sin + f2), vo, so);
+            F3 = F3 + At * bload(make_buf<T>(sa.sin + f3), vo, so);
           }
         }
         const double lk2 = nu * k2m_;
         const bool wys = !FUSE || band;
-        n1 = rk_update(sa, o, F1, lk2, h, wys);
-        n2 = rk_update(sa, o + g.st_field, F2, lk2, h, wys);
-        n3 = rk_update(sa, o + 2 * g.st_field, F3, lk2, h, wys);
+        n1 = rk_update(sa, f1, vo, so, F1, lk2, h, wys);
+        n2 = rk_update(sa, f2, vo, so, F2, lk2, h, wys);
+        n3 = rk_update(sa, f3, vo, so, F3, lk2, h, wys);
       }
       c1[m] = n1;
       c2[m] = n2;
@@ -1177,7 +1233,7 @@ k_stats_y(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<
   const bool valid = kx < g.KX;
   const LdsCol<T, W> lds{smem + c};
   const cpx<T>* in = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX) + kx;
-  const long long krow = (long long)kAZTile * g.PX;
+  const long long krow = g.PX;
   cpx<T>* out = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX + kx;
   cpx<T> a[E];
   for (int f = 0; f < nf; ++f) {
@@ -1443,14 +1499,15 @@ struct Engine {
     sa.sin = sin;
     sa.rhs = static_cast<cpx<T>*>(rhs_out);
     sa.stage = stage;
+    const int ntile_u = (g.KX + C::Fused::W - 1) / C::Fused::W;
     if (flags & kStageFuse) {
       TimedLaunch tl(x.timer, KID_ZFWDI, s);
       k_z_forward_update<N, T, true>
-          <<<dim3(ntile, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+          <<<dim3(ntile_u, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     } else {
       TimedLaunch tl(x.timer, KID_ZFWD, s);
       k_z_forward_update<N, T, false>
-          <<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+          <<<dim3(ntile_u, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     }
   }
 

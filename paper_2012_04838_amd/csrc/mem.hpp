@@ -1,0 +1,98 @@
+// Vector-memory access of the column passes through buffer resources.
+//
+// A column pass touches, per thread, E elements of one column in each of several
+// fields.  With plain 64-bit pointers every element needs its own address pair in
+// VGPRs; with a buffer resource the field base sits in SGPRs, the per-thread part of
+// the offset is one VGPR shared by every element and field, and the per-element part
+// (a multiple of the row stride, the same for all lanes) is an SGPR offset.  All
+// offsets are byte offsets below 2^32 from the resource base, which is therefore set
+// per field (and per plane where a field exceeds 4 GiB).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fft.hpp"
+
+namespace psdns {
+
+// Word 3 of a gfx9 buffer descriptor for raw dword access (data format 32, no swizzle).
+constexpr int kBufWord3 = 0x00020000;
+
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+template <typename T>
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+template <typename T>
+__device__ __forceinline__ Buf<T> make_buf(const cpx<T>* base) {
+  // stride 0 (raw buffer), no record limit below 4 GiB
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<cpx<T>*>(base), 0, -1, kBufWord3)};
+}
+
+// Loads go through a two-lane vector of T: taking the lanes of the raw dword vector
+// one by one lets the optimiser split the access into single-dword loads.
+template <typename T>
+__device__ __forceinline__ cpx<T> bload(const Buf<T>& b, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+    return {v.x, v.y};
+  } else {
+    const f64x2_t v = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)soff, 0));
+    return {v.x, v.y};
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(const Buf<T>& b, uint32_t voff, uint32_t soff, cpx<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    const f32x2_t w = {v.x, v.y};
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, w), b.r, (int)voff, (int)soff, 0);
+  } else {
+    const f64x2_t w = {v.x, v.y};
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)voff, (int)soff, 0);
+  }
+}
+
+// Positions along a column of N points handled by a thread: element m of thread j
+// is position n = j + TT m.  A compact column keeps the retained positions n <= K
+// and n >= N - K only, at compact index n and n - N + M respectively (K = (N-1)/3,
+// M = 2K + 1).  For most m every thread of a column falls in the same class, so the
+// compact row is j plus a uniform shift.
+template <int N, int TT>
+struct ColPos {
+  static constexpr int K = (N - 1) / 3;
+  static constexpr int M = 2 * K + 1;
+  static constexpr bool low(int m) { return TT * m + TT - 1 <= K; }
+  static constexpr bool high(int m) { return TT * m >= N - K; }
+  static constexpr bool cut(int m) { return TT * m > K && TT * m + TT - 1 < N - K; }
+  static constexpr int shift(int m) { return high(m) ? TT * m - N + M : TT * m; }
+};
+
+// Byte offsets (vo per thread, so uniform) of element m of a compact column whose
+// rows are rsb bytes apart and whose row-0 offset for this thread is voff (that of
+// row j).  Returns false where the element is truncated.
+template <int N, int TT>
+__device__ __forceinline__ bool compact_at(int m, int j, uint32_t voff, uint32_t rsb, uint32_t& vo, uint32_t& so) {
+  using P = ColPos<N, TT>;
+  if (P::cut(m)) return false;
+  if (P::low(m) || P::high(m)) {
+    vo = voff;
+    so = (uint32_t)P::shift(m) * rsb;
+    return true;
+  }
+  const int n = j + TT * m;
+  const int kc = n <= P::K ? n : (n >= N - P::K ? n - N + P::M : -1);
+  if (kc < 0) return false;
+  // (kc - j) may be negative; the sum wraps to the true offset, which is below 2^32
+  vo = voff + (uint32_t)(kc - j) * rsb;
+  so = 0;
+  return true;
+}
+
+}  // namespace psdns
