@@ -33,10 +33,10 @@ GRAD = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
 # the same process (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  `src` is the digest of the kernel
 # sources and build flags they were taken with; a different digest reports null.
 MEASURED_TRAFFIC = {
-    "src": "ac34a35f0f4e0a31",
+    "src": "2419b4769ec7f321",
     "workload": (512, 2, 32),
-    "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.0e6, "y_forward": 3047.5e6,
-              "z_forward_update_inverse": 6556.0e6},
+    "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.1e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
+              "z_forward_update_inverse": 5502.6e6},
 }
 
 
@@ -240,6 +240,7 @@ def main():
     launches, tot = tim[dom]
     avg_ms = tot / max(launches, 1)
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
+    traffic = measured_traffic(dom, n, s, 32)
     per_kernel = {k: {"launches": tim[k][0], "avg_ms": tim[k][1] / max(tim[k][0], 1),
                       "alg_GB_per_launch": kb[k] / 1e9 if k in kb else None,
                       "alg_GBs": (kb[k] / (tim[k][1] / max(tim[k][0], 1) * 1e-3) / 1e9) if k in kb and tim[k][0] else None}
@@ -261,7 +262,10 @@ def main():
                                f"(Sc {SCHMIDT[:s]}, G=(0,1,0)), nu={NU}, P={POWER} on 0<|k|<={KF:g}, "
                                f"Rogallo IC k_p={KP:g}, CFL 0.5", "n": n, "scalars": s, "batch": 1},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": measured_traffic(dom, n, s, 32)},
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "traffic_GBs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
+                     "alg_bytes_per_launch": kb[dom]},
         "step_roofline": {"alg_GB_per_step": step_bytes(n, s, 32) / 1e9,
                           "achieved_GBs": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9,
                           "frac": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9 / PEAK_HBM_GBS},

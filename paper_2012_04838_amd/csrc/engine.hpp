@@ -48,6 +48,24 @@ namespace psdns {
 #define PSDNS_X_BOUNDS(...) __launch_bounds__((__VA_ARGS__))
 #endif
 
+// minimum waves per SIMD of the y-forward and z-update passes (0: as the other column passes)
+#ifndef PSDNS_YF_WAVES
+#define PSDNS_YF_WAVES 0
+#endif
+#ifndef PSDNS_FUSED_WAVES
+#define PSDNS_FUSED_WAVES 0
+#endif
+#if PSDNS_YF_WAVES > 0
+#define PSDNS_YF_BOUNDS(...) __launch_bounds__((__VA_ARGS__), PSDNS_YF_WAVES)
+#else
+#define PSDNS_YF_BOUNDS(...) PSDNS_COL_BOUNDS(__VA_ARGS__)
+#endif
+#if PSDNS_FUSED_WAVES > 0
+#define PSDNS_FUSED_BOUNDS(...) __launch_bounds__((__VA_ARGS__), PSDNS_FUSED_WAVES)
+#else
+#define PSDNS_FUSED_BOUNDS(...) PSDNS_COL_BOUNDS(__VA_ARGS__)
+#endif
+
 #ifndef PSDNS_COL_BYTES
 #define PSDNS_COL_BYTES 128
 #endif
@@ -84,6 +102,32 @@ struct ColCfg {
   static_assert(THREADS <= 1024, "column block too large");
   static_assert((W * N + N) * sizeof(cpx<T>) <= 160 * 1024, "column pass LDS exceeds 160 KB");
 };
+
+// LDS of a column pass: the exchange buffer, doubled (one barrier per exchange)
+// when two buffers and the twiddle table fit in the 160 KB of a CU.
+#ifndef PSDNS_COL_DB
+#define PSDNS_COL_DB 1
+#endif
+#ifndef PSDNS_FUSED_DB
+#define PSDNS_FUSED_DB 0
+#endif
+#ifndef PSDNS_YF_DB
+#define PSDNS_YF_DB PSDNS_COL_DB
+#endif
+template <int N, typename T, int W, bool EN = PSDNS_COL_DB>
+struct ColLds {
+  static constexpr bool kDouble = EN && (2 * W * N + N) * sizeof(cpx<T>) <= 160 * 1024;
+  static constexpr int kEntries = (kDouble ? 2 : 1) * W * N;
+  using View = LdsCol<T, W, kDouble ? W * N : 0>;
+};
+
+// Whether a column pass with E elements per thread and THREADS threads per block can
+// hold the next field's elements (prefetch) next to its two working arrays within
+// the per-thread register budget of the block (65536 per SIMD over its waves).
+template <typename T, int E, int THREADS>
+constexpr bool col_prefetch() {
+  return 3 * E * (int)sizeof(cpx<T>) / 4 + 40 <= 131072 / THREADS;
+}
 
 template <int N, typename T>
 struct Cfg {
@@ -131,7 +175,8 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
-  __shared__ cpx<T> smem[W * N];
+  using L = ColLds<N, T, W>;
+  __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   if (!slots[slot].active) return;
@@ -142,7 +187,7 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   const int kx = blockIdx.x * W + c;
   const int kyc = blockIdx.y;
   const bool valid = kx < g.KX;
-  const LdsCol<T, W> lds{smem + c};
+  const typename L::View lds{smem + c};
   const T scale = T(1) / (T(N) * T(N) * T(N));
   // state rows (kz_c, ky_c) and A rows (z, ky_c) are both M PX entries apart along z
   const uint32_t rsb = (uint32_t)M * g.PX * CS;
@@ -179,22 +224,26 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
       store(fd, d);
     }
   };
-  auto take = [&]() {
+  // field cur into a (from the prefetch when enabled), then prefetch field nxt
+  constexpr bool PF = col_prefetch<T, E, C::COL_THREADS>();
+  auto advance = [&](int cur, int nxt) {
+    if constexpr (PF) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a[m] = nx[m];
+      for (int m = 0; m < E; ++m) a[m] = nx[m];
+      if (nxt >= 0) load(nxt, nx);
+    } else {
+      load(cur, a);
+    }
   };
   load(0, a);
-  load(1, nx);
+  if constexpr (PF) load(1, nx);
   emit(0, 3);  // u1, dz u1
-  take();
-  load(2, nx);
+  advance(1, 2);
   emit(1, 4);  // u2, dz u2
-  take();
-  if (g.S > 0) load(3, nx);
+  advance(2, g.S > 0 ? 3 : -1);
   emit(2, -1);  // u3
   for (int s = 0; s < g.S; ++s) {
-    take();
-    if (s + 1 < g.S) load(4 + s, nx);
+    advance(3 + s, s + 1 < g.S ? 4 + s : -1);
     emit(5 + 2 * s, 6 + 2 * s);  // phi_s, dz phi_s
   }
 }
@@ -214,7 +263,8 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
-  __shared__ cpx<T> smem[W * N];
+  using L = ColLds<N, T, W>;
+  __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   if (!slots[slot].active) return;
@@ -225,7 +275,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   const int kx = blockIdx.x * W + c;
   const int z = blockIdx.y;
   const bool valid = kx < g.KX;
-  const LdsCol<T, W> lds{smem + c};
+  const typename L::View lds{smem + c};
   // A rows (z, ky_c) and B rows (z, y) are both PX entries apart at fixed z
   const uint32_t rsb = (uint32_t)g.PX * CS;
   const uint32_t voff = ((uint32_t)j * g.PX + (uint32_t)kx) * CS;
@@ -248,13 +298,20 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
     for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
   cpx<T> a[E], d[E], nx[E];
-  auto take = [&]() {
+  // field cur into a (from the prefetch when enabled), then prefetch field nxt
+  constexpr bool PF = col_prefetch<T, E, C::COL_THREADS>();
+  auto advance = [&](int cur, int nxt) {
+    if constexpr (PF) {
 #pragma unroll
-    for (int m = 0; m < E; ++m) a[m] = nx[m];
+      for (int m = 0; m < E; ++m) a[m] = nx[m];
+      if (nxt >= 0) load(nxt, nx);
+    } else {
+      load(cur, a);
+    }
   };
   // u1 and dy u1
   load(0, a);
-  load(1, nx);
+  if constexpr (PF) load(1, nx);
 #pragma unroll
   for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m));
   fft<N, E, true>(a, lds, j, tw);
@@ -262,14 +319,12 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   fft<N, E, true>(d, lds, j, tw);
   store(5, d);
   // u2
-  take();
-  load(2, nx);
+  advance(1, 2);
   load(4, d);
   fft<N, E, true>(a, lds, j, tw);
   store(1, a);
   // u3 and omega1 = dy u3 - dz u2
-  take();
-  load(3, nx);
+  advance(2, 3);
 #pragma unroll
   for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m)) - d[m];
   fft<N, E, true>(a, lds, j, tw);
@@ -277,14 +332,12 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   fft<N, E, true>(d, lds, j, tw);
   store(3, d);
   // dz u1
-  take();
-  if (g.S > 0) load(5, nx);
+  advance(3, g.S > 0 ? 5 : -1);
   fft<N, E, true>(a, lds, j, tw);
   store(4, a);
   for (int s = 0; s < g.S; ++s) {
     // phi_s and dy phi_s
-    take();
-    load(6 + 2 * s, nx);
+    advance(5 + 2 * s, 6 + 2 * s);
 #pragma unroll
     for (int m = 0; m < E; ++m) d[m] = mul_is(a[m], kyv(m));
     fft<N, E, true>(a, lds, j, tw);
@@ -292,8 +345,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
     fft<N, E, true>(d, lds, j, tw);
     store(7 + 3 * s, d);
     // dz phi_s
-    take();
-    if (s + 1 < g.S) load(7 + 2 * s, nx);
+    advance(6 + 2 * s, s + 1 < g.S ? 7 + 2 * s : -1);
     fft<N, E, true>(a, lds, j, tw);
     store(8 + 3 * s, a);
   }
@@ -586,7 +638,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 // The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
 template <int N, typename T>
-__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+__global__ void PSDNS_YF_BOUNDS(Cfg<N, T>::COL_THREADS)
 k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
   using C = Cfg<N, T>;
@@ -594,7 +646,8 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
-  __shared__ cpx<T> smem[W * N];
+  using L = ColLds<N, T, W, PSDNS_YF_DB>;
+  __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   if (!slots[slot].active) return;
@@ -605,7 +658,7 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   const int kx = blockIdx.x * W + c;
   const int z = blockIdx.y;
   const bool valid = kx < g.KX;
-  const LdsCol<T, W> lds{smem + c};
+  const typename L::View lds{smem + c};
   const uint32_t rsb = (uint32_t)g.PX * CS;
   const uint32_t voff = ((uint32_t)j * g.PX + (uint32_t)kx) * CS;
   const cpx<T>* bplane = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX;
@@ -616,13 +669,18 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
     for (int m = 0; m < E; ++m) v[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
   };
   cpx<T> a[E], nx[E];
+  constexpr bool PF = col_prefetch<T, E, C::COL_THREADS>();
   load(0, a);
   for (int f = 0; f < g.F; ++f) {
-    if (f > 0) {
+    if constexpr (PF) {
+      if (f > 0) {
 #pragma unroll
-      for (int m = 0; m < E; ++m) a[m] = nx[m];
+        for (int m = 0; m < E; ++m) a[m] = nx[m];
+      }
+      if (f + 1 < g.F) load(f + 1, nx);
+    } else if (f > 0) {
+      load(f, a);
     }
-    if (f + 1 < g.F) load(f + 1, nx);
     fft<N, E, false>(a, lds, j, tw);
     if (valid) {
       const Buf<T> b = make_buf<T>(aplane + (long long)f * g.a_field);
@@ -708,7 +766,7 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long fof
 // apart along z, so one per-thread byte offset (row j of the column) serves every
 // field of both; element m adds a uniform multiple of the row stride.
 template <int N, typename T, bool FUSE>
-__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::Fused::THREADS)
+__global__ void PSDNS_FUSED_BOUNDS(Cfg<N, T>::Fused::THREADS)
 k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
   using C = typename Cfg<N, T>::Fused;
@@ -716,7 +774,8 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
-  __shared__ cpx<T> smem[W * N];
+  using L = ColLds<N, T, W, PSDNS_FUSED_DB>;
+  __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
   const int slot = blockIdx.z;
   const SlotDev& sp = slots[slot];
@@ -728,7 +787,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   const int kx = blockIdx.x * W + c;
   const int kyc = blockIdx.y;
   const bool valid = kx < g.KX;
-  const LdsCol<T, W> lds{smem + c};
+  const typename L::View lds{smem + c};
   const uint32_t rsb = (uint32_t)M * g.PX * CS;                       // z row stride (bytes)
   const uint32_t voff = ((uint32_t)j * M * g.PX + (uint32_t)kyc * g.PX + (uint32_t)kx) * CS;
   const cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;

@@ -124,13 +124,17 @@ __device__ __forceinline__ void dft(cpx<T> (&a)[R]) {
   for (int i = 0; i < R; ++i) a[i] = b[i];
 }
 
-// LDS views used for the inter-stage exchange.
-// Columns: element p of the line owned by lane column c sits at base[p * W].
-template <typename T, int W>
+// LDS views used for the inter-stage exchange; x is the running exchange index.
+// Columns: element p of the line owned by lane column c sits at base[p * W].  With
+// SPAN > 0 two buffers SPAN entries apart alternate between exchanges, so a buffer
+// is only rewritten after the barrier of the following exchange, which every thread
+// reaches after its reads: one barrier per exchange instead of two.
+template <typename T, int W, int SPAN = 0>
 struct LdsCol {
+  static constexpr bool kDouble = SPAN > 0;
   cpx<T>* base;
-  __device__ __forceinline__ void st(int p, cpx<T> v) const { base[p * W] = v; }
-  __device__ __forceinline__ cpx<T> ld(int p) const { return base[p * W]; }
+  __device__ __forceinline__ void st(int p, cpx<T> v, int x) const { base[(x & 1) * SPAN + p * W] = v; }
+  __device__ __forceinline__ cpx<T> ld(int p, int x) const { return base[(x & 1) * SPAN + p * W]; }
 };
 // Contiguous line (one line per E-element lane group): element p is stored at
 // p ^ ((p >> log2 E) & min(31, N-1)).  The XOR swizzle keeps the Stockham writes
@@ -141,9 +145,10 @@ struct LdsLine {
   cpx<T>* base;
   static constexpr int kShift = E == 1 ? 0 : E == 2 ? 1 : E == 4 ? 2 : E == 8 ? 3 : E == 16 ? 4 : E == 32 ? 5 : 6;
   static constexpr int kMask = N - 1 < 31 ? N - 1 : 31;
+  static constexpr bool kDouble = false;
   static __device__ __forceinline__ int idx(int p) { return p ^ ((p >> kShift) & kMask); }
-  __device__ __forceinline__ void st(int p, cpx<T> v) const { base[idx(p)] = v; }
-  __device__ __forceinline__ cpx<T> ld(int p) const { return base[idx(p)]; }
+  __device__ __forceinline__ void st(int p, cpx<T> v, int = 0) const { base[idx(p)] = v; }
+  __device__ __forceinline__ cpx<T> ld(int p, int = 0) const { return base[idx(p)]; }
 };
 template <int N>
 struct LinePad {
@@ -221,9 +226,21 @@ __device__ __forceinline__ cpx<T> tw_get(const TwReg<N, E, T>& t, int b, int r, 
   return t.w[OFF + b * (R - 1) + r - 1];
 }
 
+// Number of LDS exchanges of an N-point transform with E elements per thread.
+template <int N, int E, int NS = 1>
+__host__ __device__ constexpr int exchanges() {
+  if constexpr (NS >= N) {
+    return 0;
+  } else {
+    constexpr int R = (NS * E <= N) ? E : N / NS;
+    return (NS * R == N ? 0 : 1) + exchanges<N, E, NS * R>();
+  }
+}
+
 // One Stockham stage (and, recursively, the ones after it).
-// NS = product of the radices already applied; OFF = twiddles used so far.
-template <int N, int E, bool INV, int NS, int OFF, class Sync, typename T, class Lds, class Tw>
+// NS = product of the radices already applied; OFF = twiddles used so far;
+// XI = exchanges done so far.
+template <int N, int E, bool INV, int NS, int OFF, class Sync, int XI = 0, typename T, class Lds, class Tw>
 __device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j, const Tw& tw) {
   if constexpr (NS < N) {
     constexpr int TT = N / E;
@@ -252,15 +269,18 @@ __device__ __forceinline__ void fft_stage(cpx<T> (&v)[E], const Lds& lds, int j,
       } else {
         const int base = (vb / NS) * NS * R + kv;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lds.st(base + r * NS, a[r]);
+        for (int r = 0; r < R; ++r) lds.st(base + r * NS, a[r], XI);
       }
     }
     if constexpr (!LAST) {
       Sync::sync();
 #pragma unroll
-      for (int m = 0; m < E; ++m) v[m] = lds.ld(j + TT * m);
-      Sync::sync();
-      fft_stage<N, E, INV, NS * R, (NS > 1 ? OFF + NB * (R - 1) : OFF), Sync>(v, lds, j, tw);
+      for (int m = 0; m < E; ++m) v[m] = lds.ld(j + TT * m, XI);
+      // with two buffers the trailing barrier is needed only where the next transform
+      // would reuse this buffer first: after the last exchange of an odd count
+      constexpr int NX = exchanges<N, E>();
+      if constexpr (!Lds::kDouble || (XI + 1 == NX && NX % 2 == 1)) Sync::sync();
+      fft_stage<N, E, INV, NS * R, (NS > 1 ? OFF + NB * (R - 1) : OFF), Sync, XI + 1>(v, lds, j, tw);
     }
   }
 }
