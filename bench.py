@@ -6,7 +6,7 @@ with spectrum peak k_p = 8 and unit kinetic energy, RK4 with the integrating
 factor and dt from CFL = 0.5 every step.  FP32 is the reported value; the same
 run in FP64 is reported beside it.  Inputs are resident in HBM before timing.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--n 512] [--scalars 2]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-tune] [--n 512] [--scalars 2]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -91,7 +91,7 @@ def step_bytes(n: int, s: int, prec: int) -> float:
     return 4.0 * (kb["y_inverse"] + kb["x_pass"] + kb["y_forward"] + kb["z_forward_update_inverse"])
 
 
-def run_gpu(n, s, prec, steps, warmup, seed=3):
+def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3):
     import torch
 
     from paper_2012_04838_amd import psdns
@@ -101,6 +101,11 @@ def run_gpu(n, s, prec, steps, warmup, seed=3):
     st = plan.new_state()
     ws = plan.new_workspace()
     plan.init_field(st, ws, 0, seed=seed, k_peak=KP, kinetic_energy=1.0)
+    sched = None
+    if tune_reps > 0:
+        # autotuner (outside the timed region): every compiled schedule on this state
+        best, ms_each = plan.tune(st, ws, tune_reps)
+        sched = {"chosen": best, "ms_per_rhs": ms_each, "chosen_desc": plan.schedule_info(best)}
     plan.step(st, ws, -0.5, warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -123,7 +128,7 @@ def run_gpu(n, s, prec, steps, warmup, seed=3):
     del st, ws
     plan.close()
     torch.cuda.empty_cache()
-    return {"ms_total": ms, "wall_s": wall, "timing": timing, "info": info, "finite": ok}
+    return {"ms_total": ms, "wall_s": wall, "timing": timing, "info": info, "finite": ok, "schedule": sched}
 
 
 def copy_reference(gbytes: float, reps: int = 5):
@@ -212,6 +217,7 @@ def main():
                     help="requests of the serving mix (Poisson arrivals at --serve-load of the measured "
                          "saturated capacity); 0 disables")
     ap.add_argument("--serve-load", type=float, default=0.7)
+    ap.add_argument("--no-tune", action="store_true", help="run schedule 0 instead of the autotuned schedule")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -225,11 +231,12 @@ def main():
     n, s = args.n, args.scalars
     n3 = float(n) ** 3
     copy = copy_reference(args.copy_gb) if args.copy_gb > 0 else None
-    r32 = run_gpu(n, s, 32, args.steps, args.warmup)
+    tr = 0 if args.no_tune else 3
+    r32 = run_gpu(n, s, 32, args.steps, args.warmup, tune_reps=tr)
     print(f"[bench] fp32 done: {r32['ms_total'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(n, s, 64, args.steps, args.warmup)
+        r64 = run_gpu(n, s, 64, args.steps, args.warmup, tune_reps=tr)
         print(f"[bench] fp64 done: {r64['ms_total'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
 
     ms32 = r32["ms_total"] / args.steps
@@ -270,6 +277,7 @@ def main():
                           "achieved_GBs": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9,
                           "frac": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "kernels_fp32": per_kernel,
+        "schedule_fp32": r32["schedule"],
         "copy_reference": copy,
         "finite": r32["finite"],
     }
@@ -279,6 +287,7 @@ def main():
                        "step_frac": step_bytes(n, s, 64) / (ms64 * 1e-3) / 1e9 / PEAK_HBM_GBS,
                        "finite": r64["finite"]}
         out["fp32_over_fp64"] = ms64 / ms32
+        out["schedule_fp64"] = r64["schedule"]
         kb64 = kernel_bytes(n, s, 64)
         t64 = r64["timing"]
         out["kernels_fp64"] = {k: {"launches": t64[k][0], "avg_ms": t64[k][1] / max(t64[k][0], 1),

@@ -97,7 +97,9 @@ typedef struct {
   int32_t n_shells;        /* shells s = 0 .. n_shells-1 reported by psdns_spectra */
   int32_t spectra_doubles; /* doubles per slot written by psdns_spectra */
   int64_t state_bytes, workspace_bytes;
-  int32_t elems_col, elems_x; /* FFT elements per thread of the column and x passes */
+  int32_t elems_col, elems_x; /* FFT elements per thread of the column and x passes (schedule in use) */
+  int32_t n_schedules;        /* step schedules compiled for this size (psdns_set_schedule) */
+  int32_t schedule;           /* schedule in use */
 } psdns_plan_info;
 
 /* Bytes of the compact spectral state y for all slots (caller allocates). 0 on invalid params. */
@@ -141,6 +143,34 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
  * time, so psdns_set_slot needs no re-capture.  Steps on the default (NULL) stream are
  * launched directly.  Timing events are not recorded for replayed steps. */
 psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable);
+
+/* Step schedules.  The step kernels of a size are compiled in several tile and radix
+ * schedules: elements per thread of the column passes (the radix of their Stockham
+ * stages), kx columns per column block, the same two for the z-update pass, and lines
+ * per x-pass block.  All schedules compute the same transforms of Eq. (5) and the same
+ * right-hand side; only the association order of the butterflies differs.  Schedule 0
+ * is the default.  Choosing one changes no layout or buffer size. */
+typedef struct {
+  int32_t index;
+  int32_t elems_col;   /* elements per thread of the z and y passes */
+  int32_t col_width;   /* kx columns per block of the z and y passes */
+  int32_t elems_fused; /* elements per thread of the z-forward/update pass */
+  int32_t fused_width; /* kx columns per block of the z-forward/update pass */
+  int32_t elems_x;     /* elements per lane of the x pass */
+  int32_t x_lines;     /* (z, y) lines per x-pass block */
+} psdns_schedule_info;
+psdns_status psdns_get_schedule_info(const psdns_plan* plan, int32_t index, psdns_schedule_info* out);
+/* Select the schedule used by rhs and step (a captured step graph is dropped and
+ * re-captured on the next graph step).  PSDNS_E_INVAL for an index outside
+ * [0, n_schedules). */
+psdns_status psdns_set_schedule(psdns_plan* plan, int32_t index);
+/* Autotuner: times `reps` right-hand-side evaluations of `state` (every active slot) with
+ * each schedule after one untimed evaluation, selects the fastest and returns the mean
+ * milliseconds per evaluation in host array ms_out[n_schedules] (may be NULL) and its index
+ * in *best (may be NULL).  The evaluations write into the workspace accumulator, which
+ * holds nothing between steps; `state` is not modified.  Synchronises the stream. */
+psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
+                        int32_t* best, void* hip_stream);
 
 /* Copy the per-slot stepping records to host memory `out[batch]` (synchronises the stream). */
 psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_info* out, void* hip_stream);

@@ -91,14 +91,6 @@ Ops ops_for(int n, int prec) {
   }
 }
 
-// lines per x-pass block, mirrored from the device configuration (elements per thread ex)
-int lines_per_xblock(int n, int ex) {
-  const int tx = n / ex;
-  int l = 256 / tx;
-  if (l < 1) l = 1;
-  if (l > 64) l = 64;
-  return l;
-}
 
 // blocks per slot of the moments kernels (fixed, so their partial sums have a fixed order)
 int moment_blocks(int n) {
@@ -119,7 +111,7 @@ struct Layout {
   int nbm, rec;
 };
 
-Layout make_layout(const psdns_plan_params* p, int ex) {
+Layout make_layout(const psdns_plan_params* p) {
   Layout L{};
   Geom& g = L.g;
   g.N = p->n;
@@ -135,7 +127,9 @@ Layout make_layout(const psdns_plan_params* p, int ex) {
   g.st_field = (long long)g.M * g.M * g.PX;
   g.a_field = (long long)g.N * g.M * g.PX;
   g.b_field = (long long)g.N * g.N * g.PX;
-  g.nblk_x = (int)((long long)g.N * g.N / lines_per_xblock(g.N, ex));
+  // x-pass partial maxima: at most one per line whatever the schedule (the step sets
+  // the count of the schedule in use)
+  g.nblk_x = g.N * g.N;
   g.ns = shell_count(g.K);
   L.nbm = moment_blocks(g.N);
   L.rec = spectra_record(g.ns, g.S);
@@ -225,6 +219,7 @@ struct psdns_plan {
   const void* graph_state = nullptr;
   const void* graph_ws = nullptr;
   double graph_dt = 0.0;
+  int sched = 0;  // step schedule in use (psdns_set_schedule / psdns_tune)
 };
 
 namespace {
@@ -278,13 +273,13 @@ extern "C" {
 size_t psdns_state_bytes(const psdns_plan_params* p) {
   std::string why;
   if (!valid_params(p, &why)) return 0;
-  return make_layout(p, ops_for(p->n, p->precision).ex).st_bytes;
+  return make_layout(p).st_bytes;
 }
 
 size_t psdns_workspace_bytes(const psdns_plan_params* p) {
   std::string why;
   if (!valid_params(p, &why)) return 0;
-  return make_layout(p, ops_for(p->n, p->precision).ex).ws_bytes;
+  return make_layout(p).ws_bytes;
 }
 
 psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
@@ -296,7 +291,7 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
   if (!plan) return fail(PSDNS_E_NOMEM, "host allocation of the plan failed");
   plan->p = *p;
   plan->ops = ops_for(p->n, p->precision);
-  plan->L = make_layout(p, plan->ops.ex);
+  plan->L = make_layout(p);
   hipError_t e = hipGetDevice(&plan->device);
   if (e != hipSuccess) {
     delete plan;
@@ -374,8 +369,39 @@ psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
   out->spectra_doubles = plan->L.rec;
   out->state_bytes = (int64_t)plan->L.st_bytes;
   out->workspace_bytes = (int64_t)plan->L.ws_bytes;
-  out->elems_col = plan->ops.ec;
-  out->elems_x = plan->ops.ex;
+  out->elems_col = plan->ops.sched[plan->sched].ec;
+  out->elems_x = plan->ops.sched[plan->sched].ex;
+  out->n_schedules = plan->ops.nsched;
+  out->schedule = plan->sched;
+  return PSDNS_OK;
+}
+
+psdns_status psdns_get_schedule_info(const psdns_plan* plan, int32_t index, psdns_schedule_info* out) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!out) return fail(PSDNS_E_INVAL, "out is NULL");
+  if (index < 0 || index >= plan->ops.nsched)
+    return fail(PSDNS_E_INVAL, "schedule index out of range [0, " + std::to_string(plan->ops.nsched) + ")");
+  const StepSched& d = plan->ops.sched[index];
+  out->index = index;
+  out->elems_col = d.ec;
+  out->col_width = d.col_w;
+  out->elems_fused = d.fused_ec;
+  out->fused_width = d.fused_w;
+  out->elems_x = d.ex;
+  out->x_lines = d.x_lines;
+  return PSDNS_OK;
+}
+
+psdns_status psdns_set_schedule(psdns_plan* plan, int32_t index) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (index < 0 || index >= plan->ops.nsched)
+    return fail(PSDNS_E_INVAL, "schedule index out of range [0, " + std::to_string(plan->ops.nsched) + ")");
+  if (index != plan->sched && plan->graph_exec) {
+    // a captured step holds the kernels of the old schedule
+    HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
+    plan->graph_exec = nullptr;
+  }
+  plan->sched = index;
   return PSDNS_OK;
 }
 
@@ -429,9 +455,51 @@ psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws,
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
-  plan->ops.rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, kStageZinv, s);
+  plan->ops.sched[plan->sched].rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, kStageZinv, s);
   HIP_TRY(hipGetLastError());
   return PSDNS_OK;
+}
+
+psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
+                        int32_t* best, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
+  if (reps < 1 || reps > 1000) return fail(PSDNS_E_INVAL, "reps must be in [1, 1000]");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  Ctx c = make_ctx(plan, ws);
+  c.timer = nullptr;  // the trial launches are not part of the kernel timing record
+  std::vector<double> ms(plan->ops.nsched, 0.0);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return fail(PSDNS_E_HIP, "hipEventCreate failed");
+  }
+  hipError_t err = hipSuccess;
+  int b = 0;
+  for (int i = 0; i < plan->ops.nsched && err == hipSuccess; ++i) {
+    RhsStageFn f = plan->ops.sched[i].rhs_stage;
+    // one untimed evaluation, then reps timed ones; dy/dt goes to the accumulator,
+    // which holds nothing between steps
+    f(c, const_cast<void*>(state), state, -1, c.acc, 0, 0.0, kStageZinv, s);
+    err = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) f(c, const_cast<void*>(state), state, -1, c.acc, 0, 0.0, kStageZinv, s);
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&t, e0, e1);
+    if (err == hipSuccess) err = hipGetLastError();
+    ms[i] = (double)t / reps;
+    if (ms[i] < ms[b]) b = i;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (err != hipSuccess) return hip_fail(err, "schedule trial");
+  if (ms_out)
+    for (int i = 0; i < plan->ops.nsched; ++i) ms_out[i] = ms[i];
+  if (best) *best = b;
+  return psdns_set_schedule(plan, b);
 }
 
 psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps, void* hip_stream) {
@@ -451,7 +519,7 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
       int fl = kStageFuse;
       if (first && stage == 0) fl |= kStageZinv;
       if (last && stage == 3) fl &= ~kStageFuse;
-      plan->ops.rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
+      plan->ops.sched[plan->sched].rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
     }
   };
   if (plan->use_graph && s != nullptr && nsteps > 0) {
@@ -483,7 +551,7 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
       plan->graph_dt = dt;
     }
     // the captured step expects the z inverse of y_n: run it once, then replay
-    plan->ops.rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
+    plan->ops.sched[plan->sched].rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
     HIP_TRY(hipGetLastError());
     for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
     return PSDNS_OK;

@@ -100,13 +100,26 @@ struct Ctx {
   Timer* timer;            // may be null
 };
 
+// One evaluation of the nonlinear right-hand side at stage_in followed by the stage
+// update (stage 0..3) or, for stage < 0, the full dy/dt into rhs_out.
+typedef void (*RhsStageFn)(const Ctx&, void* state, const void* stage_in, int stage, void* rhs_out,
+                           int want_max, double dt_arg, int flags, hipStream_t);
+
+// Schedules (tile and radix choices) compiled for the step kernels of one size.
+constexpr int kMaxSched = 8;
+struct StepSched {
+  int ec, ex;          // elements per thread of the column passes and of the x pass
+  int col_w;           // kx columns per column block
+  int fused_ec;        // elements per thread of the z-update pass
+  int fused_w;         // kx columns per z-update block
+  int x_lines;         // x-pass lines per block
+  RhsStageFn rhs_stage;
+};
+
 // One (N, precision) instantiation of the device code.
 struct Ops {
-  int ec, ex;   // elements per thread of the column passes and the x pass
-  // One evaluation of the nonlinear right-hand side at stage_in followed by the
-  // stage update (stage 0..3) or, for stage < 0, the full dy/dt into rhs_out.
-  void (*rhs_stage)(const Ctx&, void* state, const void* stage_in, int stage, void* rhs_out,
-                    int want_max, double dt_arg, int flags, hipStream_t);
+  int nsched;
+  StepSched sched[kMaxSched];
   void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, double energy,
                      hipStream_t);
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);

@@ -129,10 +129,34 @@ constexpr bool col_prefetch() {
   return 3 * E * (int)sizeof(cpx<T>) / 4 + 40 <= 131072 / THREADS;
 }
 
-template <int N, typename T>
+// Step schedules the autotuner chooses from: the tile and radix choices of the step
+// kernels.  ec: elements per thread of the column passes (the radix of their Stockham
+// stages); bytes: row segment (kx tile) of a column block; ef, fb: the same for the
+// z-update pass; xl2: lines per x-pass block relative to 256 threads, in halves.
+struct Sched {
+  int ec32, ec64, bytes, ef32, ef64, fb32, fb64, xl2;
+};
+constexpr Sched kSched[] = {
+    {PSDNS_EC32, PSDNS_EC64, PSDNS_COL_BYTES, PSDNS_EF32, PSDNS_EF64, PSDNS_FB32, PSDNS_FB64, 2},  // default
+    {4, 4, PSDNS_COL_BYTES, 4, 4, PSDNS_COL_BYTES, PSDNS_COL_BYTES, 2},                          // radix 4
+    {16, 16, PSDNS_COL_BYTES, 16, 16, PSDNS_COL_BYTES, PSDNS_COL_BYTES, 2},                      // radix 16
+    {PSDNS_EC32, PSDNS_EC64, 64, PSDNS_EF32, PSDNS_EF64, 64, 64, 2},                             // narrow tiles
+    {PSDNS_EC32, PSDNS_EC64, PSDNS_COL_BYTES, PSDNS_EF32, PSDNS_EF64, PSDNS_FB32, PSDNS_FB64, 1},  // small x blocks
+};
+constexpr int kNumSched = (int)(sizeof(kSched) / sizeof(kSched[0]));
+static_assert(kNumSched <= kMaxSched, "schedule table exceeds the dispatch table");
+// schedules compiled for a grid size (the 1024^3 kernels are built once)
+template <int N>
+constexpr int sched_count() {
+  return N > 512 ? 1 : kNumSched;
+}
+
+template <int N, typename T, int V = 0>
 struct Cfg {
-  using Col = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EC32 : PSDNS_EC64>;
-  using Fused = ColCfg<N, T, sizeof(T) == 4 ? PSDNS_EF32 : PSDNS_EF64, sizeof(T) == 4 ? PSDNS_FB32 : PSDNS_FB64>;
+  static constexpr Sched D = kSched[V];
+  static constexpr bool F32 = sizeof(T) == 4;
+  using Col = ColCfg<N, T, F32 ? D.ec32 : D.ec64, D.bytes>;
+  using Fused = ColCfg<N, T, F32 ? D.ef32 : D.ef64, F32 ? D.fb32 : D.fb64>;
   // columns per block and elements per thread of the column passes (z, y)
   static constexpr int W = Col::W;
   static constexpr int EC = Col::EC;
@@ -142,7 +166,7 @@ struct Cfg {
   static constexpr int EX0 = N > 512 ? N / 64 : 8;
   static constexpr int EX = N < EX0 ? N : EX0;
   static constexpr int TX = N / EX;
-  static constexpr int LX0 = 256 / TX;
+  static constexpr int LX0 = 256 / TX * D.xl2 / 2;
   static constexpr int LX = LX0 < 1 ? 1 : (LX0 > 64 ? 64 : LX0);
   static constexpr int X_THREADS = LX * TX;
   static constexpr int LP = LinePad<N>::value;
@@ -166,11 +190,11 @@ __device__ __forceinline__ cpx<T> czero() { return {T(0), T(0)}; }
 // (all carry the 1/N^3 of Eq. (5) so that physical values are the true ones).
 // The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
-__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+template <int N, typename T, int V>
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T, V>::COL_THREADS)
 k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
-  using C = Cfg<N, T>;
+  using C = Cfg<N, T, V>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
@@ -254,11 +278,11 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
 //           6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s   (x still spectral)
 // The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
-__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+template <int N, typename T, int V>
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T, V>::COL_THREADS)
 k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
-  using C = Cfg<N, T>;
+  using C = Cfg<N, T, V>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
@@ -438,11 +462,11 @@ struct XLine {
   }
 };
 
-template <int N, typename T>
-__global__ void PSDNS_X_BOUNDS(Cfg<N, T>::X_THREADS)
+template <int N, typename T, int V>
+__global__ void PSDNS_X_BOUNDS(Cfg<N, T, V>::X_THREADS)
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
          double* __restrict__ maxpart, Geom g, int want_max) {
-  using C = Cfg<N, T>;
+  using C = Cfg<N, T, V>;
   constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
   constexpr int K = (N - 1) / 3;
   constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
@@ -637,11 +661,11 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 // y forward: columns along y at fixed (z, kx-tile); keeps |ky| <= K.
 // The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
-template <int N, typename T>
-__global__ void PSDNS_YF_BOUNDS(Cfg<N, T>::COL_THREADS)
+template <int N, typename T, int V>
+__global__ void PSDNS_YF_BOUNDS(Cfg<N, T, V>::COL_THREADS)
 k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
             const SlotDev* __restrict__ slots, Geom g) {
-  using C = Cfg<N, T>;
+  using C = Cfg<N, T, V>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
@@ -765,11 +789,11 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long fof
 // Addressing: A rows (z, ky_c) and state rows (kz_c, ky_c) are both M PX entries
 // apart along z, so one per-thread byte offset (row j of the column) serves every
 // field of both; element m adds a uniform multiple of the row stride.
-template <int N, typename T, bool FUSE>
-__global__ void PSDNS_FUSED_BOUNDS(Cfg<N, T>::Fused::THREADS)
+template <int N, typename T, bool FUSE, int V>
+__global__ void PSDNS_FUSED_BOUNDS(Cfg<N, T, V>::Fused::THREADS)
 k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
-  using C = typename Cfg<N, T>::Fused;
+  using C = typename Cfg<N, T, V>::Fused;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
   constexpr int K = (N - 1) / 3;
   constexpr int M = 2 * K + 1;
@@ -1512,15 +1536,18 @@ struct TimedLaunch {
   }
 };
 
-template <int N, typename T>
-struct Engine {
-  using C = Cfg<N, T>;
+// One right-hand-side evaluation and stage update with schedule V.
+template <int N, typename T, int V>
+struct Step {
+  using C = Cfg<N, T, V>;
 
   // flags: kStageZinv launches the standalone z inverse of stage_in first; kStageFuse makes
   // the last pass also produce the z-inverse of the next stage input.
   static void rhs_stage(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
                         double dt_arg, int flags, hipStream_t s) {
-    const Geom& g = x.g;
+    // the x-pass block count (and so the partial-maximum count) follows the schedule
+    Geom g = x.g;
+    g.nblk_x = N * N / C::LX;
     const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
     const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
     cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
@@ -1532,16 +1559,16 @@ struct Engine {
     }
     if (flags & kStageZinv) {
       TimedLaunch tl(x.timer, KID_ZINV, s);
-      k_z_inverse<N, T><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(sin, A, tw, x.slots, g);
+      k_z_inverse<N, T, V><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(sin, A, tw, x.slots, g);
     }
     if (flags & kStagePrologue) return;
     {
       TimedLaunch tl(x.timer, KID_YINV, s);
-      k_y_inverse<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, x.slots, g);
+      k_y_inverse<N, T, V><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, x.slots, g);
     }
     {
       TimedLaunch tl(x.timer, KID_XPASS, s);
-      k_x_pass<N, T><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, g, want_max);
+      k_x_pass<N, T, V><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, g, want_max);
     }
     if (stage == 0) {
       TimedLaunch tl(x.timer, KID_DT, s);
@@ -1549,7 +1576,7 @@ struct Engine {
     }
     {
       TimedLaunch tl(x.timer, KID_YFWD, s);
-      k_y_forward<N, T><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(B, A, tw, x.slots, g);
+      k_y_forward<N, T, V><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(B, A, tw, x.slots, g);
     }
     StageArgs<T> sa;
     sa.yn = static_cast<cpx<T>*>(state);
@@ -1561,14 +1588,19 @@ struct Engine {
     const int ntile_u = (g.KX + C::Fused::W - 1) / C::Fused::W;
     if (flags & kStageFuse) {
       TimedLaunch tl(x.timer, KID_ZFWDI, s);
-      k_z_forward_update<N, T, true>
+      k_z_forward_update<N, T, true, V>
           <<<dim3(ntile_u, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     } else {
       TimedLaunch tl(x.timer, KID_ZFWD, s);
-      k_z_forward_update<N, T, false>
+      k_z_forward_update<N, T, false, V>
           <<<dim3(ntile_u, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     }
   }
+};
+
+template <int N, typename T>
+struct Engine {
+  using C = Cfg<N, T>;
 
   static void init_field(const Ctx& x, void* state, int slot, uint64_t seed, double kp, double energy,
                          hipStream_t s) {
@@ -1639,11 +1671,31 @@ struct Engine {
                                                x.spectra_rec);
   }
 
+  template <int V>
+  static void add_sched(Ops& o) {
+    using CV = Cfg<N, T, V>;
+    StepSched& d = o.sched[V];
+    d.ec = CV::EC;
+    d.ex = CV::EX;
+    d.col_w = CV::W;
+    d.fused_ec = CV::Fused::EC;
+    d.fused_w = CV::Fused::W;
+    d.x_lines = CV::LX;
+    d.rhs_stage = &Step<N, T, V>::rhs_stage;
+  }
+
+  template <int V, int NV>
+  static void add_scheds(Ops& o) {
+    if constexpr (V < NV) {
+      add_sched<V>(o);
+      add_scheds<V + 1, NV>(o);
+    }
+  }
+
   static Ops ops() {
-    Ops o;
-    o.ec = C::EC;
-    o.ex = C::EX;
-    o.rhs_stage = &rhs_stage;
+    Ops o{};
+    o.nsched = sched_count<N>();
+    add_scheds<0, sched_count<N>()>(o);
     o.init_field = &init_field;
     o.get_state = &get_state;
     o.set_state = &set_state;

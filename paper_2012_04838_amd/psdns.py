@@ -45,7 +45,13 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [(name, _c_int32) for name in ("n", "k_max", "m", "kx_count", "kx_pitch", "n_scalars",
                                              "precision", "batch", "n_shells", "spectra_doubles")] + \
                [("state_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
-                ("elems_col", _c_int32), ("elems_x", _c_int32)]
+                ("elems_col", _c_int32), ("elems_x", _c_int32), ("n_schedules", _c_int32),
+                ("schedule", _c_int32)]
+
+
+class ScheduleInfo(ctypes.Structure):
+    _fields_ = [(name, _c_int32) for name in ("index", "elems_col", "col_width", "elems_fused", "fused_width",
+                                             "elems_x", "x_lines")]
 
 
 class KernelTiming(ctypes.Structure):
@@ -75,6 +81,10 @@ _SIGS = {
     "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_set_graph": (ctypes.c_int, [_c_void_p, _c_int32]),
+    "psdns_get_schedule_info": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(ScheduleInfo)]),
+    "psdns_set_schedule": (ctypes.c_int, [_c_void_p, _c_int32]),
+    "psdns_tune": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(_c_int32), _c_void_p]),
     "psdns_set_timing": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_get_timing": (ctypes.c_int, [_c_void_p, ctypes.POINTER(KernelTiming), _c_int32,
                                         ctypes.POINTER(_c_int32)]),
@@ -246,6 +256,36 @@ class Plan:
     def set_graph(self, enable: bool) -> None:
         """Replay RK4 steps from a captured HIP graph (non-default streams only)."""
         _check(lib().psdns_set_graph(self._h, 1 if enable else 0))
+
+    # ---------------------------------------------------------------- schedules
+    def _refresh_info(self) -> None:
+        _check(lib().psdns_plan_get_info(self._h, ctypes.byref(self.info)))
+
+    @property
+    def n_schedules(self) -> int:
+        return int(self.info.n_schedules)
+
+    @property
+    def schedule(self) -> int:
+        return int(self.info.schedule)
+
+    def schedule_info(self, index: int) -> dict:
+        si = ScheduleInfo()
+        _check(lib().psdns_get_schedule_info(self._h, index, ctypes.byref(si)))
+        return {name: int(getattr(si, name)) for name, _ in ScheduleInfo._fields_}
+
+    def set_schedule(self, index: int) -> None:
+        _check(lib().psdns_set_schedule(self._h, index))
+        self._refresh_info()
+
+    def tune(self, state, ws, reps: int = 3):
+        """Time every schedule on `state` (right-hand-side evaluations), select the fastest;
+        returns (best index, [ms per evaluation of each schedule])."""
+        ms = (ctypes.c_double * self.n_schedules)()
+        best = _c_int32()
+        _check(lib().psdns_tune(self._h, _ptr(state), _ptr(ws), reps, ms, ctypes.byref(best), _stream()))
+        self._refresh_info()
+        return int(best.value), [float(v) for v in ms]
 
     def set_timing(self, enable: bool) -> None:
         _check(lib().psdns_set_timing(self._h, 1 if enable else 0))

@@ -25,7 +25,7 @@ from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
-from . import psdns
+from . import psdns, tune
 
 
 def viscosity_for(n: int, power: float = 0.1, kmax_eta: float = 1.5) -> float:
@@ -68,7 +68,8 @@ def default_capacity(n: int) -> int:
 class Group:
     """One batched plan for a given (N, S), with its buffers and stream."""
 
-    def __init__(self, n: int, s: int, capacity: int, precision: int = 32, use_graph: bool = True):
+    def __init__(self, n: int, s: int, capacity: int, precision: int = 32, use_graph: bool = True,
+                 tune_cache: Optional[tune.TuneCache] = None, autotune: bool = True):
         import torch
 
         self.n, self.s, self.capacity = n, s, capacity
@@ -79,6 +80,13 @@ class Group:
             self.ws = self.plan.new_workspace()
             self.spec = torch.empty((capacity, int(self.plan.info.spectra_doubles)), dtype=torch.float64,
                                     device="cuda")
+            if autotune:
+                # schedule for this (N, S, capacity): timed on a zero field with every slot active
+                self.state.zero_()
+                for i in range(capacity):
+                    self.plan.set_slot(i, nu=viscosity_for(n), active=True)
+                tune.autotune(self.plan, self.state, self.ws, cache=tune_cache, reps=2)
+        self.stream.synchronize()
         self.plan.set_graph(use_graph)
         self.footprint = int(self.plan.info.state_bytes + self.plan.info.workspace_bytes)
         self.slots: List[Optional[Request]] = [None] * capacity
@@ -106,7 +114,8 @@ class Server:
     """Admission, continuous batching and completion of DNS requests."""
 
     def __init__(self, hbm_budget: Optional[int] = None, precision: int = 32, use_graph: bool = True,
-                 capacity=default_capacity, max_chunk: int = 16):
+                 capacity=default_capacity, max_chunk: int = 16, autotune: bool = True,
+                 tune_cache: Optional[tune.TuneCache] = None):
         import torch
 
         if hbm_budget is None:
@@ -117,6 +126,8 @@ class Server:
         self.use_graph = use_graph
         self.capacity = capacity
         self.max_chunk = max_chunk
+        self.autotune = autotune
+        self.tune_cache = tune_cache if tune_cache is not None else (tune.TuneCache() if autotune else None)
         self.groups: Dict[Tuple[int, int], Group] = {}
         self.waiting: deque = deque()
         self.done: List[Request] = []
@@ -150,7 +161,8 @@ class Server:
                         break
         if self.reserved() + need > self.budget:
             return None
-        g = Group(req.n, req.n_scalars, self.capacity(req.n), self.precision, self.use_graph)
+        g = Group(req.n, req.n_scalars, self.capacity(req.n), self.precision, self.use_graph,
+                  tune_cache=self.tune_cache, autotune=self.autotune)
         self.groups[key] = g
         return g
 

@@ -1,0 +1,116 @@
+"""Every compiled step schedule (tile and radix choice) against the CPU FP64 oracle, and
+the autotuner that picks among them.
+
+All schedules compute the same transforms; only the association order of the
+butterflies and the tiling differ, so each must meet the FP64 bar (1e-12 relative L2)
+on its own.  N = 64 has 22 kx columns (ragged against 16-, 8- and 4-wide tiles) and
+N = 128 has 43.
+"""
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_2012_04838_amd import inputs
+from tests.gpu_helpers import make_plan, rel_l2, set_params, to_numpy, torch_mod
+
+pytestmark = pytest.mark.gpu
+
+
+def _prm(S):
+    sc = (1.0, 0.7)[:S]
+    g = ((0.0, 1.0, 0.0), (0.2, 1.0, -0.3))[:S]
+    return ora.Params(nu=0.01, schmidt=sc, mean_grad=g, power=0.1, k_force=2.0, forcing=True)
+
+
+@pytest.mark.parametrize("N,S,prec", [(32, 1, 64), (64, 2, 64), (128, 1, 64), (64, 2, 32)])
+def test_every_schedule_rhs_matches_oracle(N, S, prec):
+    torch = torch_mod()
+    x = inputs.random_spectral_state(N, 3 + S, 40 + N + S, ora.kmax_retained(N), 5.0)
+    prm = _prm(S)
+    ref = ora.rhs(x, prm)
+    plan = make_plan(N, S, prec)
+    assert plan.n_schedules >= 2
+    set_params(plan, 0, prm)
+    st, ws, out = plan.new_state(), plan.new_workspace(), plan.new_state()
+    plan.set_state(st, x, 0)
+    tol = 1e-12 if prec == 64 else 1e-5
+    for v in range(plan.n_schedules):
+        plan.set_schedule(v)
+        assert plan.schedule == v
+        out.zero_()
+        plan.rhs(st, out, ws)
+        got = to_numpy(plan.get_state(out, 0))
+        torch.cuda.synchronize()
+        err = rel_l2(got, ref)
+        print(f"N={N} S={S} fp{prec} schedule {v} {plan.schedule_info(v)}: rel L2 {err:.2e}", flush=True)
+        assert err < tol, (v, err)
+
+
+def test_every_schedule_steps_match_oracle():
+    torch = torch_mod()
+    N, S, steps, dt = 64, 1, 3, 0.004
+    x = ora.init_field(N, S, 7, 4.0, 1.0)
+    prm = _prm(S)
+    ref = ora.step(x, prm, dt, steps)
+    plan = make_plan(N, S, 64)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    for v in range(plan.n_schedules):
+        plan.set_schedule(v)
+        plan.set_state(st, x, 0)
+        plan.step(st, ws, dt, steps)
+        got = to_numpy(plan.get_state(st, 0))
+        torch.cuda.synchronize()
+        assert rel_l2(got, ref) < 1e-12, (v, rel_l2(got, ref))
+
+
+def test_tune_selects_a_schedule_and_leaves_the_state_alone(tmp_path):
+    torch = torch_mod()
+    from paper_2012_04838_amd import tune
+
+    N, S = 64, 2
+    plan = make_plan(N, S, 32, batch=2)
+    prm = _prm(S)
+    for slot in range(2):
+        set_params(plan, slot, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    plan.init_field(st, ws, 0, seed=3, k_peak=4.0)
+    plan.init_field(st, ws, 1, seed=4, k_peak=4.0)
+    before = st.clone()
+    best, ms = plan.tune(st, ws, reps=2)
+    torch.cuda.synchronize()
+    assert len(ms) == plan.n_schedules and all(m > 0 for m in ms)
+    assert best == int(np.argmin(ms)) and plan.schedule == best
+    assert torch.equal(st, before)
+    # cache: the second autotune takes the stored choice without timing
+    cache = tune.TuneCache(str(tmp_path / "tune.json"))
+    v = tune.autotune(plan, st, ws, cache=cache, reps=1)
+    assert 0 <= v < plan.n_schedules
+
+    def no_timing(*a, **k):
+        raise AssertionError("cache hit expected")
+
+    plan.tune = no_timing
+    cache2 = tune.TuneCache(str(tmp_path / "tune.json"))
+    assert tune.autotune(plan, st, ws, cache=cache2) == v
+
+
+def test_graph_recaptures_after_schedule_change():
+    torch = torch_mod()
+    N, S, dt = 32, 1, 0.005
+    x = ora.init_field(N, S, 11, 4.0, 1.0)
+    prm = _prm(S)
+    plan = make_plan(N, S, 64)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        plan.set_graph(True)
+        plan.set_state(st, x, 0)
+        plan.step(st, ws, dt, 2)       # captured with schedule 0
+        plan.set_schedule(plan.n_schedules - 1)
+        plan.step(st, ws, dt, 2)       # re-captured with the last schedule
+        got = to_numpy(plan.get_state(st, 0))
+    stream.synchronize()
+    ref = ora.step(x, prm, dt, 4)
+    assert rel_l2(got, ref) < 1e-12

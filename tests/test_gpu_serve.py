@@ -12,13 +12,21 @@ from tests.gpu_helpers import torch_mod
 pytestmark = pytest.mark.gpu
 
 
-def test_result_same_alone_and_in_mix():
+@pytest.mark.parametrize("autotune", [False, True])
+def test_result_same_alone_and_in_mix(autotune, tmp_path):
+    """With one fixed schedule the result is bitwise the same alone and in the mix.  With
+    the autotuner on, a group of another capacity may run another schedule (same
+    transforms, other butterfly association), so the bar is the FP32 field tolerance."""
     torch = torch_mod()
+    from paper_2012_04838_amd import tune
+
+    cache = tune.TuneCache(str(tmp_path / "tune.json")) if autotune else None
     mix = make_mix(14, rate=200.0, seed=3, sizes=(32, 64), weights=(0.5, 0.5), steps=(3, 12), scalars=(0, 1, 2))
     picked = [0, 5, 9, 13]
     for i in picked:
         mix[i].keep_state = True
-    srv = Server(capacity=lambda n: 3)  # small groups force slot reuse and waiting
+    # small groups force slot reuse and waiting
+    srv = Server(capacity=lambda n: 3, autotune=autotune, tune_cache=cache)
     done = srv.run(copy.deepcopy(mix))
     srv.close()
     assert len(done) == len(mix)
@@ -26,13 +34,18 @@ def test_result_same_alone_and_in_mix():
     for i in picked:
         alone = copy.deepcopy(mix[i])
         alone.arrival = 0.0
-        s2 = Server(capacity=lambda n: 1)
+        s2 = Server(capacity=lambda n: 1, autotune=autotune, tune_cache=cache)
         res = s2.run([alone])[0]
         s2.close()
         a, b = res.state, by_id[i].state
         assert a is not None and b is not None
-        assert np.array_equal(a, b), (i, np.max(np.abs(a - b)))
-        assert res.spectra["K"] == by_id[i].spectra["K"]
+        if autotune:
+            err = np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel())
+            assert err < 1e-5, (i, err)
+            assert abs(res.spectra["K"] - by_id[i].spectra["K"]) <= 1e-5 * abs(by_id[i].spectra["K"])
+        else:
+            assert np.array_equal(a, b), (i, np.max(np.abs(a - b)))
+            assert res.spectra["K"] == by_id[i].spectra["K"]
     torch.cuda.synchronize()
 
 
@@ -40,7 +53,7 @@ def test_admission_respects_budget_and_reuses_slots():
     torch = torch_mod()
     per = psdns.state_bytes(64, 1, 32, 2) + psdns.workspace_bytes(64, 1, 32, 2)
     reqs = [Request(rid=i, n=64, n_scalars=1, steps=4, seed=10 + i, nu=viscosity_for(64)) for i in range(5)]
-    srv = Server(hbm_budget=int(1.5 * per), capacity=lambda n: 2)
+    srv = Server(hbm_budget=int(1.5 * per), capacity=lambda n: 2, autotune=False)
     done = srv.run(reqs)
     assert len(done) == 5
     assert len(srv.groups) == 1 and srv.reserved() <= srv.budget
