@@ -184,6 +184,16 @@ psdns_status psdns_get_state(psdns_plan* plan, const void* state, int32_t slot, 
 psdns_status psdns_set_state(psdns_plan* plan, void* state, int32_t slot, const void* canonical_in,
                              void* hip_stream);
 
+/* Modified pressure (Sec. 2.2): p_hat(k) = i k.(u.grad u)^(k) / |k|^2 on the retained
+ * modes, p_hat(0) = 0, in the transform convention of Eq. (5) (unnormalised like the
+ * state).  Evaluated as -(|u|^2/2)^ - i k.(u x omega)^ / |k|^2, which equals it because
+ * u.grad u = grad(|u|^2/2) - u x omega and both products are dealiased by the same
+ * truncation.  `canonical_out` (device) receives batch * N * N * (N/2+1) complex values:
+ * per slot one field in the canonical layout, modes outside the retained cube and
+ * inactive slots zero.  Uses the workspace transform buffers and accumulator (which
+ * holds nothing between steps); asynchronous on the stream. */
+psdns_status psdns_pressure(psdns_plan* plan, const void* state, void* ws, void* canonical_out, void* hip_stream);
+
 /* Spectra and statistics of every slot (Table 1; Eqs. (11)-(13)), accumulated in FP64 with
  * a fixed summation order (bitwise reproducible).  `out` is a device buffer of
  * batch * psdns_plan_info.spectra_doubles doubles; with ns = n_shells and S scalars the

@@ -436,6 +436,32 @@ def n_shells(N: int) -> int:
     return int(round(math.sqrt(3.0) * K)) + 1
 
 
+def pressure(state: np.ndarray) -> np.ndarray:
+    """Modified pressure of Sec. 2.2 (the divergence of the momentum equation under
+    continuity): p_hat = i k.(u.grad u)^ / |k|^2 on the retained modes, 0 at k = 0.
+
+    u.grad u is formed in physical space from the nine gradients i k_j u_i_hat, then
+    transformed forward and truncated to the retained cube, the same dealiasing as the
+    right-hand side.  Returns one half-spectrum field.
+    """
+    N = state.shape[-3]
+    kx, ky, kz = kgrid(N)
+    ik = (1j * kx, 1j * ky, 1j * kz)
+    uhat = state[:3]
+    u = [to_physical(uhat[i]) for i in range(3)]
+    nhat = []
+    for i in range(3):
+        acc = 0.0
+        for j in range(3):
+            acc = acc + u[j] * to_physical(ik[j] * uhat[i])
+        nhat.append(truncate(to_spectral(acc)))
+    k2 = k_squared(N)
+    p = 1j * (kx * nhat[0] + ky * nhat[1] + kz * nhat[2]) / np.where(k2 > 0, k2, 1.0)
+    p[k2 == 0] = 0.0
+    p[~retained_mask(N)] = 0.0
+    return p
+
+
 def spectra(state: np.ndarray, prm: Params) -> dict:
     """Shell spectra and the Table 1 statistics, all from the spectral state.
 

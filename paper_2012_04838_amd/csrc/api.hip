@@ -573,6 +573,20 @@ psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable) {
   return PSDNS_OK;
 }
 
+psdns_status psdns_pressure(psdns_plan* plan, const void* state, void* ws, void* canonical_out, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !ws || !canonical_out) return fail(PSDNS_E_INVAL, "state, ws and canonical_out must be device pointers");
+  if (state == canonical_out) return fail(PSDNS_E_INVAL, "canonical_out must not alias state");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  Ctx c = make_ctx(plan, ws);
+  std::vector<int> active(plan->p.batch);
+  for (int i = 0; i < plan->p.batch; ++i) active[i] = plan->slots_host[i].active;
+  plan->ops.pressure(c, state, canonical_out, active.data(), s);
+  HIP_TRY(hipGetLastError());
+  return PSDNS_OK;
+}
+
 psdns_status psdns_spectra(psdns_plan* plan, const void* state, void* ws, double* out, int32_t flags,
                            void* hip_stream) {
   if (psdns_status s = check_plan(plan)) return s;

@@ -125,6 +125,7 @@ struct Ops {
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);
   void (*set_state)(const Ctx&, void* state, int slot, const void* canon, hipStream_t);
   void (*spectra)(const Ctx&, const void* state, double* out, int flags, hipStream_t);
+  void (*pressure)(const Ctx&, const void* state, void* canon, const int* active, hipStream_t);
 };
 
 template <int N>

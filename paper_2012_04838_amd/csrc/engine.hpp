@@ -462,10 +462,14 @@ struct XLine {
   }
 };
 
+// mode bits of the x pass
+constexpr int kXMax = 1;       // partial maxima of |u1|+|u2|+|u3| (CFL)
+constexpr int kXPressure = 2;  // with S = 0: forward field 3 is |u|^2/2 (pressure assembly)
+
 template <int N, typename T, int V>
 __global__ void PSDNS_X_BOUNDS(Cfg<N, T, V>::X_THREADS)
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
-         double* __restrict__ maxpart, Geom g, int want_max) {
+         double* __restrict__ maxpart, Geom g, int mode) {
   using C = Cfg<N, T, V>;
   constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
   constexpr int K = (N - 1) / 3;
@@ -586,7 +590,15 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 
   forward_pair(c1, c2, 0, 1);
   if (S == 0) {
-    forward_pair(c3, zero, 2, -1);
+    if (mode & kXPressure) {
+      // kinetic energy density |u|^2/2, the gradient part of u.grad u in rotational form
+      T q[E];
+#pragma unroll
+      for (int m = 0; m < E; ++m) q[m] = T(0.5) * (u1p[m] * u1p[m] + u2p[m] * u2p[m] + u3p[m] * u3p[m]);
+      forward_pair(c3, q, 2, 3);
+    } else {
+      forward_pair(c3, zero, 2, -1);
+    }
   } else {
     const SlotDev& sp = slots[slot];
     T as0[E], as1[E];
@@ -643,7 +655,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     }
   }
 
-  if (want_max) {
+  if (mode & kXMax) {
     red[threadIdx.x] = (double)mx;
     __syncthreads();
     for (int o = C::X_THREADS / 2; o > 0; o >>= 1) {
@@ -925,6 +937,71 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       inverse_out(c2, 1, 4);
       inverse_out(c3, 2, -1);
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// pressure (Sec. 2.2): with u.grad u = grad(|u|^2/2) - u x omega,
+//   p_hat = i k.(u.grad u)^ / |k|^2 = -(|u|^2/2)^ - i k.c_hat / |k|^2,  c = u x omega,
+// and p_hat(0) = 0.  A fields 0..3 hold c1, c2, c3 and |u|^2/2 after the y forward
+// pass; the z forward transform is followed by this assembly, written to one compact
+// field per slot (rows (kz_c, ky_c), PX apart in kx).
+// ---------------------------------------------------------------------------
+template <int N, typename T>
+__global__ void PSDNS_COL_BOUNDS(Cfg<N, T>::COL_THREADS)
+k_z_forward_pressure(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ pout, const cpx<T>* __restrict__ tw_g,
+                     const SlotDev* __restrict__ slots, Geom g) {
+  using C = Cfg<N, T>;
+  constexpr int W = C::W, E = C::EC, TT = C::TC;
+  constexpr int K = (N - 1) / 3;
+  constexpr int M = 2 * K + 1;
+  constexpr uint32_t CS = sizeof(cpx<T>);
+  using L = ColLds<N, T, W>;
+  __shared__ cpx<T> smem[L::kEntries];
+  __shared__ cpx<T> stw[N];
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  stage_twiddles<N>(stw, tw_g);
+  const cpx<T>* tw = stw;
+  const int c = threadIdx.x % W;
+  const int j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c;
+  const int kyc = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const typename L::View lds{smem + c};
+  const uint32_t rsb = (uint32_t)M * g.PX * CS;
+  const uint32_t voff = ((uint32_t)j * M * g.PX + (uint32_t)kyc * g.PX + (uint32_t)kx) * CS;
+  const cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
+  const int ky = wave_of_compact(kyc, K, M);
+  cpx<T> v[E], kdc[E];
+  auto load_fwd = [&](int f) {
+    const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
+#pragma unroll
+    for (int m = 0; m < E; ++m) v[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
+    fft<N, E, false>(v, lds, j, tw);
+  };
+  // k . c_hat, one component at a time
+  load_fwd(0);
+#pragma unroll
+  for (int m = 0; m < E; ++m) kdc[m] = T(kx) * v[m];
+  load_fwd(1);
+#pragma unroll
+  for (int m = 0; m < E; ++m) kdc[m] = kdc[m] + T(ky) * v[m];
+  load_fwd(2);
+#pragma unroll
+  for (int m = 0; m < E; ++m) kdc[m] = kdc[m] + T(wave_of(j + TT * m, N)) * v[m];
+  load_fwd(3);
+  if (!valid) return;
+  const Buf<T> out = make_buf<T>(pout + (long long)slot * g.st_field);
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    uint32_t vo, so;
+    if (!compact_at<N, TT>(m, j, voff, rsb, vo, so)) continue;
+    const int kz = wave_of(j + TT * m, N);
+    const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    cpx<T> p = czero<T>();
+    if (k2 > 0.0) p = czero<T>() - v[m] - mul_is(kdc[m], T(1.0 / k2));
+    bstore(out, vo, so, p);
   }
 }
 
@@ -1568,7 +1645,7 @@ struct Step {
     }
     {
       TimedLaunch tl(x.timer, KID_XPASS, s);
-      k_x_pass<N, T, V><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, g, want_max);
+      k_x_pass<N, T, V><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, g, want_max ? kXMax : 0);
     }
     if (stage == 0) {
       TimedLaunch tl(x.timer, KID_DT, s);
@@ -1629,6 +1706,40 @@ struct Engine {
     TimedLaunch tl(x.timer, KID_AUX, s);
     k_convert<T, false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
         static_cast<cpx<T>*>(state), const_cast<cpx<T>*>(static_cast<const cpx<T>*>(canon)), g, slot);
+  }
+
+  // pressure of every active slot into the canonical layout (one field per slot)
+  static void pressure(const Ctx& x, const void* state, void* canon, const int* active, hipStream_t s) {
+    using C0 = Cfg<N, T, 0>;
+    const cpx<T>* st = static_cast<const cpx<T>*>(state);
+    const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
+    cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
+    cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
+    cpx<T>* P = static_cast<cpx<T>*>(x.acc);  // compact pressure, one field per slot
+    // velocity only: the scalar fields are skipped (slot strides keep the real counts)
+    Geom gp = x.g;
+    gp.S = 0;
+    gp.nblk_x = N * N / C0::LX;
+    const int ntile = (gp.KX + C0::W - 1) / C0::W;
+    TimedLaunch tl(x.timer, KID_AUX, s);
+    k_z_inverse<N, T, 0><<<dim3(ntile, gp.M, gp.batch), C0::COL_THREADS, 0, s>>>(st, A, tw, x.slots, gp);
+    k_y_inverse<N, T, 0><<<dim3(ntile, N, gp.batch), C0::COL_THREADS, 0, s>>>(A, B, tw, x.slots, gp);
+    k_x_pass<N, T, 0><<<dim3(gp.nblk_x, gp.batch), C0::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, gp, kXPressure);
+    Geom gy = gp;
+    gy.F = 4;  // c1, c2, c3, |u|^2/2
+    k_y_forward<N, T, 0><<<dim3(ntile, N, gp.batch), C0::COL_THREADS, 0, s>>>(B, A, tw, x.slots, gy);
+    k_z_forward_pressure<N, T><<<dim3(ntile, gp.M, gp.batch), C0::COL_THREADS, 0, s>>>(A, P, tw, x.slots, gp);
+    const long long per = (long long)N * N * (N / 2 + 1);
+    k_fill_zero<T><<<(unsigned)((per * gp.batch + 255) / 256), 256, 0, s>>>(static_cast<cpx<T>*>(canon),
+                                                                             per * gp.batch);
+    Geom g1 = gp;
+    g1.F = 1;
+    const long long n = (long long)g1.M * g1.M * g1.KX;
+    for (int slot = 0; slot < gp.batch; ++slot) {
+      if (!active[slot]) continue;
+      k_convert<T, true><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(P, static_cast<cpx<T>*>(canon) + slot * per, g1,
+                                                                     slot);
+    }
   }
 
   static void spectra(const Ctx& x, const void* state, double* out, int flags, hipStream_t s) {
@@ -1700,6 +1811,7 @@ struct Engine {
     o.get_state = &get_state;
     o.set_state = &set_state;
     o.spectra = &spectra;
+    o.pressure = &pressure;
     return o;
   }
 };

@@ -81,6 +81,7 @@ _SIGS = {
     "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_set_graph": (ctypes.c_int, [_c_void_p, _c_int32]),
+    "psdns_pressure": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "psdns_get_schedule_info": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(ScheduleInfo)]),
     "psdns_set_schedule": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_tune": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
@@ -252,6 +253,13 @@ class Plan:
         """Per-slot dicts of shell spectra and statistics (copies to the host)."""
         raw = self.spectra_raw(state, ws, flags).cpu().numpy()
         return [parse_spectra(r, int(self.info.n_shells), self.n_scalars) for r in raw]
+
+    def pressure(self, state, ws):
+        """Modified pressure of every slot: complex tensor [batch, N, N, N/2+1] (canonical layout)."""
+        torch = _torch()
+        out = torch.empty((self.batch, self.n, self.n, self.n // 2 + 1), dtype=self.complex_dtype, device="cuda")
+        _check(lib().psdns_pressure(self._h, _ptr(state), _ptr(ws), _ptr(out), _stream()))
+        return out
 
     def set_graph(self, enable: bool) -> None:
         """Replay RK4 steps from a captured HIP graph (non-default streams only)."""

@@ -437,3 +437,35 @@ def test_scalar_variance_and_production_physical():
     prod = -2 * np.mean(f[3] * (g[0] * f[0] + g[1] * f[1] + g[2] * f[2]))
     assert abs(sp["production"][0] - prod) <= 1e-12 * abs(prod)
     assert abs(2 * sp["E_phi"][0].sum() - sp["phi_var"][0]) <= 1e-12 * sp["phi_var"][0]
+
+
+def test_pressure_of_taylor_green_vortex_closed_form():
+    """u = (sin x cos y, -cos x sin y, 0) is a steady Euler flow held by the pressure
+    p = (cos 2x + cos 2y)/4: u.grad u = -grad p exactly."""
+    N = 16
+    X, Y, Z = _grid(N)
+    u = [np.sin(X) * np.cos(Y), -np.cos(X) * np.sin(Y), np.zeros_like(X)]
+    st = np.stack([ora.to_spectral(f) for f in u])
+    p = ora.to_physical(ora.pressure(st))
+    ref = 0.25 * (np.cos(2 * X) + np.cos(2 * Y))
+    assert np.max(np.abs(p - ref)) < 1e-14
+
+
+def test_pressure_of_beltrami_flow_is_minus_kinetic_energy_density():
+    """ABC flow: omega = k0 u, so u.grad u = grad(|u|^2/2) and p = -|u|^2/2 up to its
+    mean (the k = 0 mode is held at zero)."""
+    N, k0 = 16, 2
+    st = np.stack(_abc(N, k0))
+    u = [ora.to_physical(st[i]) for i in range(3)]
+    q = 0.5 * (u[0] ** 2 + u[1] ** 2 + u[2] ** 2)
+    p = ora.to_physical(ora.pressure(st))
+    assert np.max(np.abs(p - (-(q - q.mean())))) < 1e-13 * np.max(q)
+
+
+def test_pressure_of_single_shear_mode_vanishes():
+    """u = (0, sin x, 0): u.grad u = 0 pointwise, so the pressure is zero."""
+    N = 16
+    X, Y, Z = _grid(N)
+    z = np.zeros_like(X)
+    st = np.stack([ora.to_spectral(f) for f in (z, np.sin(X), z)])
+    assert np.max(np.abs(ora.pressure(st))) < 1e-12
