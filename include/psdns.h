@@ -184,6 +184,16 @@ psdns_status psdns_get_state(psdns_plan* plan, const void* state, int32_t slot, 
 psdns_status psdns_set_state(psdns_plan* plan, void* state, int32_t slot, const void* canonical_in,
                              void* hip_stream);
 
+/* Stepping with statistics time series (the records the paper writes at a user-defined
+ * interval, Sec. 2.3): advances every active slot by nsteps steps exactly as psdns_step
+ * (same dt rule), and after every `every` steps appends one record block to the device
+ * buffer `records`: batch doubles of simulated time t per slot, then batch spectra
+ * records (psdns_spectra layout, `flags` as there).  floor(nsteps / every) blocks of
+ * batch * (1 + spectra_doubles) doubles are written; steps beyond the last full interval
+ * run without a record.  Asynchronous on the stream. */
+psdns_status psdns_run(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps, int32_t every,
+                       double* records, int32_t flags, void* hip_stream);
+
 /* Modified pressure (Sec. 2.2): p_hat(k) = i k.(u.grad u)^(k) / |k|^2 on the retained
  * modes, p_hat(0) = 0, in the transform convention of Eq. (5) (unnormalised like the
  * state).  Evaluated as -(|u|^2/2)^ - i k.(u x omega)^ / |k|^2, which equals it because

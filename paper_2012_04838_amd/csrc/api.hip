@@ -244,6 +244,12 @@ Ctx make_ctx(psdns_plan* plan, void* ws) {
   return c;
 }
 
+// simulated time of every slot into a record block
+__global__ void k_record_time(const DynDev* __restrict__ d, double* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = d[i].t;
+}
+
 __global__ void k_clear_dyn(DynDev* d, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
@@ -570,6 +576,30 @@ psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable) {
     HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
     plan->graph_exec = nullptr;
   }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_run(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps, int32_t every,
+                       double* records, int32_t flags, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!records) return fail(PSDNS_E_INVAL, "records must be a device pointer");
+  if (every < 1) return fail(PSDNS_E_INVAL, "every must be >= 1");
+  if (nsteps < 0) return fail(PSDNS_E_INVAL, "nsteps must be >= 0");
+  if (flags < 1 || flags > 3) return fail(PSDNS_E_INVAL, "flags must be a nonzero combination of PSDNS_SPECTRA_*");
+  const int B = plan->p.batch;
+  const size_t block = (size_t)B * (1 + plan->L.rec);
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  int done = 0;
+  for (int r = 0; done + every <= nsteps; ++r) {
+    if (psdns_status st = psdns_step(plan, state, ws, dt, every, hip_stream)) return st;
+    done += every;
+    double* blk = records + (size_t)r * block;
+    k_record_time<<<(B + 255) / 256, 256, 0, s>>>(reinterpret_cast<const DynDev*>(static_cast<char*>(ws) + plan->L.off_dyn),
+                                                  blk, B);
+    HIP_TRY(hipGetLastError());
+    if (psdns_status st = psdns_spectra(plan, state, ws, blk + B, flags, hip_stream)) return st;
+  }
+  if (done < nsteps) return psdns_step(plan, state, ws, dt, nsteps - done, hip_stream);
   return PSDNS_OK;
 }
 

@@ -82,6 +82,8 @@ _SIGS = {
     "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_set_graph": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_pressure": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
+    "psdns_run": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, ctypes.c_double, _c_int32, _c_int32, _c_void_p,
+                                 _c_int32, _c_void_p]),
     "psdns_get_schedule_info": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(ScheduleInfo)]),
     "psdns_set_schedule": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_tune": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
@@ -253,6 +255,27 @@ class Plan:
         """Per-slot dicts of shell spectra and statistics (copies to the host)."""
         raw = self.spectra_raw(state, ws, flags).cpu().numpy()
         return [parse_spectra(r, int(self.info.n_shells), self.n_scalars) for r in raw]
+
+    def run(self, state, ws, dt: float, nsteps: int, every: int, flags: int = SPECTRA_SHELLS | SPECTRA_MOMENTS):
+        """Step with a statistics time series: returns records[r][slot] as dicts of
+        parse_spectra plus "t", one record after every `every` steps."""
+        torch = _torch()
+        nrec = nsteps // every
+        rec = int(self.info.spectra_doubles)
+        buf = torch.empty((max(nrec, 1), self.batch * (1 + rec)), dtype=torch.float64, device="cuda")
+        _check(lib().psdns_run(self._h, _ptr(state), _ptr(ws), dt, nsteps, every, _ptr(buf), flags, _stream()))
+        raw = buf.cpu().numpy()
+        out = []
+        for r in range(nrec):
+            t = raw[r, :self.batch]
+            sp = raw[r, self.batch:].reshape(self.batch, rec)
+            row = []
+            for i in range(self.batch):
+                d = parse_spectra(sp[i], int(self.info.n_shells), self.n_scalars)
+                d["t"] = float(t[i])
+                row.append(d)
+            out.append(row)
+        return out
 
     def pressure(self, state, ws):
         """Modified pressure of every slot: complex tensor [batch, N, N, N/2+1] (canonical layout)."""

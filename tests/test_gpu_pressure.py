@@ -56,3 +56,39 @@ def test_pressure_of_taylor_green_vortex_on_gpu():
     st = np.stack([ora.to_spectral(f) for f in u])
     p = ora.to_physical(_gpu_pressure([st], 64)[0])
     assert np.max(np.abs(p - 0.25 * (np.cos(2 * X) + np.cos(2 * Y)))) < 1e-13
+
+
+def test_statistics_time_series_match_oracle_and_close_the_scalar_budget():
+    """psdns_run: one record every 4 steps; each record equals the oracle's statistics of
+    the oracle state at that step, and the scalar-variance rate from the recorded series
+    (central difference) matches production - chi of Eq. (13)."""
+    torch = torch_mod()
+    from tests.gpu_helpers import set_params
+
+    N, S, dt, every, nrec = 32, 1, 0.004, 4, 4
+    prm = ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1, k_force=2.0)
+    y = ora.init_field(N, S, 1, 4.0, 1.0)
+    plan = make_plan(N, S, 64)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    plan.set_state(st, y, 0)
+    plan.clear_step_info(ws)
+    recs = plan.run(st, ws, dt, every * nrec + 2, every)
+    torch.cuda.synchronize()
+    assert len(recs) == nrec
+    assert plan.read_step_info(ws)[0]["steps"] == every * nrec + 2
+    series = []
+    for r in range(nrec):
+        y = ora.step(y, prm, dt, every)
+        ref = ora.spectra(y, prm)
+        got = recs[r][0]
+        assert abs(got["t"] - (r + 1) * every * dt) < 1e-14
+        for k in ("K", "eps", "Re_lambda"):
+            assert abs(got[k] - ref[k]) <= 1e-12 * abs(ref[k])
+        assert abs(got["phi_var"][0] - ref["phi_var"][0]) <= 1e-12 * abs(ref["phi_var"][0])
+        series.append(got)
+    # central difference of <phi^2> over two intervals about the middle record
+    h = every * dt
+    rate = (series[2]["phi_var"][0] - series[0]["phi_var"][0]) / (2 * h)
+    budget = series[1]["production"][0] - series[1]["chi"][0]
+    assert abs(rate - budget) <= 2e-3 * abs(budget), (rate, budget)
