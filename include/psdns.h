@@ -72,13 +72,24 @@ typedef struct {
   int32_t batch;     /* number of independent realizations (slots), >= 1 */
 } psdns_plan_params;
 
+/* Forcing of the band 0 < |k| <= k_force (Eq. (1) term A U, Sec. 2.3).
+ * POWER: constant power, A = P / (2 E_f) evaluated at every RK stage from the stage input.
+ * HOLD:  the paper's deterministic scheme, evaluated once after the last stage of every
+ *        step: the band modes of u are scaled by sqrt(hold_energy / E_f), which keeps the
+ *        band energy at hold_energy (no forcing term inside the stages). */
+#define PSDNS_FORCING_POWER 0
+#define PSDNS_FORCING_HOLD 1
+
 /* Physical parameters of one slot (Sec. 2.1, Sec. 2.3, Table 2). */
 typedef struct {
   double nu;                              /* kinematic viscosity, >= 0 */
-  double power;                           /* forcing power P >= 0; 0 gives decaying turbulence */
+  double power;                           /* forcing power P >= 0 (POWER); 0 gives decaying turbulence */
   double k_force;                         /* forced band 0 < |k| <= k_force */
   double schmidt[PSDNS_MAX_SCALARS];      /* Sc_s = nu / D_s, > 0 */
   double mean_grad[PSDNS_MAX_SCALARS][3]; /* g_s = grad <Phi_s>; Eq. (3) has (0, beta, 0) */
+  int32_t forcing;                        /* PSDNS_FORCING_POWER (default 0) or PSDNS_FORCING_HOLD */
+  int32_t reserved;                       /* 0 */
+  double hold_energy;                     /* HOLD: target band energy E_f > 0 */
 } psdns_slot_params;
 
 /* Per-slot stepping record (host copy). */
@@ -140,7 +151,8 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
  * non-default stream captures the launches of one RK4 step the first time it sees a given
  * (state, ws, dt) and then replays that graph once per step; a different state, workspace
  * or dt re-captures.  Slot parameters and active flags are read by the kernels at replay
- * time, so psdns_set_slot needs no re-capture.  Steps on the default (NULL) stream are
+ * time, so psdns_set_slot needs no re-capture, except that switching slots into or out of
+ * PSDNS_FORCING_HOLD changes the step structure and re-captures.  Steps on the default (NULL) stream are
  * launched directly.  Timing events are not recorded for replayed steps. */
 psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable);
 

@@ -120,6 +120,10 @@ class Params:
     power     injected power P of the constant-power forcing
     k_force   forced band 0 < |k| <= k_F (Sec. 2.3)
     forcing   False gives decaying turbulence (Sec. 2.3)
+    forcing_mode  "power": constant power P, A re-evaluated at every stage (reading of
+              the configurations); "hold": the paper's deterministic scheme, applied
+              after the last stage only, holding the band energy at hold_energy
+    hold_energy   target band energy E_f of the "hold" mode
     """
     nu: float
     schmidt: Sequence[float] = field(default_factory=tuple)
@@ -127,6 +131,8 @@ class Params:
     power: float = 0.0
     k_force: float = 2.0
     forcing: bool = True
+    forcing_mode: str = "power"
+    hold_energy: float = 0.0
 
     @property
     def n_scalars(self) -> int:
@@ -156,10 +162,28 @@ def forcing_amplitude(uhat: np.ndarray, prm: Params) -> float:
     0 < |k| <= k_F, applied as A * u_hat on that band and re-evaluated at every
     RK stage from the stage input; A = 0 when forcing is off or E_f = 0.
     """
-    if not prm.forcing or prm.power == 0.0:
+    if not prm.forcing or prm.forcing_mode != "power" or prm.power == 0.0:
         return 0.0
     ef = band_energy(uhat, prm.k_force)
     return prm.power / (2.0 * ef) if ef > 0.0 else 0.0
+
+
+def band_hold(uhat: np.ndarray, prm: Params) -> np.ndarray:
+    """The paper's deterministic forcing (Sec. 2.3): evaluated once, after the last RK
+    stage, it keeps the energy of the band 0 < |k| <= k_F constant.  Applied as an
+    amplitude A over the step, exp(A h) = sqrt(E_target / E_f), i.e. the band modes of
+    the velocity are scaled by sqrt(E_target / E_f); the rest of the field is untouched.
+
+    reading: the target is the prescribed band energy hold_energy; nothing is done
+    when E_f = 0.
+    """
+    ef = band_energy(uhat, prm.k_force)
+    if ef <= 0.0:
+        return uhat
+    out = uhat.copy()
+    mask = band_mask(uhat.shape[-3], prm.k_force)
+    out[:, mask] *= math.sqrt(prm.hold_energy / ef)
+    return out
 
 
 def band_mask(N: int, k_force: float) -> np.ndarray:
@@ -318,6 +342,8 @@ def step(state: np.ndarray, prm: Params, dt: float | None = None, nsteps: int = 
         yc = e1 * y + h * eh * k3
         k4 = nonlinear(yc, prm, form)
         y = e1 * y + (h / 6.0) * (e1 * k1 + 2.0 * eh * (k2 + k3) + k4)
+        if prm.forcing and prm.forcing_mode == "hold":
+            y[:3] = band_hold(y[:3], prm)
     return (y, dts) if return_dts else y
 
 

@@ -219,6 +219,7 @@ struct psdns_plan {
   const void* graph_state = nullptr;
   const void* graph_ws = nullptr;
   double graph_dt = 0.0;
+  bool graph_hold = false;  // captured with the hold forcing's step structure
   int sched = 0;  // step schedule in use (psdns_set_schedule / psdns_tune)
 };
 
@@ -432,6 +433,12 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
       s.g[i][d] = prm->mean_grad[i][d];
     }
   }
+  if (prm->forcing != PSDNS_FORCING_POWER && prm->forcing != PSDNS_FORCING_HOLD)
+    return fail(PSDNS_E_INVAL, "forcing must be PSDNS_FORCING_POWER or PSDNS_FORCING_HOLD");
+  if (prm->forcing == PSDNS_FORCING_HOLD && (!(prm->hold_energy > 0.0) || !std::isfinite(prm->hold_energy)))
+    return fail(PSDNS_E_INVAL, "hold_energy must be finite and > 0 with PSDNS_FORCING_HOLD");
+  s.forcing = prm->forcing;
+  s.hold = prm->forcing == PSDNS_FORCING_HOLD ? prm->hold_energy : 0.0;
   s.active = active ? 1 : 0;
   plan->slots_host[slot] = s;
   HIP_TRY(hipMemcpy(plan->slots_dev + slot, &s, sizeof(SlotDev), hipMemcpyHostToDevice));
@@ -519,17 +526,24 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
   // Every stage's last pass also inverts the next stage input along z (it is in its
   // registers already), so only the first stage of a call runs the standalone z pass;
   // the very last stage of a direct call skips the unneeded inverse.
+  // With the hold forcing y_{n+1} is rescaled on the band after the last stage, so that
+  // stage cannot run the next step's z inverse: every step then starts with its own.
+  bool hold = false;
+  for (int i = 0; i < plan->p.batch; ++i)
+    hold = hold || (plan->slots_host[i].active && plan->slots_host[i].forcing == PSDNS_FORCING_HOLD);
   auto one_step = [&](const Ctx& cx, bool first, bool last) {
     for (int stage = 0; stage < 4; ++stage) {
       const void* sin = stage == 0 ? state : cx.ystage;
       int fl = kStageFuse;
-      if (first && stage == 0) fl |= kStageZinv;
-      if (last && stage == 3) fl &= ~kStageFuse;
+      if ((first || hold) && stage == 0) fl |= kStageZinv;
+      if ((last || hold) && stage == 3) fl &= ~kStageFuse;
       plan->ops.sched[plan->sched].rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
     }
+    if (hold) plan->ops.band_hold(cx, state, s);
   };
   if (plan->use_graph && s != nullptr && nsteps > 0) {
-    if (!plan->graph_exec || plan->graph_state != state || plan->graph_ws != ws || plan->graph_dt != dt) {
+    if (!plan->graph_exec || plan->graph_state != state || plan->graph_ws != ws || plan->graph_dt != dt ||
+        plan->graph_hold != hold) {
       if (plan->graph_exec) {
         HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
         plan->graph_exec = nullptr;
@@ -554,6 +568,7 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
       }
       plan->graph_state = state;
       plan->graph_ws = ws;
+      plan->graph_hold = hold;
       plan->graph_dt = dt;
     }
     // the captured step expects the z inverse of y_n: run it once, then replay

@@ -43,7 +43,8 @@ struct SlotDev {
   double diff[3 + kMaxScalars];     // diffusivity of each spectral field
   double g[kMaxScalars][3];         // mean scalar gradients
   int active;
-  int pad_;
+  int forcing;                      // PSDNS_FORCING_POWER or PSDNS_FORCING_HOLD
+  double hold;                      // target band energy of PSDNS_FORCING_HOLD
 };
 
 // Per-slot values written on the device while stepping (part of the workspace).
@@ -126,6 +127,8 @@ struct Ops {
   void (*set_state)(const Ctx&, void* state, int slot, const void* canon, hipStream_t);
   void (*spectra)(const Ctx&, const void* state, double* out, int flags, hipStream_t);
   void (*pressure)(const Ctx&, const void* state, void* canon, const int* active, hipStream_t);
+  // the hold forcing after the last stage of a step (slots in PSDNS_FORCING_HOLD)
+  void (*band_hold)(const Ctx&, void* state, hipStream_t);
 };
 
 template <int N>

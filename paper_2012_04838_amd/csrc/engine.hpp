@@ -1016,6 +1016,11 @@ k_forcing_amplitude(const cpx<T>* __restrict__ sin, const SlotDev* __restrict__ 
   const int slot = blockIdx.x;
   const SlotDev& sp = slots[slot];
   if (!sp.active) return;
+  if (sp.forcing != PSDNS_FORCING_POWER) {
+    // the hold scheme acts after the last stage only (k_band_hold)
+    if (threadIdx.x == 0) dyn[slot].A = 0.0;
+    return;
+  }
   int kf = 0;
   while ((double)(kf + 1) * (kf + 1) <= sp.kf2) ++kf;
   if (kf > g.K) kf = g.K;
@@ -1049,6 +1054,63 @@ k_forcing_amplitude(const cpx<T>* __restrict__ sin, const SlotDev* __restrict__ 
     const double n3 = double(g.N) * g.N * g.N;
     const double ef = red[0] / (n3 * n3);
     dyn[slot].A = (sp.power > 0.0 && ef > 0.0) ? sp.power / (2.0 * ef) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// band-energy hold (the paper's deterministic forcing, Sec. 2.3), after the last stage:
+// E_f of y_{n+1} over 0 < |k|^2 <= kf^2 (FP64, the summation order of
+// k_forcing_amplitude), then the band modes of u scaled by sqrt(target / E_f)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_band_hold(cpx<T>* __restrict__ state, const SlotDev* __restrict__ slots, Geom g) {
+  __shared__ double red[256];
+  const int slot = blockIdx.x;
+  const SlotDev& sp = slots[slot];
+  if (!sp.active || sp.forcing != PSDNS_FORCING_HOLD) return;
+  int kf = 0;
+  while ((double)(kf + 1) * (kf + 1) <= sp.kf2) ++kf;
+  if (kf > g.K) kf = g.K;
+  const int span = 2 * kf + 1;
+  const int ncand = (kf + 1) * span * span;
+  cpx<T>* base = state + (long long)slot * g.F * g.st_field;
+  auto mode_at = [&](int i, long long& o) {
+    const int kx = i % (kf + 1);
+    const int ky = (i / (kf + 1)) % span - kf;
+    const int kz = i / ((kf + 1) * span) - kf;
+    const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    const int kyc = ky >= 0 ? ky : ky + g.M;
+    const int kzc = kz >= 0 ? kz : kz + g.M;
+    o = st_row(kzc, kyc, g.M, g.PX) + kx;
+    return !(k2 == 0.0 || k2 > sp.kf2) ? (kx == 0 ? 1 : 2) : 0;
+  };
+  double e = 0.0;
+  for (int i = threadIdx.x; i < ncand; i += 256) {
+    long long o;
+    const int w = mode_at(i, o);
+    if (!w) continue;
+    double s = 0.0;
+    for (int f = 0; f < 3; ++f) {
+      const cpx<T> v = base[o + f * g.st_field];
+      s += double(v.x) * double(v.x) + double(v.y) * double(v.y);
+    }
+    e += (w == 1 ? 0.5 : 1.0) * s;
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double n3 = double(g.N) * g.N * g.N;
+  const double ef = red[0] / (n3 * n3);
+  if (!(ef > 0.0)) return;
+  const T fac = T(sqrt(sp.hold / ef));
+  for (int i = threadIdx.x; i < ncand; i += 256) {
+    long long o;
+    if (!mode_at(i, o)) continue;
+    for (int f = 0; f < 3; ++f) base[o + f * g.st_field] = fac * base[o + f * g.st_field];
   }
 }
 
@@ -1708,6 +1770,11 @@ struct Engine {
         static_cast<cpx<T>*>(state), const_cast<cpx<T>*>(static_cast<const cpx<T>*>(canon)), g, slot);
   }
 
+  static void band_hold(const Ctx& x, void* state, hipStream_t s) {
+    TimedLaunch tl(x.timer, KID_FORCE, s);
+    k_band_hold<T><<<x.g.batch, 256, 0, s>>>(static_cast<cpx<T>*>(state), x.slots, x.g);
+  }
+
   // pressure of every active slot into the canonical layout (one field per slot)
   static void pressure(const Ctx& x, const void* state, void* canon, const int* active, hipStream_t s) {
     using C0 = Cfg<N, T, 0>;
@@ -1812,6 +1879,7 @@ struct Engine {
     o.set_state = &set_state;
     o.spectra = &spectra;
     o.pressure = &pressure;
+    o.band_hold = &band_hold;
     return o;
   }
 };

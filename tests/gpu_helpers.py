@@ -18,8 +18,12 @@ def make_plan(N, S, prec, batch=1):
 
 
 def set_params(plan, slot, prm: "ora.Params", active=True):
-    plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing else 0.0), k_force=prm.k_force,
-                  schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad], active=active)
+    from paper_2012_04838_amd import psdns
+    hold = prm.forcing and prm.forcing_mode == "hold"
+    plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing and not hold else 0.0), k_force=prm.k_force,
+                  schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad], active=active,
+                  forcing=psdns.FORCING_HOLD if hold else psdns.FORCING_POWER,
+                  hold_energy=prm.hold_energy if hold else 0.0)
 
 
 def to_numpy(t):

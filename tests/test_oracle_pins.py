@@ -469,3 +469,37 @@ def test_pressure_of_single_shear_mode_vanishes():
     z = np.zeros_like(X)
     st = np.stack([ora.to_spectral(f) for f in (z, np.sin(X), z)])
     assert np.max(np.abs(ora.pressure(st))) < 1e-12
+
+
+def test_band_energy_hold_keeps_band_energy_and_leaves_other_modes():
+    """Hold forcing (applied after the last stage): the band energy after every step is
+    the target, modes outside the band are those of the unforced step, and band modes
+    are only rescaled (no change of direction)."""
+    N, S = 16, 1
+    y0 = ora.init_field(N, S, 3, 3.0, 1.0)
+    base = ora.Params(nu=0.02, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), k_force=2.0, forcing=False)
+    target = 0.8 * ora.band_energy(y0[:3], 2.0)
+    hold = ora.Params(nu=0.02, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), k_force=2.0,
+                      forcing_mode="hold", hold_energy=target)
+    free = ora.step(y0, base, 0.01, 1)
+    held = ora.step(y0, hold, 0.01, 1)
+    band = ora.band_mask(N, 2.0)
+    assert abs(ora.band_energy(held[:3], 2.0) - target) < 1e-15
+    assert np.array_equal(held[:, ~band], free[:, ~band])
+    fb, hb = free[:3][:, band], held[:3][:, band]
+    i = np.unravel_index(np.argmax(np.abs(fb)), fb.shape)
+    c = hb[i] / fb[i]
+    assert abs(c.imag) < 1e-15 and c.real > 0
+    assert np.max(np.abs(hb - c.real * fb)) <= 1e-14 * np.max(np.abs(fb))
+    more = ora.step(held, hold, 0.01, 4)
+    assert abs(ora.band_energy(more[:3], 2.0) - target) < 1e-15
+
+
+def test_band_energy_hold_makes_beltrami_flow_stationary():
+    """An ABC flow on a shell inside the band is an exact solution whose unforced decay is
+    exp(-nu k0^2 t); holding its band energy at the initial value makes it stationary."""
+    N, k0, nu = 16, 2, 0.05
+    st = np.stack(_abc(N, k0))
+    prm = ora.Params(nu=nu, k_force=2.0, forcing_mode="hold", hold_energy=ora.band_energy(st, 2.0))
+    out = ora.step(st, prm, 0.03, 5)
+    assert np.max(np.abs(out - st)) <= 1e-13 * np.max(np.abs(st))
