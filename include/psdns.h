@@ -80,6 +80,15 @@ typedef struct {
 #define PSDNS_FORCING_POWER 0
 #define PSDNS_FORCING_HOLD 1
 
+/* Time integrator (Sec. 2.2-2.3).
+ * IF:       classical RK4 in the frame of the viscous/diffusive integrating factor
+ *           exp(-D |k|^2 t) (Lawson): the linear terms are integrated exactly.
+ * EXPLICIT: the paper's classical RK4 with the viscous and diffusive terms evaluated in
+ *           every stage like the others (stable while D |k|^2 dt stays inside the RK4
+ *           stability region, about 2.78). */
+#define PSDNS_INTEGRATOR_IF 0
+#define PSDNS_INTEGRATOR_EXPLICIT 1
+
 /* Physical parameters of one slot (Sec. 2.1, Sec. 2.3, Table 2). */
 typedef struct {
   double nu;                              /* kinematic viscosity, >= 0 */
@@ -88,7 +97,7 @@ typedef struct {
   double schmidt[PSDNS_MAX_SCALARS];      /* Sc_s = nu / D_s, > 0 */
   double mean_grad[PSDNS_MAX_SCALARS][3]; /* g_s = grad <Phi_s>; Eq. (3) has (0, beta, 0) */
   int32_t forcing;                        /* PSDNS_FORCING_POWER (default 0) or PSDNS_FORCING_HOLD */
-  int32_t reserved;                       /* 0 */
+  int32_t integrator;                     /* PSDNS_INTEGRATOR_IF (default 0) or PSDNS_INTEGRATOR_EXPLICIT */
   double hold_energy;                     /* HOLD: target band energy E_f > 0 */
 } psdns_slot_params;
 

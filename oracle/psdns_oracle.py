@@ -124,6 +124,9 @@ class Params:
               the configurations); "hold": the paper's deterministic scheme, applied
               after the last stage only, holding the band energy at hold_energy
     hold_energy   target band energy E_f of the "hold" mode
+    integrator    "if": RK4 in the frame of the viscous/diffusive integrating factor
+              (reading of the configurations); "explicit": the paper's classical RK4
+              with the viscous and diffusive terms evaluated in every stage (Sec. 2.3)
     """
     nu: float
     schmidt: Sequence[float] = field(default_factory=tuple)
@@ -133,6 +136,7 @@ class Params:
     forcing: bool = True
     forcing_mode: str = "power"
     hold_energy: float = 0.0
+    integrator: str = "if"
 
     @property
     def n_scalars(self) -> int:
@@ -332,6 +336,16 @@ def step(state: np.ndarray, prm: Params, dt: float | None = None, nsteps: int = 
     for _ in range(nsteps):
         h = dt if cfl is None else cfl_dt(y, cfl)
         dts.append(h)
+        if prm.integrator == "explicit":
+            # the paper's scheme (Sec. 2.3): classical RK4 on the full right-hand side
+            k1 = rhs(y, prm, form)
+            k2 = rhs(y + 0.5 * h * k1, prm, form)
+            k3 = rhs(y + 0.5 * h * k2, prm, form)
+            k4 = rhs(y + h * k3, prm, form)
+            y = y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+            if prm.forcing and prm.forcing_mode == "hold":
+                y[:3] = band_hold(y[:3], prm)
+            continue
         e1 = np.exp(L * h)
         eh = np.exp(L * (0.5 * h))
         k1 = nonlinear(y, prm, form)

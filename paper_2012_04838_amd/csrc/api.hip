@@ -437,6 +437,9 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
     return fail(PSDNS_E_INVAL, "forcing must be PSDNS_FORCING_POWER or PSDNS_FORCING_HOLD");
   if (prm->forcing == PSDNS_FORCING_HOLD && (!(prm->hold_energy > 0.0) || !std::isfinite(prm->hold_energy)))
     return fail(PSDNS_E_INVAL, "hold_energy must be finite and > 0 with PSDNS_FORCING_HOLD");
+  if (prm->integrator != PSDNS_INTEGRATOR_IF && prm->integrator != PSDNS_INTEGRATOR_EXPLICIT)
+    return fail(PSDNS_E_INVAL, "integrator must be PSDNS_INTEGRATOR_IF or PSDNS_INTEGRATOR_EXPLICIT");
+  s.integrator = prm->integrator;
   s.forcing = prm->forcing;
   s.hold = prm->forcing == PSDNS_FORCING_HOLD ? prm->hold_energy : 0.0;
   s.active = active ? 1 : 0;

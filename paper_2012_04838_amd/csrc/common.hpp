@@ -45,6 +45,8 @@ struct SlotDev {
   int active;
   int forcing;                      // PSDNS_FORCING_POWER or PSDNS_FORCING_HOLD
   double hold;                      // target band energy of PSDNS_FORCING_HOLD
+  int integrator;                   // PSDNS_INTEGRATOR_IF or PSDNS_INTEGRATOR_EXPLICIT
+  int pad_;
 };
 
 // Per-slot values written on the device while stepping (part of the workspace).

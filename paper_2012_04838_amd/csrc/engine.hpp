@@ -746,36 +746,45 @@ struct StageArgs {
 // Stage update of one mode.  Returns the input of the next stage (y_stage for
 // stages 0-2, y_{n+1} after stage 3); y_stage is stored only when write_ys.  The
 // mode sits at byte offsets (vo, so) inside the field that starts foff entries
-// into each state array.
+// into each state array.  F is the right-hand side without the linear term
+// -lk2 y (lk2 = D |k|^2).  Integrating factor (expl = false): the stage formulas of
+// Lawson's RK4 with exp(-lk2 h/2) and exp(-lk2 h) (FP64, then cast).  Explicit: the
+// same formulas with both factors 1 and F completed by -lk2 times the stage input,
+// which is classical RK4 on the full right-hand side.
 template <typename T>
 __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so, cpx<T> F,
-                                            double lk2, double h, bool write_ys = true) {
-  // lk2 = D |k|^2; exponential factors in FP64, then cast
+                                            double lk2, double h, bool write_ys, bool expl) {
   if (a.stage < 0) {
     const cpx<T> y = bload(make_buf<T>(a.sin + foff), vo, so);
     bstore(make_buf<T>(a.rhs + foff), vo, so, F - T(lk2) * y);
     return czero<T>();
   }
   const Buf<T> yn = make_buf<T>(a.yn + foff), acc = make_buf<T>(a.acc + foff);
-  const double ehd = exp(-0.5 * lk2 * h);
-  const T eh = T(ehd), e1 = T(ehd * ehd);
+  const cpx<T> y = a.stage < 3 ? bload(yn, vo, so) : czero<T>();
+  T eh, e1;
+  if (expl) {
+    const cpx<T> yin = a.stage == 0 ? y : bload(make_buf<T>(a.sin + foff), vo, so);
+    F = F - T(lk2) * yin;
+    eh = e1 = T(1);
+  } else {
+    const double ehd = exp(-0.5 * lk2 * h);
+    eh = T(ehd);
+    e1 = T(ehd * ehd);
+  }
   const T th = T(h);
   cpx<T> nxt;
   switch (a.stage) {
     case 0: {
-      const cpx<T> y = bload(yn, vo, so);
       bstore(acc, vo, so, e1 * (y + (th / T(6)) * F));
       nxt = eh * (y + (th / T(2)) * F);
       break;
     }
     case 1: {
-      const cpx<T> y = bload(yn, vo, so);
       bstore(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
       nxt = eh * y + (th / T(2)) * F;
       break;
     }
     case 2: {
-      const cpx<T> y = bload(yn, vo, so);
       bstore(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
       nxt = e1 * y + (th * eh) * F;
       break;
@@ -831,6 +840,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   const int ky = wave_of_compact(kyc, g.K, g.M);
   const double h = dyn[slot].dt;
   const double A = dyn[slot].A;
+  const bool expl = sp.integrator == PSDNS_INTEGRATOR_EXPLICIT;
   const T scale = T(1) / (T(N) * T(N) * T(N));
 
   const int kxy2 = kx * kx + ky * ky;
@@ -883,7 +893,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       if (state_at(m, vo, so)) {
         const double k2m_ = k2m(m);
         const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
-        nxt = rk_update(sa, foff, vo, so, F, dif * k2m_, h, !FUSE);
+        nxt = rk_update(sa, foff, vo, so, F, dif * k2m_, h, !FUSE || expl, expl);
       }
       a[m] = nxt;
     }
@@ -923,10 +933,11 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
           }
         }
         const double lk2 = nu * k2m_;
-        const bool wys = !FUSE || band;
-        n1 = rk_update(sa, f1, vo, so, F1, lk2, h, wys);
-        n2 = rk_update(sa, f2, vo, so, F2, lk2, h, wys);
-        n3 = rk_update(sa, f3, vo, so, F3, lk2, h, wys);
+        // the next stage reads y_stage on the band (forcing) and, explicit, everywhere
+        const bool wys = !FUSE || band || expl;
+        n1 = rk_update(sa, f1, vo, so, F1, lk2, h, wys, expl);
+        n2 = rk_update(sa, f2, vo, so, F2, lk2, h, wys, expl);
+        n3 = rk_update(sa, f3, vo, so, F3, lk2, h, wys, expl);
       }
       c1[m] = n1;
       c2[m] = n2;

@@ -32,13 +32,15 @@ class PlanParams(ctypes.Structure):
 
 FORCING_POWER = 0
 FORCING_HOLD = 1
+INTEGRATOR_IF = 0
+INTEGRATOR_EXPLICIT = 1
 
 
 class SlotParams(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("power", ctypes.c_double), ("k_force", ctypes.c_double),
                 ("schmidt", ctypes.c_double * MAX_SCALARS),
                 ("mean_grad", (ctypes.c_double * 3) * MAX_SCALARS),
-                ("forcing", _c_int32), ("reserved", _c_int32), ("hold_energy", ctypes.c_double)]
+                ("forcing", _c_int32), ("integrator", _c_int32), ("hold_energy", ctypes.c_double)]
 
 
 class StepInfo(ctypes.Structure):
@@ -202,10 +204,11 @@ class Plan:
     # ---------------------------------------------------------------- calls
     def set_slot(self, slot: int, nu: float, power: float = 0.0, k_force: float = 2.0,
                  schmidt: Sequence[float] = (), mean_grad: Sequence[Sequence[float]] = (),
-                 active: bool = True, forcing: int = FORCING_POWER, hold_energy: float = 0.0) -> None:
+                 active: bool = True, forcing: int = FORCING_POWER, hold_energy: float = 0.0,
+                 integrator: int = INTEGRATOR_IF) -> None:
         sp = SlotParams()
         sp.nu, sp.power, sp.k_force = nu, power, k_force
-        sp.forcing, sp.hold_energy = forcing, hold_energy
+        sp.forcing, sp.hold_energy, sp.integrator = forcing, hold_energy, integrator
         for i in range(MAX_SCALARS):
             sp.schmidt[i] = schmidt[i] if i < len(schmidt) else 1.0
             g = mean_grad[i] if i < len(mean_grad) else (0.0, 0.0, 0.0)

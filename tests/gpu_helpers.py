@@ -23,7 +23,8 @@ def set_params(plan, slot, prm: "ora.Params", active=True):
     plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing and not hold else 0.0), k_force=prm.k_force,
                   schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad], active=active,
                   forcing=psdns.FORCING_HOLD if hold else psdns.FORCING_POWER,
-                  hold_energy=prm.hold_energy if hold else 0.0)
+                  hold_energy=prm.hold_energy if hold else 0.0,
+                  integrator=psdns.INTEGRATOR_EXPLICIT if prm.integrator == "explicit" else psdns.INTEGRATOR_IF)
 
 
 def to_numpy(t):
