@@ -144,6 +144,20 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
 psdns_status psdns_init_field(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed,
                               double k_peak, double kinetic_energy, void* hip_stream);
 
+/* The same field from another initial spectrum shape (Sec. 2.3):
+ *   PSDNS_SPECTRUM_CONFIG  E(k) ~ k^4 exp(-2 (k/k_param)^2)              (as psdns_init_field)
+ *   PSDNS_SPECTRUM_PAPER   the paper's spectrum (after Lamorgese et al.) with k_F = k_param:
+ *                          E(k) = (u_rms^2/k_F) (k/k_F)^2 for k <= k_F, (u_rms^2/k_F) (k/k_F)^(-5/3)
+ *                          beyond; the shape only matters, the field is scaled to kinetic_energy. */
+#define PSDNS_SPECTRUM_CONFIG 0
+#define PSDNS_SPECTRUM_PAPER 1
+psdns_status psdns_init_field_spectrum(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed,
+                                       int32_t spectrum, double k_param, double kinetic_energy, void* hip_stream);
+
+/* Set the scalars of one slot to zero and keep its velocity: the paper's way of starting
+ * the scalar on a developed velocity field (phi_0 = 0, Sec. 2.3).  Asynchronous. */
+psdns_status psdns_zero_scalars(psdns_plan* plan, void* state, int32_t slot, void* hip_stream);
+
 /* Full right-hand side dy/dt (Eqs. (7)-(8), including the viscous and diffusive
  * terms) of every active slot of `state`, written to `out` (state layout).
  * `out` must not alias `state`. */

@@ -395,7 +395,16 @@ def init_spectrum(kappa: np.ndarray, k_peak: float) -> np.ndarray:
     return kappa ** 4 * np.exp(-2.0 * (kappa / k_peak) ** 2)
 
 
-def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy: float = 1.0) -> np.ndarray:
+def paper_spectrum(kappa: np.ndarray, k_f: float, u_rms: float = 1.0) -> np.ndarray:
+    """The paper's initial spectrum (Sec. 2.3, after Lamorgese et al.):
+    E = (u_rms^2 / k_F) (kappa/k_F)^2 for kappa <= k_F and (u_rms^2 / k_F) (kappa/k_F)^(-5/3) beyond."""
+    q = np.asarray(kappa / k_f, dtype=np.float64)
+    upper = np.where(q > 1.0, q, 1.0) ** (-5.0 / 3.0)
+    return (u_rms * u_rms / k_f) * np.where(q <= 1.0, q * q, upper)
+
+
+def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy: float = 1.0,
+               spectrum: str = "config") -> np.ndarray:
     """Rogallo-type random divergence-free isotropic velocity (Sec. 2.3) with phi = 0 (Sec. 2.3,
     scalar started from zero).
 
@@ -409,6 +418,7 @@ def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy:
     The kx = 0 plane is completed by u_hat(-k) = conj(u_hat(k)), and the field is
     scaled so that K = 1/2 <u.u> equals `kinetic_energy` (reading: "unit kinetic
     energy" of the configurations; the paper's TKE magnification is a factor on K).
+    spectrum="paper" uses the paper's spectrum with k_F = k_peak instead of E(k) above.
     """
     K = kmax_retained(N)
     NX = N // 2 + 1
@@ -423,7 +433,8 @@ def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy:
     lin = (iz.astype(np.uint64) * np.uint64(N) + iy.astype(np.uint64)) * np.uint64(NX) + ix.astype(np.uint64)
     k1, k2, k3 = KX[sel], KY[sel], KZ[sel]
     kmag = np.sqrt(k1 * k1 + k2 * k2 + k3 * k3)
-    amp = np.sqrt(init_spectrum(kmag, k_peak) / (4.0 * math.pi * kmag * kmag))
+    espec = paper_spectrum(kmag, k_peak) if spectrum == "paper" else init_spectrum(kmag, k_peak)
+    amp = np.sqrt(espec / (4.0 * math.pi * kmag * kmag))
     # e1 = k x z_hat / |k x z_hat| = (ky, -kx, 0)/sqrt(kx^2+ky^2)
     kp = np.sqrt(k1 * k1 + k2 * k2)
     along_z = kp == 0

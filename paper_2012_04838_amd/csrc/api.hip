@@ -448,18 +448,37 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
   return PSDNS_OK;
 }
 
-psdns_status psdns_init_field(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed, double k_peak,
-                              double kinetic_energy, void* hip_stream) {
+psdns_status psdns_init_field_spectrum(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed,
+                                       int32_t spectrum, double k_param, double kinetic_energy, void* hip_stream) {
   if (psdns_status s = check_plan(plan)) return s;
   if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
   if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
-  if (!(k_peak > 0.0) || !std::isfinite(k_peak)) return fail(PSDNS_E_INVAL, "k_peak must be > 0");
+  if (spectrum != PSDNS_SPECTRUM_CONFIG && spectrum != PSDNS_SPECTRUM_PAPER)
+    return fail(PSDNS_E_INVAL, "spectrum must be PSDNS_SPECTRUM_CONFIG or PSDNS_SPECTRUM_PAPER");
+  if (!(k_param > 0.0) || !std::isfinite(k_param)) return fail(PSDNS_E_INVAL, "k_peak / k_force must be > 0");
   if (!(kinetic_energy >= 0.0) || !std::isfinite(kinetic_energy))
     return fail(PSDNS_E_INVAL, "kinetic_energy must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
-  plan->ops.init_field(c, state, slot, seed, k_peak, kinetic_energy, s);
+  plan->ops.init_field(c, state, slot, seed, k_param, spectrum, kinetic_energy, s);
+  HIP_TRY(hipGetLastError());
+  return PSDNS_OK;
+}
+
+psdns_status psdns_init_field(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed, double k_peak,
+                              double kinetic_energy, void* hip_stream) {
+  return psdns_init_field_spectrum(plan, state, ws, slot, seed, PSDNS_SPECTRUM_CONFIG, k_peak, kinetic_energy,
+                                   hip_stream);
+}
+
+psdns_status psdns_zero_scalars(psdns_plan* plan, void* state, int32_t slot, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state) return fail(PSDNS_E_INVAL, "state must be a device pointer");
+  if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
+  Ctx c{};
+  c.g = plan->L.g;
+  plan->ops.zero_scalars(c, state, slot, static_cast<hipStream_t>(hip_stream));
   HIP_TRY(hipGetLastError());
   return PSDNS_OK;
 }

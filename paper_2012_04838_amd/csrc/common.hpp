@@ -123,7 +123,7 @@ struct StepSched {
 struct Ops {
   int nsched;
   StepSched sched[kMaxSched];
-  void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, double energy,
+  void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, int spectrum, double energy,
                      hipStream_t);
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);
   void (*set_state)(const Ctx&, void* state, int slot, const void* canon, hipStream_t);
@@ -131,6 +131,7 @@ struct Ops {
   void (*pressure)(const Ctx&, const void* state, void* canon, const int* active, hipStream_t);
   // the hold forcing after the last stage of a step (slots in PSDNS_FORCING_HOLD)
   void (*band_hold)(const Ctx&, void* state, hipStream_t);
+  void (*zero_scalars)(const Ctx&, void* state, int slot, hipStream_t);
 };
 
 template <int N>

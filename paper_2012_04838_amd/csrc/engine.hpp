@@ -1176,14 +1176,22 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counte
 }
 __device__ __forceinline__ double unit_double(uint64_t x) { return double(x >> 11) * (1.0 / 9007199254740992.0); }
 
+// Initial energy spectrum shape E(kappa): kind 0 the configured kappa^4 exp(-2 (kappa/kp)^2);
+// kind 1 the paper's spectrum (Sec. 2.3, after Lamorgese et al.) with kp = k_F:
+// (1/k_F) (kappa/k_F)^2 up to k_F and (1/k_F) (kappa/k_F)^(-5/3) beyond (u_rms = 1).
+static __device__ double init_spectrum(double kmag, double kp, int kind) {
+  const double q = kmag / kp;
+  if (kind == 1) return (q <= 1.0 ? q * q : pow(q, -5.0 / 3.0)) / kp;
+  return kmag * kmag * kmag * kmag * exp(-2.0 * q * q);
+}
+
 // Coefficient vector of the canonical mode (kx, ky, kz) before the energy scaling.
-static __device__ void rogallo_mode(int kx, int ky, int kz, int N, uint64_t seed, double kp, double (&re)[3],
-                             double (&im)[3]) {
+static __device__ void rogallo_mode(int kx, int ky, int kz, int N, uint64_t seed, double kp, int kind,
+                                    double (&re)[3], double (&im)[3]) {
   const double fx = kx, fy = ky, fz = kz;
   const double k2 = fx * fx + fy * fy + fz * fz;
   const double kmag = sqrt(k2);
-  const double q = kmag / kp;
-  const double spec = kmag * kmag * kmag * kmag * exp(-2.0 * q * q);
+  const double spec = init_spectrum(kmag, kp, kind);
   const double amp = sqrt(spec / (4.0 * 3.14159265358979323846 * kmag * kmag));
   const double kperp = sqrt(fx * fx + fy * fy);
   double e1[3], e2[3];
@@ -1213,23 +1221,23 @@ static __device__ void rogallo_mode(int kx, int ky, int kz, int N, uint64_t seed
 }
 
 // coefficient of any retained mode (mirror modes of the kx = 0 plane by conjugation)
-static __device__ void init_coeff(int kx, int ky, int kz, int N, uint64_t seed, double kp, double (&re)[3],
-                           double (&im)[3]) {
+static __device__ void init_coeff(int kx, int ky, int kz, int N, uint64_t seed, double kp, int kind,
+                                  double (&re)[3], double (&im)[3]) {
   if (kx == 0 && ky == 0 && kz == 0) {
     for (int c = 0; c < 3; ++c) re[c] = im[c] = 0.0;
     return;
   }
   const bool canon = kx > 0 || (kx == 0 && ky > 0) || (kx == 0 && ky == 0 && kz > 0);
   if (canon) {
-    rogallo_mode(kx, ky, kz, N, seed, kp, re, im);
+    rogallo_mode(kx, ky, kz, N, seed, kp, kind, re, im);
   } else {
-    rogallo_mode(0, -ky, -kz, N, seed, kp, re, im);
+    rogallo_mode(0, -ky, -kz, N, seed, kp, kind, re, im);
     for (int c = 0; c < 3; ++c) im[c] = -im[c];
   }
 }
 
 static __global__ void __launch_bounds__(256)
-k_init_energy(Geom g, uint64_t seed, double kp, double* __restrict__ part) {
+k_init_energy(Geom g, uint64_t seed, double kp, int kind, double* __restrict__ part) {
   __shared__ double red[256];
   const long long nmodes = (long long)g.M * g.M * g.KX;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -1239,7 +1247,7 @@ k_init_energy(Geom g, uint64_t seed, double kp, double* __restrict__ part) {
     const int kyc = (int)((i / g.KX) % g.M);
     const int kzc = (int)(i / ((long long)g.KX * g.M));
     double re[3], im[3];
-    init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, re, im);
+    init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, kind, re, im);
     double s = 0.0;
     for (int c = 0; c < 3; ++c) s += re[c] * re[c] + im[c] * im[c];
     e = (kx == 0 ? 0.5 : 1.0) * s;
@@ -1273,7 +1281,8 @@ k_init_scale(const double* __restrict__ part, int nblocks, double energy, int N,
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_init_write(cpx<T>* __restrict__ st, Geom g, int slot, uint64_t seed, double kp, const DynDev* __restrict__ d) {
+k_init_write(cpx<T>* __restrict__ st, Geom g, int slot, uint64_t seed, double kp, int kind,
+             const DynDev* __restrict__ d) {
   const long long nmodes = (long long)g.M * g.M * g.KX;
   const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   if (i >= nmodes) return;
@@ -1281,7 +1290,7 @@ k_init_write(cpx<T>* __restrict__ st, Geom g, int slot, uint64_t seed, double kp
   const int kyc = (int)((i / g.KX) % g.M);
   const int kzc = (int)(i / ((long long)g.KX * g.M));
   double re[3], im[3];
-  init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, re, im);
+  init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, kind, re, im);
   const double sc = d->scratch;
   const long long o = st_row(kzc, kyc, g.M, g.PX) + kx;
   cpx<T>* base = st + (long long)slot * g.F * g.st_field;
@@ -1752,15 +1761,15 @@ template <int N, typename T>
 struct Engine {
   using C = Cfg<N, T>;
 
-  static void init_field(const Ctx& x, void* state, int slot, uint64_t seed, double kp, double energy,
+  static void init_field(const Ctx& x, void* state, int slot, uint64_t seed, double kp, int kind, double energy,
                          hipStream_t s) {
     const Geom& g = x.g;
     const long long nmodes = (long long)g.M * g.M * g.KX;
     const int nb = (int)((nmodes + 255) / 256);
     TimedLaunch tl(x.timer, KID_AUX, s);
-    k_init_energy<<<nb, 256, 0, s>>>(g, seed, kp, x.part);
+    k_init_energy<<<nb, 256, 0, s>>>(g, seed, kp, kind, x.part);
     k_init_scale<<<1, 256, 0, s>>>(x.part, nb, energy, g.N, x.dyn + slot);
-    k_init_write<T><<<nb, 256, 0, s>>>(static_cast<cpx<T>*>(state), g, slot, seed, kp, x.dyn + slot);
+    k_init_write<T><<<nb, 256, 0, s>>>(static_cast<cpx<T>*>(state), g, slot, seed, kp, kind, x.dyn + slot);
   }
 
   static void get_state(const Ctx& x, const void* state, int slot, void* canon, hipStream_t s) {
@@ -1779,6 +1788,15 @@ struct Engine {
     TimedLaunch tl(x.timer, KID_AUX, s);
     k_convert<T, false><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(
         static_cast<cpx<T>*>(state), const_cast<cpx<T>*>(static_cast<const cpx<T>*>(canon)), g, slot);
+  }
+
+  static void zero_scalars(const Ctx& x, void* state, int slot, hipStream_t s) {
+    const Geom& g = x.g;
+    const long long n = (long long)g.S * g.st_field;
+    if (n == 0) return;
+    cpx<T>* p = static_cast<cpx<T>*>(state) + (long long)slot * g.F * g.st_field + 3 * g.st_field;
+    TimedLaunch tl(x.timer, KID_AUX, s);
+    k_fill_zero<T><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(p, n);
   }
 
   static void band_hold(const Ctx& x, void* state, hipStream_t s) {
@@ -1891,6 +1909,7 @@ struct Engine {
     o.spectra = &spectra;
     o.pressure = &pressure;
     o.band_hold = &band_hold;
+    o.zero_scalars = &zero_scalars;
     return o;
   }
 };

@@ -34,6 +34,8 @@ FORCING_POWER = 0
 FORCING_HOLD = 1
 INTEGRATOR_IF = 0
 INTEGRATOR_EXPLICIT = 1
+SPECTRUM_CONFIG = 0
+SPECTRUM_PAPER = 1
 
 
 class SlotParams(ctypes.Structure):
@@ -80,6 +82,9 @@ _SIGS = {
     "psdns_set_slot": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(SlotParams), _c_int32]),
     "psdns_init_field": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.c_uint64,
                                         ctypes.c_double, ctypes.c_double, _c_void_p]),
+    "psdns_init_field_spectrum": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.c_uint64,
+                                                 _c_int32, ctypes.c_double, ctypes.c_double, _c_void_p]),
+    "psdns_zero_scalars": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_rhs": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "psdns_step": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, ctypes.c_double, _c_int32, _c_void_p]),
     "psdns_read_step_info": (ctypes.c_int, [_c_void_p, _c_void_p, ctypes.POINTER(StepInfo), _c_void_p]),
@@ -219,6 +224,14 @@ class Plan:
     def init_field(self, state, ws, slot: int, seed: int, k_peak: float, kinetic_energy: float = 1.0) -> None:
         _check(lib().psdns_init_field(self._h, _ptr(state), _ptr(ws), slot, seed, k_peak, kinetic_energy,
                                       _stream()))
+
+    def init_field_spectrum(self, state, ws, slot: int, seed: int, spectrum: int, k_param: float,
+                            kinetic_energy: float = 1.0) -> None:
+        _check(lib().psdns_init_field_spectrum(self._h, _ptr(state), _ptr(ws), slot, seed, spectrum, k_param,
+                                               kinetic_energy, _stream()))
+
+    def zero_scalars(self, state, slot: int) -> None:
+        _check(lib().psdns_zero_scalars(self._h, _ptr(state), slot, _stream()))
 
     def rhs(self, state, out, ws) -> None:
         _check(lib().psdns_rhs(self._h, _ptr(state), _ptr(out), _ptr(ws), _stream()))

@@ -546,3 +546,32 @@ def test_explicit_and_integrating_factor_rk4_agree_to_fourth_order():
         diffs.append(np.linalg.norm(a - b))
     rates = [math.log2(diffs[i] / diffs[i + 1]) for i in range(2)]
     assert all(3.6 < r < 4.4 for r in rates), rates
+
+
+def test_paper_spectrum_initial_field_shells_follow_the_spectrum():
+    """Rogallo field from the paper's piecewise spectrum (k_F = 3): exact K, solenoidal, and
+    shell energies following (k/k_F)^2 below k_F and (k/k_F)^(-5/3) above, within the
+    sampling scatter of the random phases."""
+    N, kf = 64, 3.0
+    st = ora.init_field(N, 1, 5, kf, 1.0, spectrum="paper")
+    assert abs(ora.kinetic_energy_of(st) - 1.0) < 1e-13
+    kx, ky, kz = ora.kgrid(N)
+    div = kx * st[0] + ky * st[1] + kz * st[2]
+    assert np.max(np.abs(div)) < 1e-10 * np.max(np.abs(st[:3]))
+    assert np.max(np.abs(st[3])) == 0.0
+    E = ora.spectra(st, ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),)))["E"]
+    sh = ora.shell_index(N)
+    mask = ora.retained_mask(N)
+    w = ora.half_weights(N)
+    kk = np.sqrt(ora.k_squared(N))
+    model = np.array([float(np.sum(w * ((sh == s) & mask) *
+                                   (kf ** 2 * np.where(kk / kf <= 1, (kk / kf) ** 2, (kk / kf) ** (-5.0 / 3.0)) /
+                                    (4 * np.pi * np.where(kk > 0, kk, 1) ** 2))))
+                      for s in range(len(E))])
+    model *= E.sum() / model.sum()
+    for s in range(2, 18):
+        cnt = float(np.sum(((sh == s) & mask) * w))
+        assert abs(E[s] / model[s] - 1.0) < 4.0 / math.sqrt(cnt), s
+    # the two branches meet at k_F: the spectrum is continuous there
+    assert abs(float(ora.paper_spectrum(np.array(kf * (1 - 1e-12)), kf)) -
+               float(ora.paper_spectrum(np.array(kf * (1 + 1e-12)), kf))) < 1e-10
