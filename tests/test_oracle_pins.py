@@ -564,9 +564,9 @@ def test_paper_spectrum_initial_field_shells_follow_the_spectrum():
     mask = ora.retained_mask(N)
     w = ora.half_weights(N)
     kk = np.sqrt(ora.k_squared(N))
-    model = np.array([float(np.sum(w * ((sh == s) & mask) *
-                                   (kf ** 2 * np.where(kk / kf <= 1, (kk / kf) ** 2, (kk / kf) ** (-5.0 / 3.0)) /
-                                    (4 * np.pi * np.where(kk > 0, kk, 1) ** 2))))
+    q = np.where(kk > 0, kk, 1.0) / kf
+    shape = np.where(q <= 1, q ** 2, q ** (-5.0 / 3.0))  # the stated piecewise law, written out
+    model = np.array([float(np.sum(w * ((sh == s) & mask) * shape / (4 * np.pi * np.where(kk > 0, kk, 1) ** 2)))
                       for s in range(len(E))])
     model *= E.sum() / model.sum()
     for s in range(2, 18):
