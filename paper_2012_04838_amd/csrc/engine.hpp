@@ -111,6 +111,10 @@ struct ColCfg {
 #ifndef PSDNS_FUSED_DB
 #define PSDNS_FUSED_DB 0
 #endif
+// velocity components of the z-update pass fetched one ahead of their transform
+#ifndef PSDNS_FUSED_PF
+#define PSDNS_FUSED_PF 1
+#endif
 #ifndef PSDNS_YF_DB
 #define PSDNS_YF_DB PSDNS_COL_DB
 #endif
@@ -848,11 +852,11 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     const int kz = wave_of(j + TT * m, N);
     return double(kxy2 + kz * kz);
   };
-  auto load_fwd = [&](int f, cpx<T> (&v)[E]) {
+  // forward data of A field f into v (the loads are issued; the transform comes later)
+  auto fetch = [&](int f, cpx<T> (&v)[E]) {
     const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
-    fft<N, E, false>(v, lds, j, tw);
   };
   auto store_a = [&](int f, const cpx<T> (&v)[E]) {
     if (!valid) return;
@@ -883,7 +887,8 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   // scalars: F = -a_hat (a already holds u.grad phi + g.u)
   for (int s = g.S - 1; s >= 0; --s) {
     cpx<T> a[E];
-    load_fwd(3 + s, a);
+    fetch(3 + s, a);
+    fft<N, E, false>(a, lds, j, tw);
     const double dif = sp.diff[3 + s];
     const long long foff = sslot + (long long)(3 + s) * g.st_field;
 #pragma unroll
@@ -902,9 +907,22 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   // velocity: F = P(k) c_hat + A 1_band u_hat
   {
     cpx<T> c1[E], c2[E], c3[E];
-    load_fwd(0, c1);
-    load_fwd(1, c2);
-    load_fwd(2, c3);
+#if PSDNS_FUSED_PF
+    // the next component's loads are in flight while the current one is transformed
+    fetch(0, c1);
+    fetch(1, c2);
+    fft<N, E, false>(c1, lds, j, tw);
+    fetch(2, c3);
+    fft<N, E, false>(c2, lds, j, tw);
+    fft<N, E, false>(c3, lds, j, tw);
+#else
+    fetch(0, c1);
+    fft<N, E, false>(c1, lds, j, tw);
+    fetch(1, c2);
+    fft<N, E, false>(c2, lds, j, tw);
+    fetch(2, c3);
+    fft<N, E, false>(c3, lds, j, tw);
+#endif
     const double nu = sp.nu;
     const long long f1 = sslot, f2 = sslot + g.st_field, f3 = sslot + 2 * g.st_field;
 #pragma unroll
