@@ -166,8 +166,9 @@ struct Cfg {
   static constexpr int EC = Col::EC;
   static constexpr int TC = Col::TC;
   static constexpr int COL_THREADS = Col::THREADS;
-  // x pass: a line never spans two wavefronts (TX <= 64)
-  static constexpr int EX0 = N > 512 ? N / 64 : 8;
+  // x pass: 8 elements per lane; lines of N <= 512 stay inside one wavefront, a line of
+  // N = 1024 spans two
+  static constexpr int EX0 = 8;
   static constexpr int EX = N < EX0 ? N : EX0;
   static constexpr int TX = N / EX;
   static constexpr int LX0 = 256 / TX * D.xl2 / 2;
@@ -410,11 +411,60 @@ struct XLine {
   static constexpr int E = Cfg<N, T>::EX, TT = Cfg<N, T>::TX;
   static constexpr int K = (N - 1) / 3;
   static constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
-  static_assert(TT <= 64 && 64 % TT == 0, "a line must stay inside one wavefront");
+  // a line inside one wavefront exchanges with its mirror lane by a cross-lane permute;
+  // a line over several wavefronts goes through LDS (block barriers)
+  static constexpr bool kMulti = TT > 64;
+  static_assert((TT <= 64 && 64 % TT == 0) || TT % 64 == 0, "lines must tile wavefronts");
   static_assert(NQ < E, "retained band must be shorter than the line");
-  int j, partner;
-  __device__ __forceinline__ explicit XLine(int tid)
-      : j(tid % TT), partner(((tid & 63) - tid % TT) + ((TT - tid % TT) & (TT - 1))) {}
+  using Sync = std::conditional_t<kMulti, BlockSync, WaveSync>;
+  // LDS entries of the mirror exchange per block thread (kMulti)
+  static constexpr int kXch = kMulti ? 2 * NQ : 0;
+  int j, partner;  // partner: lane in the wavefront, or thread in the block (kMulti)
+  cpx<T>* xs;      // exchange area [2 NQ][blockDim] (kMulti)
+  __device__ __forceinline__ explicit XLine(int tid, cpx<T>* xch = nullptr)
+      : j(tid % TT),
+        partner(kMulti ? (tid - tid % TT) + ((TT - tid % TT) & (TT - 1))
+                       : ((tid & 63) - tid % TT) + ((TT - tid % TT) & (TT - 1))),
+        xs(xch) {}
+  __device__ __forceinline__ void mirror1(const cpx<T> (&v)[NQ], cpx<T> (&p)[NQ]) const {
+    if constexpr (kMulti) {
+      const int nt = blockDim.x;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) xs[q * nt + threadIdx.x] = v[q];
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) p[q] = xs[q * nt + partner];
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) p[q] = shfl_c(v[q], partner);
+    }
+  }
+  // values of the mirror lane: p[q] = v[q] of thread `partner`, q < NQ (two arrays at once)
+  __device__ __forceinline__ void mirror(const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&pa)[NQ],
+                                         cpx<T> (&pb)[NQ]) const {
+    if constexpr (kMulti) {
+      const int nt = blockDim.x;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        xs[q * nt + threadIdx.x] = va[q];
+        xs[(NQ + q) * nt + threadIdx.x] = vb[q];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        pa[q] = xs[q * nt + partner];
+        pb[q] = xs[(NQ + q) * nt + partner];
+      }
+      __syncthreads();
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        pa[q] = shfl_c(va[q], partner);
+        pb[q] = shfl_c(vb[q], partner);
+      }
+    }
+  }
   __device__ __forceinline__ T kx(int q) const { return T(j + TT * q); }
   // r[q] = entry kx = j + TT q of the line at p (zero beyond K); at kx = 0 only the
   // real part is kept, as a complex-to-real transform does.
@@ -429,6 +479,10 @@ struct XLine {
   // h at positions n = j + TT m from the half-spectrum entries of f (va) and g (vb):
   // n <= K: va + i vb;  n >= N - K: conj(va) + i conj(vb) of kx = N - n;  else 0
   __device__ __forceinline__ void build(const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) const {
+    // multi-wave lines gather the mirror lane's entries through LDS first; single-wave
+    // lines permute each one where it is needed (fewer live registers)
+    cpx<T> ma[NQ], mb[NQ];
+    if constexpr (kMulti) mirror(va, vb, ma, mb);
     static_for<0, E>([&](auto mc) {
       constexpr int m = decltype(mc)::value;
       const int n = j + TT * m;
@@ -444,8 +498,13 @@ struct XLine {
         constexpr int q0 = E - m;      // own slot when j == 0
         cpx<T> pa = czero<T>(), pb = czero<T>();
         if constexpr (q1 < NQ) {
-          pa = shfl_c(va[q1], partner);
-          pb = shfl_c(vb[q1], partner);
+          if constexpr (kMulti) {
+            pa = ma[q1];
+            pb = mb[q1];
+          } else {
+            pa = shfl_c(va[q1], partner);
+            pb = shfl_c(vb[q1], partner);
+          }
         }
         if (j == 0) {
           if constexpr (q0 < NQ) {
@@ -475,46 +534,51 @@ __global__ void PSDNS_X_BOUNDS(Cfg<N, T, V>::X_THREADS)
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
          double* __restrict__ maxpart, Geom g, int mode) {
   using C = Cfg<N, T, V>;
+  using XL = XLine<N, T>;
+  using XS = typename XL::Sync;
   constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
   constexpr int K = (N - 1) / 3;
-  constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
-  static_assert(TT <= 64 && 64 % TT == 0, "a line must stay inside one wavefront");
-  static_assert(NQ < E, "retained band must be shorter than the line");
+  constexpr int NQ = XL::NQ;  // unique entries per lane and field
   __shared__ cpx<T> smem[L * LP];
   __shared__ cpx<T> stw[N];
   __shared__ double red[C::X_THREADS];
+  __shared__ cpx<T> xch[XL::kXch > 0 ? XL::kXch * C::X_THREADS : 1];
   const int slot = blockIdx.y;
   if (!slots[slot].active) return;
   stage_twiddles<N>(stw, tw_g);
   const int li = threadIdx.x / TT;
   const int j = threadIdx.x % TT;
-  // FP32: the lane's twiddles live in registers for all nine transforms of the
-  // line; FP64 keeps them in LDS to leave registers for the line data.
-  constexpr bool kRegTw = sizeof(T) == 4;
+  // FP32 up to N = 512: the lane's twiddles live in registers for all nine transforms
+  // of the line; FP64, and the 16-element lines of N = 1024, keep them in LDS to leave
+  // registers for the line data.
+  constexpr bool kLong = E > 8;
+  constexpr bool kRegTw = sizeof(T) == 4 && !kLong;
   using TwT = std::conditional_t<kRegTw, TwReg<N, E, T>, const cpx<T>*>;
   TwT tw;
   if constexpr (kRegTw)
     tw = tw_fill<N, E>(j, stw);
   else
     tw = stw;
-  const int lane = threadIdx.x & 63;
-  const int partner = (lane - j) + ((TT - j) & (TT - 1));
   const long long line = (long long)blockIdx.x * L + li;  // z * N + y
   const LdsLine<T, N, E> lds{smem + li * LP};
   cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
 
-  const XLine<N, T> xl(threadIdx.x);
+  const XL xl(threadIdx.x, xch);
   auto load = [&](int f, cpx<T> (&r)[NQ]) { xl.load(base + (long long)f * g.b_field, r); };
   auto build = [&](const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) { xl.build(va, vb, h); };
   auto kxq = [&](int q) { return T(j + TT * q); };
 
+  // short lines load every input up front; 16-element lines load u3/omega1 and
+  // u1/u2 only when their transform comes (registers)
   cpx<T> r0[NQ], r1[NQ], r2[NQ], r3[NQ], r4[NQ], r5[NQ];
   load(1, r1);
   load(2, r2);
   load(4, r4);
   load(5, r5);
-  load(3, r3);
-  load(0, r0);
+  if constexpr (!kLong) {
+    load(3, r3);
+    load(0, r0);
+  }
   cpx<T> h[E], va[NQ], vb[NQ];
   // omega2 = dz u1 - dx u3, omega3 = dx u2 - dy u1
 #pragma unroll
@@ -523,7 +587,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     vb[q] = mul_is(r1[q], kxq(q)) - r5[q];
   }
   build(va, vb, h);
-  fft<N, E, true, WaveSync>(h, lds, j, tw);
+  fft<N, E, true, XS>(h, lds, j, tw);
   T w2p[E], w3p[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -531,8 +595,9 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     w3p[m] = h[m].y;
   }
   // u3, omega1
+  if constexpr (kLong) load(3, r3);
   build(r2, r3, h);
-  fft<N, E, true, WaveSync>(h, lds, j, tw);
+  fft<N, E, true, XS>(h, lds, j, tw);
   T u3p[E], w1p[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -540,6 +605,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     w1p[m] = h[m].y;
   }
   // u1, u2
+  if constexpr (kLong) load(0, r0);
   build(r0, r1, h);
   const int S = g.S;
   // first scalar pair's entries go in flight before the next transforms
@@ -554,9 +620,9 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       load(11 + 3 * s, s5);
     }
   };
-  constexpr bool kPrefetchScalars = sizeof(T) == 4;
+  constexpr bool kPrefetchScalars = sizeof(T) == 4 && !kLong;
   if (kPrefetchScalars && S > 0) load_scalar_pair(0);
-  fft<N, E, true, WaveSync>(h, lds, j, tw);
+  fft<N, E, true, XS>(h, lds, j, tw);
   T u1p[E], u2p[E], c1[E], c2[E], c3[E];
   T mx = T(0);
 #pragma unroll
@@ -574,10 +640,14 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   auto forward_pair = [&](const T (&p)[E], const T (&q)[E], int fp, int fq) {
 #pragma unroll
     for (int m = 0; m < E; ++m) h[m] = {p[m], q[m]};
-    fft<N, E, false, WaveSync>(h, lds, j, tw);
+    fft<N, E, false, XS>(h, lds, j, tw);
+    cpx<T> hm[NQ], pm[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) hm[q] = h[E - q - 1];
+    xl.mirror1(hm, pm);
     static_for<0, NQ>([&](auto sc) {
       constexpr int s = decltype(sc)::value;
-      cpx<T> zm = shfl_c(h[E - s - 1], partner);
+      cpx<T> zm = pm[s];
       if (j == 0) zm = h[(E - s) % E];
       const cpx<T> zk = h[s];
       const cpx<T> zc = conj(zm);
@@ -615,7 +685,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 #pragma unroll
         for (int q = 0; q < NQ; ++q) va[q] = mul_is(s0[q], kxq(q));
         build(va, s1, h);
-        fft<N, E, true, WaveSync>(h, lds, j, tw);
+        fft<N, E, true, XS>(h, lds, j, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m)
           as0[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
@@ -625,7 +695,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 #pragma unroll
         for (int q = 0; q < NQ; ++q) va[q] = mul_is(s3[q], kxq(q));
         build(va, s4, h);
-        fft<N, E, true, WaveSync>(h, lds, j, tw);
+        fft<N, E, true, XS>(h, lds, j, tw);
 #pragma unroll
         for (int m = 0; m < E; ++m)
           as1[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
@@ -636,7 +706,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
         for (int q = 0; q < NQ; ++q) s5[q] = czero<T>();
       }
       build(s2, s5, h);
-      fft<N, E, true, WaveSync>(h, lds, j, tw);
+      fft<N, E, true, XS>(h, lds, j, tw);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         as0[m] += u3p[m] * h[m].x;
@@ -1526,10 +1596,11 @@ k_x_moments(const cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, Ge
   __shared__ cpx<T> smem[L * LP];
   __shared__ cpx<T> stw[N];
   __shared__ double red[C::X_THREADS];
+  __shared__ cpx<T> xch[XL::kXch > 0 ? XL::kXch * C::X_THREADS : 1];
   const int slot = blockIdx.y;
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
-  const XL xl(threadIdx.x);
+  const XL xl(threadIdx.x, xch);
   const int li = threadIdx.x / TT, j = xl.j;
   const LdsLine<T, N, E> lds{smem + li * LP};
   double mom[6][3];
@@ -1552,7 +1623,7 @@ k_x_moments(const cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, Ge
         for (int q = 0; q < NQ; ++q) rb[q] = czero<T>();
       }
       xl.build(ra, rb, h);
-      fft<N, E, true, WaveSync>(h, lds, j, tw);
+      fft<N, E, true, typename XL::Sync>(h, lds, j, tw);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const double vx = h[m].x, vy = h[m].y;

@@ -100,3 +100,37 @@ def test_1024_fp32_single_realization_properties():
     info = plan.read_step_info(ws)[0]
     assert info["flags"] == 0 and info["steps"] == 2 and np.isfinite(info["max_u"])
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_1024_rhs_of_analytic_field(prec):
+    """u = (sin z, sin x, 0), phi = sin y, g = (0, 1, 0), nu = 0 at 1024^3 (lines of the x
+    pass span two wavefronts here): du2/dt = -cos x sin z and dphi/dt = -sin x cos y - sin x,
+    every other coefficient zero.  Built and checked in the canonical layout on the device."""
+    torch = torch_mod()
+    n = 1024
+    plan = make_plan(n, 1, prec)
+    plan.set_slot(0, nu=0.0, power=0.0, schmidt=[1.0], mean_grad=[[0.0, 1.0, 0.0]])
+    ct = torch.complex128 if prec == 64 else torch.complex64
+    c = float(n) ** 3
+    can = torch.zeros((4, n, n, n // 2 + 1), dtype=ct, device="cuda")
+    can[0, 1, 0, 0], can[0, n - 1, 0, 0] = -0.5j * c, 0.5j * c   # sin z
+    can[1, 0, 0, 1] = -0.5j * c                                    # sin x
+    can[3, 0, 1, 0], can[3, 0, n - 1, 0] = -0.5j * c, 0.5j * c   # sin y
+    st, out, ws = plan.new_state(), plan.new_state(), plan.new_workspace()
+    plan.set_state(st, can, 0)
+    del can
+    plan.rhs(st, out, ws)
+    F = plan.get_state(out, 0)
+    torch.cuda.synchronize()
+    # expected coefficients (half spectrum kx = 1 carries every term)
+    F[1, 1, 0, 1] -= 0.25j * c          # -cos x sin z: e^{i(x+z)}
+    F[1, n - 1, 0, 1] -= -0.25j * c     #               e^{i(x-z)}
+    F[3, 0, 1, 1] -= 0.25j * c          # -sin x cos y: e^{i(x+y)}
+    F[3, 0, n - 1, 1] -= 0.25j * c      #               e^{i(x-y)}
+    F[3, 0, 0, 1] -= 0.5j * c           # -sin x
+    err = float(torch.max(torch.abs(F))) / c
+    print(f"[fullsize] 1024^3 FP{prec} analytic rhs: max coefficient error / N^3 = {err:.2e}", flush=True)
+    assert err < (1e-13 if prec == 64 else 1e-6)
+    del F, st, out, ws
+    torch.cuda.empty_cache()
