@@ -105,7 +105,7 @@ def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3):
     if tune_reps > 0:
         # autotuner (outside the timed region): every compiled schedule on this state
         best, ms_each = plan.tune(st, ws, tune_reps)
-        sched = {"chosen": best, "ms_per_rhs": ms_each, "chosen_desc": plan.schedule_info(best)}
+        sched = {"chosen": best, "ms_per_stage": ms_each, "chosen_desc": plan.schedule_info(best)}
     plan.step(st, ws, -0.5, warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()

@@ -199,11 +199,14 @@ psdns_status psdns_get_schedule_info(const psdns_plan* plan, int32_t index, psdn
  * re-captured on the next graph step).  PSDNS_E_INVAL for an index outside
  * [0, n_schedules). */
 psdns_status psdns_set_schedule(psdns_plan* plan, int32_t index);
-/* Autotuner: times `reps` right-hand-side evaluations of `state` (every active slot) with
- * each schedule after one untimed evaluation, selects the fastest and returns the mean
- * milliseconds per evaluation in host array ms_out[n_schedules] (may be NULL) and its index
- * in *best (may be NULL).  The evaluations write into the workspace accumulator, which
- * holds nothing between steps; `state` is not modified.  Synchronises the stream. */
+/* Autotuner: times `reps` RK stages of every active slot of `state` with each schedule
+ * (after one untimed trial), selects the fastest and returns the mean milliseconds per
+ * stage in host array ms_out[n_schedules] (may be NULL) and its index in *best (may be
+ * NULL).  A trial is the stage of a multi-step call that every step repeats (forcing
+ * amplitude, y inverse, x pass, y forward, z forward with the update and the next
+ * stage's z inverse); it writes only workspace buffers that a step rebuilds (the
+ * accumulator, the stage input, the transform buffers) and leaves `state` and the step
+ * records untouched.  Synchronises the stream. */
 psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
                         int32_t* best, void* hip_stream);
 

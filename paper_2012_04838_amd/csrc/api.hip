@@ -515,11 +515,14 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
   int b = 0;
   for (int i = 0; i < plan->ops.nsched && err == hipSuccess; ++i) {
     RhsStageFn f = plan->ops.sched[i].rhs_stage;
-    // one untimed evaluation, then reps timed ones; dy/dt goes to the accumulator,
-    // which holds nothing between steps
-    f(c, const_cast<void*>(state), state, -1, c.acc, 0, 0.0, kStageZinv, s);
+    // one untimed trial, then reps timed ones.  A trial is a steady-state RK stage of a
+    // multi-step call (stage 1: forcing amplitude, y inverse, x pass, y forward and the
+    // fused z pass); it reads the state and writes only workspace buffers (accumulator,
+    // stage input on the band, transform buffers), all of which a step rebuilds.
+    void* st = const_cast<void*>(state);
+    f(c, st, c.ystage, 1, nullptr, 0, 0.0, kStageFuse, s);
     err = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) f(c, const_cast<void*>(state), state, -1, c.acc, 0, 0.0, kStageZinv, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) f(c, st, c.ystage, 1, nullptr, 0, 0.0, kStageFuse, s);
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float t = 0.f;

@@ -140,8 +140,10 @@ constexpr bool col_prefetch() {
 struct Sched {
   int ec32, ec64, bytes, ef32, ef64, fb32, fb64, xl2;
 };
+// bytes 0: the default of the size, 128-byte rows up to N = 512 and 64-byte rows above,
+// where 1024-thread blocks of 128-byte rows would exceed the register budget.
 constexpr Sched kSched[] = {
-    {PSDNS_EC32, PSDNS_EC64, PSDNS_COL_BYTES, PSDNS_EF32, PSDNS_EF64, PSDNS_FB32, PSDNS_FB64, 2},  // default
+    {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2},  // default
     {4, 4, PSDNS_COL_BYTES, 4, 4, PSDNS_COL_BYTES, PSDNS_COL_BYTES, 2},                          // radix 4
     {16, 16, PSDNS_COL_BYTES, 16, 16, PSDNS_COL_BYTES, PSDNS_COL_BYTES, 2},                      // radix 16
     {PSDNS_EC32, PSDNS_EC64, 64, PSDNS_EF32, PSDNS_EF64, 64, 64, 2},                             // narrow tiles
@@ -149,18 +151,22 @@ constexpr Sched kSched[] = {
 };
 constexpr int kNumSched = (int)(sizeof(kSched) / sizeof(kSched[0]));
 static_assert(kNumSched <= kMaxSched, "schedule table exceeds the dispatch table");
-// schedules compiled for a grid size (the 1024^3 kernels are built once)
+// schedules compiled for a grid size
 template <int N>
 constexpr int sched_count() {
-  return N > 512 ? 1 : kNumSched;
+  return kNumSched;
+}
+template <int N>
+constexpr int row_bytes(int b, int dflt) {
+  return b > 0 ? b : (N > 512 ? 64 : dflt);
 }
 
 template <int N, typename T, int V = 0>
 struct Cfg {
   static constexpr Sched D = kSched[V];
   static constexpr bool F32 = sizeof(T) == 4;
-  using Col = ColCfg<N, T, F32 ? D.ec32 : D.ec64, D.bytes>;
-  using Fused = ColCfg<N, T, F32 ? D.ef32 : D.ef64, F32 ? D.fb32 : D.fb64>;
+  using Col = ColCfg<N, T, F32 ? D.ec32 : D.ec64, row_bytes<N>(D.bytes, PSDNS_COL_BYTES)>;
+  using Fused = ColCfg<N, T, F32 ? D.ef32 : D.ef64, row_bytes<N>(F32 ? D.fb32 : D.fb64, F32 ? PSDNS_FB32 : PSDNS_FB64)>;
   // columns per block and elements per thread of the column passes (z, y)
   static constexpr int W = Col::W;
   static constexpr int EC = Col::EC;

@@ -332,8 +332,8 @@ class Plan:
         self._refresh_info()
 
     def tune(self, state, ws, reps: int = 3):
-        """Time every schedule on `state` (right-hand-side evaluations), select the fastest;
-        returns (best index, [ms per evaluation of each schedule])."""
+        """Time every schedule on `state` (steady-state RK stages), select the fastest;
+        returns (best index, [ms per stage of each schedule])."""
         ms = (ctypes.c_double * self.n_schedules)()
         best = _c_int32()
         _check(lib().psdns_tune(self._h, _ptr(state), _ptr(ws), reps, ms, ctypes.byref(best), _stream()))

@@ -245,11 +245,18 @@ class Server:
                 self._launch(g)
         return bool(self.waiting) or any(g.busy() for g in self.groups.values())
 
-    def run(self, requests: List[Request], idle_sleep: float = 2e-4) -> List[Request]:
+    def run(self, requests: List[Request], idle_sleep: float = 2e-4, progress_every: int = 0) -> List[Request]:
+        import sys
+
         for r in requests:
             self.submit(r)
         self.t0 = time.perf_counter()
+        reported = 0
         while self.tick():
+            if progress_every and len(self.done) >= reported + progress_every:
+                reported = len(self.done) - len(self.done) % progress_every
+                print(f"[serve] {len(self.done)}/{len(requests)} done at {self.now():.1f} s", file=sys.stderr,
+                      flush=True)
             if all(g.event is None or not g.event.query() for g in self.groups.values()):
                 time.sleep(idle_sleep)
         return self.done
@@ -280,9 +287,16 @@ def make_mix(n_requests: int, rate: float, seed: int = 0, sizes=(64, 128, 256, 5
 
 def summarize(done: List[Request], wall: float, steps_n3: float) -> dict:
     lat = np.array([r.latency for r in done])
-    return {"requests": len(done), "wall_s": wall, "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
-            "requests_per_s": len(done) / wall, "N3_steps_per_s": steps_n3 / wall}
+    out = {"requests": len(done), "wall_s": wall, "p50_s": float(np.percentile(lat, 50)),
+           "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+           "requests_per_s": len(done) / wall, "N3_steps_per_s": steps_n3 / wall}
+    per = {}
+    for n in sorted({r.n for r in done}):
+        ln = np.array([r.latency for r in done if r.n == n])
+        per[str(n)] = {"requests": int(ln.size), "p50_s": float(np.percentile(ln, 50)),
+                       "p99_s": float(np.percentile(ln, 99))}
+    out["per_size"] = per
+    return out
 
 
 def main():
@@ -292,23 +306,32 @@ def main():
     ap = argparse.ArgumentParser(description="serve a Poisson mix of DNS requests on one GPU")
     ap.add_argument("--requests", type=int, default=100)
     ap.add_argument("--load", type=float, default=0.7, help="offered load as a fraction of measured capacity")
+    ap.add_argument("--loads", type=str, default="",
+                    help="comma-separated offered loads (a sweep); overrides --load")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--progress", type=int, default=50, help="report every this many completions (stderr)")
     args = ap.parse_args()
+    loads = [float(v) for v in args.loads.split(",")] if args.loads else [args.load]
     # saturated capacity: every request present at t = 0
     sat = make_mix(args.requests, 0.0, args.seed)
     srv = Server()
     t = time.perf_counter()
-    srv.run(sat)
-    cap = len(sat) / (time.perf_counter() - t)
+    done = srv.run(sat, progress_every=args.progress)
+    wall = time.perf_counter() - t
+    cap = len(sat) / wall
+    out = summarize(done, wall, srv.steps_done)
+    out.update(load="saturated")
     srv.close()
-    mix = make_mix(args.requests, args.load * cap, args.seed)
-    srv = Server()
-    t = time.perf_counter()
-    done = srv.run(mix)
-    out = summarize(done, time.perf_counter() - t, srv.steps_done)
-    out.update(saturated_requests_per_s=cap, load=args.load)
-    srv.close()
-    print(json.dumps(out))
+    print(json.dumps(out), flush=True)
+    for load in loads:
+        mix = make_mix(args.requests, load * cap, args.seed)
+        srv = Server()
+        t = time.perf_counter()
+        done = srv.run(mix, progress_every=args.progress)
+        out = summarize(done, time.perf_counter() - t, srv.steps_done)
+        out.update(saturated_requests_per_s=cap, load=load)
+        srv.close()
+        print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -76,12 +76,28 @@ def test_tune_selects_a_schedule_and_leaves_the_state_alone(tmp_path):
     st, ws = plan.new_state(), plan.new_workspace()
     plan.init_field(st, ws, 0, seed=3, k_peak=4.0)
     plan.init_field(st, ws, 1, seed=4, k_peak=4.0)
+    plan.step(st, ws, -0.5, 2)
     before = st.clone()
+    info0 = plan.read_step_info(ws)
     best, ms = plan.tune(st, ws, reps=2)
     torch.cuda.synchronize()
     assert len(ms) == plan.n_schedules and all(m > 0 for m in ms)
     assert best == int(np.argmin(ms)) and plan.schedule == best
     assert torch.equal(st, before)
+    info1 = plan.read_step_info(ws)
+    for a, b in zip(info0, info1):
+        assert a["steps"] == b["steps"] and a["t"] == b["t"] and a["flags"] == b["flags"]
+    # stepping after tuning matches stepping without it
+    ref = before.clone()
+    plan.step(st, ws, -0.5, 2)
+    plan2 = make_plan(N, S, 32, batch=2)
+    for slot in range(2):
+        set_params(plan2, slot, prm)
+    plan2.set_schedule(best)
+    ws2 = plan2.new_workspace()
+    plan2.step(ref, ws2, -0.5, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(st, ref)
     # cache: the second autotune takes the stored choice without timing
     cache = tune.TuneCache(str(tmp_path / "tune.json"))
     v = tune.autotune(plan, st, ws, cache=cache, reps=1)
