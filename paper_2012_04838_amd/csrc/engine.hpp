@@ -139,6 +139,9 @@ constexpr bool col_prefetch() {
 // z-update pass; xl2: lines per x-pass block relative to 256 threads, in halves.
 struct Sched {
   int ec32, ec64, bytes, ef32, ef64, fb32, fb64, xl2;
+  int xw = 0;    // x pass, FP32: minimum waves per SIMD for the register allocator (0: PSDNS_X_WAVES)
+  int xreg = 1;  // x pass, FP32: stage twiddles held in registers (else read from LDS)
+  int xpf = 1;   // x pass, FP32: first scalar pair loaded before the velocity transforms
 };
 // bytes 0: the default of the size, 128-byte rows up to N = 512 and 64-byte rows above,
 // where 1024-thread blocks of 128-byte rows would exceed the register budget.
@@ -148,6 +151,8 @@ constexpr Sched kSched[] = {
     {16, 16, PSDNS_COL_BYTES, 16, 16, PSDNS_COL_BYTES, PSDNS_COL_BYTES, 2},                      // radix 16
     {PSDNS_EC32, PSDNS_EC64, 64, PSDNS_EF32, PSDNS_EF64, 64, 64, 2},                             // narrow tiles
     {PSDNS_EC32, PSDNS_EC64, PSDNS_COL_BYTES, PSDNS_EF32, PSDNS_EF64, PSDNS_FB32, PSDNS_FB64, 1},  // small x blocks
+    // x pass at three waves per SIMD: twiddles from LDS, no early scalar loads
+    {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2, 3, 0, 0},
 };
 constexpr int kNumSched = (int)(sizeof(kSched) / sizeof(kSched[0]));
 static_assert(kNumSched <= kMaxSched, "schedule table exceeds the dispatch table");
@@ -180,6 +185,7 @@ struct Cfg {
   static constexpr int LX0 = 256 / TX * D.xl2 / 2;
   static constexpr int LX = LX0 < 1 ? 1 : (LX0 > 64 ? 64 : LX0);
   static constexpr int X_THREADS = LX * TX;
+  static constexpr int X_WAVES = (D.xw > 0 && F32) ? D.xw : PSDNS_X_WAVES;  // FP64 lines need the registers
   static constexpr int LP = LinePad<N>::value;
 };
 
@@ -536,7 +542,7 @@ constexpr int kXMax = 1;       // partial maxima of |u1|+|u2|+|u3| (CFL)
 constexpr int kXPressure = 2;  // with S = 0: forward field 3 is |u|^2/2 (pressure assembly)
 
 template <int N, typename T, int V>
-__global__ void PSDNS_X_BOUNDS(Cfg<N, T, V>::X_THREADS)
+__global__ void __launch_bounds__((Cfg<N, T, V>::X_THREADS), (Cfg<N, T, V>::X_WAVES))
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
          double* __restrict__ maxpart, Geom g, int mode) {
   using C = Cfg<N, T, V>;
@@ -558,7 +564,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   // of the line; FP64, and the 16-element lines of N = 1024, keep them in LDS to leave
   // registers for the line data.
   constexpr bool kLong = E > 8;
-  constexpr bool kRegTw = sizeof(T) == 4 && !kLong;
+  constexpr bool kRegTw = sizeof(T) == 4 && !kLong && C::D.xreg;
   using TwT = std::conditional_t<kRegTw, TwReg<N, E, T>, const cpx<T>*>;
   TwT tw;
   if constexpr (kRegTw)
@@ -626,7 +632,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       load(11 + 3 * s, s5);
     }
   };
-  constexpr bool kPrefetchScalars = sizeof(T) == 4 && !kLong;
+  constexpr bool kPrefetchScalars = sizeof(T) == 4 && !kLong && C::D.xpf;
   if (kPrefetchScalars && S > 0) load_scalar_pair(0);
   fft<N, E, true, XS>(h, lds, j, tw);
   T u1p[E], u2p[E], c1[E], c2[E], c3[E];
