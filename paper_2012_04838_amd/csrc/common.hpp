@@ -59,6 +59,10 @@ struct DynDev {
   long long steps;   // steps taken by psdns_step
   int flags;         // PSDNS_FLAG_* bits, sticky until psdns_clear_flags
   int pad_;
+  // running max of |u1|+|u2|+|u3| over the grid during the stage-0 x pass, as the bits
+  // of a non-negative double: their unsigned order is the numeric order (NaN above
+  // everything), so an integer atomic max gives the exact, order-independent result
+  unsigned long long umax;
 };
 
 enum KernelId {

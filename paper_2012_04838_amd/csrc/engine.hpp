@@ -544,7 +544,7 @@ constexpr int kXPressure = 2;  // with S = 0: forward field 3 is |u|^2/2 (pressu
 template <int N, typename T, int V>
 __global__ void __launch_bounds__((Cfg<N, T, V>::X_THREADS), (Cfg<N, T, V>::X_WAVES))
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
-         double* __restrict__ maxpart, Geom g, int mode) {
+         DynDev* __restrict__ dyn, Geom g, int mode) {
   using C = Cfg<N, T, V>;
   using XL = XLine<N, T>;
   using XS = typename XL::Sync;
@@ -751,7 +751,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) maxpart[(long long)slot * g.nblk_x + blockIdx.x] = red[0];
+    if (threadIdx.x == 0) atomicMax(&dyn[slot].umax, (unsigned long long)__double_as_longlong(red[0]));
   }
 }
 
@@ -1127,6 +1127,8 @@ k_forcing_amplitude(const cpx<T>* __restrict__ sin, const SlotDev* __restrict__ 
   const int slot = blockIdx.x;
   const SlotDev& sp = slots[slot];
   if (!sp.active) return;
+  // every stage starts a fresh grid maximum (only stage 0's x pass contributes to it)
+  if (threadIdx.x == 0) dyn[slot].umax = 0ull;
   if (sp.forcing != PSDNS_FORCING_POWER) {
     // the hold scheme acts after the last stage only (k_band_hold)
     if (threadIdx.x == 0) dyn[slot].A = 0.0;
@@ -1229,28 +1231,12 @@ k_band_hold(cpx<T>* __restrict__ state, const SlotDev* __restrict__ slots, Geom 
 // step size from the stage-0 maxima (Eq. (10)) and the step record
 // ---------------------------------------------------------------------------
 static __global__ void __launch_bounds__(256)
-k_step_dt(const double* __restrict__ maxpart, const SlotDev* __restrict__ slots, DynDev* __restrict__ dyn, Geom g,
-          double dt_arg) {
-  __shared__ double red[256];
+k_step_dt(const SlotDev* __restrict__ slots, DynDev* __restrict__ dyn, Geom g, double dt_arg) {
   const int slot = blockIdx.x;
   if (!slots[slot].active) return;
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < g.nblk_x; i += 256) {
-    const double v = maxpart[(long long)slot * g.nblk_x + i];
-    mx = (v > mx || v != v) ? v : mx;
-  }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) {
-      const double a = red[threadIdx.x], b = red[threadIdx.x + o];
-      red[threadIdx.x] = (b > a || b != b) ? b : a;
-    }
-    __syncthreads();
-  }
   if (threadIdx.x == 0) {
     DynDev& d = dyn[slot];
-    const double m = red[0];
+    const double m = __longlong_as_double((long long)d.umax);
     const double dx = 6.283185307179586476925286766559 / g.N;
     double dt = dt_arg;
     int fl = d.flags;
@@ -1828,11 +1814,11 @@ struct Step {
     }
     {
       TimedLaunch tl(x.timer, KID_XPASS, s);
-      k_x_pass<N, T, V><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, g, want_max ? kXMax : 0);
+      k_x_pass<N, T, V><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.dyn, g, want_max ? kXMax : 0);
     }
     if (stage == 0) {
       TimedLaunch tl(x.timer, KID_DT, s);
-      k_step_dt<<<g.batch, 256, 0, s>>>(x.part, x.slots, x.dyn, g, dt_arg);
+      k_step_dt<<<g.batch, 64, 0, s>>>(x.slots, x.dyn, g, dt_arg);
     }
     {
       TimedLaunch tl(x.timer, KID_YFWD, s);
@@ -1921,7 +1907,7 @@ struct Engine {
     TimedLaunch tl(x.timer, KID_AUX, s);
     k_z_inverse<N, T, 0><<<dim3(ntile, gp.M, gp.batch), C0::COL_THREADS, 0, s>>>(st, A, tw, x.slots, gp);
     k_y_inverse<N, T, 0><<<dim3(ntile, N, gp.batch), C0::COL_THREADS, 0, s>>>(A, B, tw, x.slots, gp);
-    k_x_pass<N, T, 0><<<dim3(gp.nblk_x, gp.batch), C0::X_THREADS, 0, s>>>(B, tw, x.slots, x.part, gp, kXPressure);
+    k_x_pass<N, T, 0><<<dim3(gp.nblk_x, gp.batch), C0::X_THREADS, 0, s>>>(B, tw, x.slots, x.dyn, gp, kXPressure);
     Geom gy = gp;
     gy.F = 4;  // c1, c2, c3, |u|^2/2
     k_y_forward<N, T, 0><<<dim3(ntile, N, gp.batch), C0::COL_THREADS, 0, s>>>(B, A, tw, x.slots, gy);

@@ -115,7 +115,7 @@ class Server:
 
     def __init__(self, hbm_budget: Optional[int] = None, precision: int = 32, use_graph: bool = True,
                  capacity=default_capacity, max_chunk: int = 16, autotune: bool = True,
-                 tune_cache: Optional[tune.TuneCache] = None):
+                 tune_cache: Optional[tune.TuneCache] = None, launch_ms: float = 25.0):
         import torch
 
         if hbm_budget is None:
@@ -126,6 +126,9 @@ class Server:
         self.use_graph = use_graph
         self.capacity = capacity
         self.max_chunk = max_chunk
+        # a launch covers about launch_ms of device time, so that a large group's steps do
+        # not hold up small groups that share a hardware queue with it
+        self.launch_ms = launch_ms
         self.autotune = autotune
         self.tune_cache = tune_cache if tune_cache is not None else (tune.TuneCache() if autotune else None)
         self.groups: Dict[Tuple[int, int], Group] = {}
@@ -197,7 +200,9 @@ class Server:
         active = [i for i, r in enumerate(g.slots) if r is not None and g.remaining[i] > 0]
         if not active:
             return
-        chunk = min(min(g.remaining[i] for i in active), self.max_chunk)
+        est_ms = 21.0 * (g.n / 512.0) ** 3 * (3 + g.s) / 5.0 * len(active)  # FP32 step time model
+        by_time = max(1, int(self.launch_ms / max(est_ms, 1e-3)))
+        chunk = min(min(g.remaining[i] for i in active), self.max_chunk, by_time)
         cfl = g.slots[active[0]].cfl
         with torch.cuda.stream(g.stream):
             g.plan.step(g.state, g.ws, -cfl, chunk)
