@@ -35,6 +35,7 @@ GRAD = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
 MEASURED_TRAFFIC = {
     "src": "2419b4769ec7f321",
     "workload": (512, 2, 32),
+    "schedule": 0,
     "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.1e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
               "z_forward_update_inverse": 5502.6e6},
 }
@@ -55,9 +56,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n: int, s: int, prec: int):
+def measured_traffic(kernel: str, n: int, s: int, prec: int, schedule: int):
+    """Counter bytes per launch of a kernel, if they were taken on these sources, this
+    workload and this schedule (spills and tile shapes change the traffic)."""
     t = MEASURED_TRAFFIC
-    if t["workload"] != (n, s, prec) or kernel not in t["bytes"] or t["src"] != kernel_source_digest():
+    if (t["workload"] != (n, s, prec) or t["schedule"] != schedule or kernel not in t["bytes"]
+            or t["src"] != kernel_source_digest()):
         return None
     return t["bytes"][kernel]
 
@@ -91,7 +95,7 @@ def step_bytes(n: int, s: int, prec: int) -> float:
     return 4.0 * (kb["y_inverse"] + kb["x_pass"] + kb["y_forward"] + kb["z_forward_update_inverse"])
 
 
-def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3):
+def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3, schedule=-1):
     import torch
 
     from paper_2012_04838_amd import psdns
@@ -102,7 +106,10 @@ def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3):
     ws = plan.new_workspace()
     plan.init_field(st, ws, 0, seed=seed, k_peak=KP, kinetic_energy=1.0)
     sched = None
-    if tune_reps > 0:
+    if schedule >= 0:
+        plan.set_schedule(schedule)
+        sched = {"chosen": schedule, "ms_per_stage": None, "chosen_desc": plan.schedule_info(schedule)}
+    elif tune_reps > 0:
         # autotuner (outside the timed region): every compiled schedule on this state
         best, ms_each = plan.tune(st, ws, tune_reps)
         sched = {"chosen": best, "ms_per_stage": ms_each, "chosen_desc": plan.schedule_info(best)}
@@ -218,6 +225,7 @@ def main():
                          "saturated capacity); 0 disables")
     ap.add_argument("--serve-load", type=float, default=0.7)
     ap.add_argument("--no-tune", action="store_true", help="run schedule 0 instead of the autotuned schedule")
+    ap.add_argument("--schedule", type=int, default=-1, help="run this schedule (no tuning); -1 tunes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -232,11 +240,11 @@ def main():
     n3 = float(n) ** 3
     copy = copy_reference(args.copy_gb) if args.copy_gb > 0 else None
     tr = 0 if args.no_tune else 3
-    r32 = run_gpu(n, s, 32, args.steps, args.warmup, tune_reps=tr)
+    r32 = run_gpu(n, s, 32, args.steps, args.warmup, tune_reps=tr, schedule=args.schedule)
     print(f"[bench] fp32 done: {r32['ms_total'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     r64 = None
     if not args.no_fp64:
-        r64 = run_gpu(n, s, 64, args.steps, args.warmup, tune_reps=tr)
+        r64 = run_gpu(n, s, 64, args.steps, args.warmup, tune_reps=tr, schedule=args.schedule)
         print(f"[bench] fp64 done: {r64['ms_total'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
 
     ms32 = r32["ms_total"] / args.steps
@@ -247,7 +255,8 @@ def main():
     launches, tot = tim[dom]
     avg_ms = tot / max(launches, 1)
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
-    traffic = measured_traffic(dom, n, s, 32)
+    chosen = r32["schedule"]["chosen"] if r32["schedule"] else 0
+    traffic = measured_traffic(dom, n, s, 32, chosen)
     per_kernel = {k: {"launches": tim[k][0], "avg_ms": tim[k][1] / max(tim[k][0], 1),
                       "alg_GB_per_launch": kb[k] / 1e9 if k in kb else None,
                       "alg_GBs": (kb[k] / (tim[k][1] / max(tim[k][0], 1) * 1e-3) / 1e9) if k in kb and tim[k][0] else None}

@@ -153,6 +153,8 @@ constexpr Sched kSched[] = {
     {PSDNS_EC32, PSDNS_EC64, PSDNS_COL_BYTES, PSDNS_EF32, PSDNS_EF64, PSDNS_FB32, PSDNS_FB64, 1},  // small x blocks
     // x pass at three waves per SIMD: twiddles from LDS, no early scalar loads
     {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2, 3, 0, 0},
+    // the same with the twiddles kept in registers
+    {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2, 3, 1, 0},
 };
 constexpr int kNumSched = (int)(sizeof(kSched) / sizeof(kSched[0]));
 static_assert(kNumSched <= kMaxSched, "schedule table exceeds the dispatch table");
@@ -480,11 +482,13 @@ struct XLine {
   __device__ __forceinline__ T kx(int q) const { return T(j + TT * q); }
   // r[q] = entry kx = j + TT q of the line at p (zero beyond K); at kx = 0 only the
   // real part is kept, as a complex-to-real transform does.
-  __device__ __forceinline__ void load(const cpx<T>* p, cpx<T> (&r)[NQ]) const {
+  // (the line is the field buffer b at byte offset voff + the entry's kx * entry size;
+  //  entry j + TT q adds the uniform q TT entries)
+  __device__ __forceinline__ void load(const Buf<T>& b, uint32_t voff, cpx<T> (&r)[NQ]) const {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int k = j + TT * q;
-      r[q] = k <= K ? p[k] : czero<T>();
+      r[q] = k <= K ? bload(b, voff, (uint32_t)(TT * q * (int)sizeof(cpx<T>))) : czero<T>();
     }
     if (j == 0) r[0].y = T(0);
   }
@@ -573,10 +577,13 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     tw = stw;
   const long long line = (long long)blockIdx.x * L + li;  // z * N + y
   const LdsLine<T, N, E> lds{smem + li * LP};
-  cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
+  // fields addressed from the block's first line; a lane's offset covers its line and kx
+  const cpx<T>* bblock = bbuf + (long long)slot * g.FB * g.b_field + (long long)blockIdx.x * L * g.PX;
+  const uint32_t voff = ((uint32_t)li * g.PX + (uint32_t)j) * (uint32_t)sizeof(cpx<T>);
+  auto fbuf = [&](int f) { return make_buf<T>(bblock + (long long)f * g.b_field); };
 
   const XL xl(threadIdx.x, xch);
-  auto load = [&](int f, cpx<T> (&r)[NQ]) { xl.load(base + (long long)f * g.b_field, r); };
+  auto load = [&](int f, cpx<T> (&r)[NQ]) { xl.load(fbuf(f), voff, r); };
   auto build = [&](const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) { xl.build(va, vb, h); };
   auto kxq = [&](int q) { return T(j + TT * q); };
 
@@ -665,8 +672,9 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       const cpx<T> zc = conj(zm);
       const int kx = j + TT * s;
       if (kx <= K) {
-        base[(long long)fp * g.b_field + kx] = T(0.5) * (zk + zc);
-        if (fq >= 0) base[(long long)fq * g.b_field + kx] = mul_mi(T(0.5) * (zk - zc));
+        const uint32_t so = (uint32_t)(TT * s * (int)sizeof(cpx<T>));
+        bstore(fbuf(fp), voff, so, T(0.5) * (zk + zc));
+        if (fq >= 0) bstore(fbuf(fq), voff, so, mul_mi(T(0.5) * (zk - zc)));
       }
     });
   };
@@ -1607,15 +1615,16 @@ k_x_moments(const cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, Ge
   double mx = 0.0;
   const long long nlines = (long long)N * N;
   for (long long l0 = (long long)blockIdx.x * L; l0 < nlines; l0 += (long long)gridDim.x * L) {
-    const cpx<T>* base = bbuf + (long long)slot * g.FB * g.b_field + (l0 + li) * g.PX;
+    const cpx<T>* bblock = bbuf + (long long)slot * g.FB * g.b_field + l0 * g.PX;
+    const uint32_t voff = ((uint32_t)li * g.PX + (uint32_t)j) * (uint32_t)sizeof(cpx<T>);
     T u12x[E], u12y[E];
 #pragma unroll
     for (int f = 0; f < 6; f += 2) {
       if (f >= nf) break;
       cpx<T> ra[NQ], rb[NQ], h[E];
-      xl.load(base + (long long)f * g.b_field, ra);
+      xl.load(make_buf<T>(bblock + (long long)f * g.b_field), voff, ra);
       if (f + 1 < nf) {
-        xl.load(base + (long long)(f + 1) * g.b_field, rb);
+        xl.load(make_buf<T>(bblock + (long long)(f + 1) * g.b_field), voff, rb);
       } else {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) rb[q] = czero<T>();

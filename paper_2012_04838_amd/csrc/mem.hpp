@@ -48,6 +48,11 @@ __device__ __forceinline__ cpx<T> bload(const Buf<T>& b, uint32_t voff, uint32_t
   }
 }
 
+// A store of more than 64 bits of data needs one wait state before a VALU instruction
+// may overwrite its data registers.  The compiler inserts it only for buffer stores
+// whose SGPR offset is the constant 0, so the 128-bit (FP64) stores carry their whole
+// offset in the VGPR; with the offset in an SGPR the overwrite was observed to corrupt
+// stored values now and then.  64-bit (FP32) stores are not affected.
 template <typename T>
 __device__ __forceinline__ void bstore(const Buf<T>& b, uint32_t voff, uint32_t soff, cpx<T> v) {
   if constexpr (sizeof(T) == 4) {
@@ -55,7 +60,7 @@ __device__ __forceinline__ void bstore(const Buf<T>& b, uint32_t voff, uint32_t 
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, w), b.r, (int)voff, (int)soff, 0);
   } else {
     const f64x2_t w = {v.x, v.y};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)(voff + soff), 0, 0);
   }
 }
 

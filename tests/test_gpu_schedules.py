@@ -130,3 +130,37 @@ def test_graph_recaptures_after_schedule_change():
     stream.synchronize()
     ref = ora.step(x, prm, dt, 4)
     assert rel_l2(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_every_schedule_repeats_bitwise(prec):
+    """Identical input gives bitwise identical steps, every schedule, run after run.
+
+    A store whose data registers are overwritten too early corrupts single values now
+    and then (a 1e-9 relative difference after one step, far inside the FP64 bar of a
+    single comparison), so each schedule repeats the same two steps and every repeat
+    must equal the first exactly."""
+    torch = torch_mod()
+    N, S, dt, reps = 128, 1, 0.0037, 6
+    x = ora.init_field(N, S, 2, 6.0, 1.0)
+    x[3:] = inputs.random_spectral_state(N, S, 5, ora.kmax_retained(N), 4.0, 0.3)
+    prm = _prm(S)
+    plan = make_plan(N, S, prec)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    for v in range(plan.n_schedules):
+        plan.set_schedule(v)
+        first = None
+        for r in range(reps):
+            plan.set_state(st, x, 0)
+            plan.step(st, ws, dt, 2)
+            if first is None:
+                first = st.clone()
+            else:
+                same = torch.equal(st, first)
+                if not same:
+                    d = (st.view(torch.float64 if prec == 64 else torch.float32) -
+                         first.view(torch.float64 if prec == 64 else torch.float32)).abs().max().item()
+                    print(f"fp{prec} schedule {v} repeat {r}: max difference {d:.3e}", flush=True)
+                assert same, (v, r)
+        torch.cuda.synchronize()
