@@ -33,10 +33,10 @@ GRAD = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
 # the same process (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  `src` is the digest of the kernel
 # sources and build flags they were taken with; a different digest reports null.
 MEASURED_TRAFFIC = {
-    "src": "2419b4769ec7f321",
+    "src": "cd1dc1a84153f1fa",
     "workload": (512, 2, 32),
-    "schedule": 0,
-    "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.1e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
+    "schedule": 6,
+    "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.0e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
               "z_forward_update_inverse": 5502.6e6},
 }
 
