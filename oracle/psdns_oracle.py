@@ -124,6 +124,13 @@ class Params:
               the configurations); "hold": the paper's deterministic scheme, applied
               after the last stage only, holding the band energy at hold_energy
     hold_energy   target band energy E_f of the "hold" mode
+                  "stochastic": the stochastic band forcing the paper names as an option
+              (Sec. 2.3, after Eswaran & Pope): an Ornstein-Uhlenbeck vector b(k) per
+              band mode, forcing term P(k) b (see ou_update)
+    stoch_sigma   standard deviation of each real and imaginary part of b in the
+              stationary state of the "stochastic" mode
+    stoch_tl      correlation time T_L of b
+    stoch_seed    SplitMix64 seed of the normal draws
     integrator    "if": RK4 in the frame of the viscous/diffusive integrating factor
               (reading of the configurations); "explicit": the paper's classical RK4
               with the viscous and diffusive terms evaluated in every stage (Sec. 2.3)
@@ -137,6 +144,9 @@ class Params:
     forcing_mode: str = "power"
     hold_energy: float = 0.0
     integrator: str = "if"
+    stoch_sigma: float = 0.0
+    stoch_tl: float = 1.0
+    stoch_seed: int = 0
 
     @property
     def n_scalars(self) -> int:
@@ -196,6 +206,83 @@ def band_mask(N: int, k_force: float) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# Stochastic band forcing (Sec. 2.3 names Eswaran & Pope's scheme as an option)
+# --------------------------------------------------------------------------
+def band_radius(N: int, k_force: float) -> int:
+    """Largest integer kf with kf^2 <= k_force^2, capped at the retained K."""
+    kf = 0
+    while float(kf + 1) ** 2 <= k_force * k_force:
+        kf += 1
+    return min(kf, kmax_retained(N))
+
+
+def stochastic_candidates(N: int, k_force: float):
+    """The wavevectors (kx >= 0, ky, kz) of the box |k_i| <= kf in the order that keys the
+    random draws: candidate i = kx + (kf+1) ((ky+kf) + (2kf+1) (kz+kf)).  Returns the
+    list of (i, kx, ky, kz) inside the band 0 < |k|^2 <= k_force^2 and the box size."""
+    kf = band_radius(N, k_force)
+    span = 2 * kf + 1
+    out = []
+    for kz in range(-kf, kf + 1):
+        for ky in range(-kf, kf + 1):
+            for kx in range(0, kf + 1):
+                k2 = kx * kx + ky * ky + kz * kz
+                if 0 < k2 <= k_force * k_force:
+                    out.append((kx + (kf + 1) * ((ky + kf) + span * (kz + kf)), kx, ky, kz))
+    return out, (kf + 1) * span * span
+
+
+def standard_normal(seed: int, q: int) -> float:
+    """Normal number q of the stream: Box-Muller on the uniforms 2q and 2q+1,
+    sqrt(-2 ln(1 - u1)) cos(2 pi u2)."""
+    u = uniform01(seed, np.array([2 * q, 2 * q + 1], dtype=np.uint64))
+    return math.sqrt(-2.0 * math.log(1.0 - float(u[0]))) * math.cos(2.0 * math.pi * float(u[1]))
+
+
+def ou_update(b: dict, h: float, n: int, N: int, prm: Params) -> dict:
+    """Step n (1, 2, ... since the process started at b = 0) of the Ornstein-Uhlenbeck
+    vector of every band mode, exact over the step h:
+
+        b <- a b + sigma sqrt(1 - a^2) xi,   a = exp(-h / T_L),
+
+    xi a complex 3-vector whose real and imaginary parts are independent standard
+    normals (stationary variance sigma^2 per part).  The normal of part p of component
+    c of candidate i is number ((n C + i) 3 + c) 2 + p of the stream (C candidates).
+    On the plane kx = 0 the field must be real in physical space: b(0, -ky, -kz) is the
+    conjugate of b(0, ky, kz), whose own draw is kept for ky > 0 or (ky = 0, kz > 0).
+
+    reading: the paper names the stochastic scheme without giving its formulas; this is
+    the Ornstein-Uhlenbeck process of Eswaran & Pope with one complex vector per mode,
+    updated once per step with that step's h and held over the stages."""
+    cands, C = stochastic_candidates(N, prm.k_force)
+    a = math.exp(-h / prm.stoch_tl)
+    c = prm.stoch_sigma * math.sqrt(max(0.0, 1.0 - a * a))
+    out = {}
+    for i, kx, ky, kz in cands:
+        if kx == 0 and (ky < 0 or (ky == 0 and kz < 0)):
+            continue
+        old = b.get((kx, ky, kz), np.zeros(3, dtype=np.complex128))
+        xi = np.array([complex(standard_normal(prm.stoch_seed, ((n * C + i) * 3 + comp) * 2),
+                               standard_normal(prm.stoch_seed, ((n * C + i) * 3 + comp) * 2 + 1))
+                       for comp in range(3)])
+        out[(kx, ky, kz)] = a * old + c * xi
+    for i, kx, ky, kz in cands:
+        if kx == 0 and (ky < 0 or (ky == 0 and kz < 0)):
+            out[(kx, ky, kz)] = np.conj(out[(0, -ky, -kz)])
+    return out
+
+
+def stochastic_forcing_field(b: dict, N: int) -> np.ndarray:
+    """The forcing term P(k) b(k) on the band, zero elsewhere (half spectrum)."""
+    f = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    for (kx, ky, kz), v in b.items():
+        k = np.array([kx, ky, kz], dtype=np.float64)
+        pv = v - k * (k @ v) / (k @ k)
+        f[:, kz % N, ky % N, kx] = pv
+    return f
+
+
+# --------------------------------------------------------------------------
 # Right-hand side (Eqs. (6)-(8))
 # --------------------------------------------------------------------------
 def project(vhat: np.ndarray) -> np.ndarray:
@@ -213,7 +300,8 @@ def project(vhat: np.ndarray) -> np.ndarray:
     return out
 
 
-def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational") -> np.ndarray:
+def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational",
+              fvec: np.ndarray | None = None) -> np.ndarray:
     """Everything in dy/dt except the viscous/diffusive term -D_f |k|^2 y_f.
 
     state = (u1_hat, u2_hat, u3_hat, phi_1_hat, ..., phi_S_hat), half spectrum.
@@ -261,6 +349,8 @@ def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational") -> np.nd
     A = forcing_amplitude(uhat, prm)
     if A != 0.0:
         fu = fu + A * band_mask(N, prm.k_force) * uhat
+    if fvec is not None:
+        fu = fu + fvec
 
     out = np.empty_like(state)
     out[:3] = fu
@@ -282,10 +372,10 @@ def linear_rates(N: int, prm: Params) -> np.ndarray:
     return np.stack([-d * k2 for d in prm.diffusivities()])
 
 
-def rhs(state: np.ndarray, prm: Params, form: str = "rotational") -> np.ndarray:
+def rhs(state: np.ndarray, prm: Params, form: str = "rotational", fvec: np.ndarray | None = None) -> np.ndarray:
     """Full dy/dt of Eqs. (7)-(8): nonlinear + forcing + mean-gradient + viscous terms."""
     N = state.shape[-3]
-    out = nonlinear(state, prm, form) + linear_rates(N, prm) * state
+    out = nonlinear(state, prm, form, fvec) + linear_rates(N, prm) * state
     out[:, ~retained_mask(N)] = 0.0
     out[:, k_squared(N) == 0] = 0.0
     return out
@@ -311,7 +401,8 @@ def cfl_dt(state: np.ndarray, cfl: float) -> float:
 
 
 def step(state: np.ndarray, prm: Params, dt: float | None = None, nsteps: int = 1,
-         cfl: float | None = None, form: str = "rotational", return_dts: bool = False):
+         cfl: float | None = None, form: str = "rotational", return_dts: bool = False,
+         stoch_state: dict | None = None):
     """Advance nsteps with the classical RK4 of Sec. 2.2 applied in the frame of the
     viscous/diffusive integrating factor (Lawson's IF-RK4).
 
@@ -328,33 +419,46 @@ def step(state: np.ndarray, prm: Params, dt: float | None = None, nsteps: int = 
     explicitly in each stage; the configurations ask for the integrating factor.
 
     Either a fixed dt or a CFL target (dt from Eq. (10) at the start of each step).
+
+    With the "stochastic" forcing, stoch_state = {"b": {mode: vector}, "n": steps so far}
+    carries the Ornstein-Uhlenbeck process across calls (a fresh process when None):
+    every step first draws b with its own h (ou_update), then holds P(k) b over the four
+    stages.
     """
     N = state.shape[-3]
     L = linear_rates(N, prm)
     y = state.copy()
     dts = []
+    stoch = prm.forcing and prm.forcing_mode == "stochastic"
+    if stoch and stoch_state is None:
+        stoch_state = {"b": {}, "n": 0}
     for _ in range(nsteps):
         h = dt if cfl is None else cfl_dt(y, cfl)
         dts.append(h)
+        fvec = None
+        if stoch:
+            stoch_state["n"] += 1
+            stoch_state["b"] = ou_update(stoch_state["b"], h, stoch_state["n"], N, prm)
+            fvec = stochastic_forcing_field(stoch_state["b"], N)
         if prm.integrator == "explicit":
             # the paper's scheme (Sec. 2.3): classical RK4 on the full right-hand side
-            k1 = rhs(y, prm, form)
-            k2 = rhs(y + 0.5 * h * k1, prm, form)
-            k3 = rhs(y + 0.5 * h * k2, prm, form)
-            k4 = rhs(y + h * k3, prm, form)
+            k1 = rhs(y, prm, form, fvec)
+            k2 = rhs(y + 0.5 * h * k1, prm, form, fvec)
+            k3 = rhs(y + 0.5 * h * k2, prm, form, fvec)
+            k4 = rhs(y + h * k3, prm, form, fvec)
             y = y + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
             if prm.forcing and prm.forcing_mode == "hold":
                 y[:3] = band_hold(y[:3], prm)
             continue
         e1 = np.exp(L * h)
         eh = np.exp(L * (0.5 * h))
-        k1 = nonlinear(y, prm, form)
+        k1 = nonlinear(y, prm, form, fvec)
         ya = eh * (y + 0.5 * h * k1)
-        k2 = nonlinear(ya, prm, form)
+        k2 = nonlinear(ya, prm, form, fvec)
         yb = eh * y + 0.5 * h * k2
-        k3 = nonlinear(yb, prm, form)
+        k3 = nonlinear(yb, prm, form, fvec)
         yc = e1 * y + h * eh * k3
-        k4 = nonlinear(yc, prm, form)
+        k4 = nonlinear(yc, prm, form, fvec)
         y = e1 * y + (h / 6.0) * (e1 * k1 + 2.0 * eh * (k2 + k3) + k4)
         if prm.forcing and prm.forcing_mode == "hold":
             y[:3] = band_hold(y[:3], prm)

@@ -605,3 +605,79 @@ def test_quarter_turn_about_mean_gradient_axis_commutes_with_step():
     assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(b))
     # and the rotation is not trivially the identity on this field
     assert np.max(np.abs(_rotate_about_y(y0) - y0)) > 0.1 * np.max(np.abs(y0))
+
+
+# --------------------------------------------------------------------------
+# Stochastic band forcing (Ornstein-Uhlenbeck vector per band mode)
+# --------------------------------------------------------------------------
+def test_box_muller_normals_have_unit_moments():
+    g = np.array([ora.standard_normal(5, q) for q in range(20000)])
+    assert abs(g.mean()) < 0.03
+    assert abs(g.var() - 1.0) < 0.04
+    assert abs(np.mean(g ** 4) - 3.0) < 0.25  # Gaussian kurtosis
+
+
+def test_ou_process_stationary_variance_and_correlation():
+    """The exact Ornstein-Uhlenbeck update keeps variance sigma^2 per real part in the
+    stationary state and has lag-one correlation a = exp(-h/T_L)."""
+    N, h = 16, 0.05
+    prm = ora.Params(nu=0.0, forcing_mode="stochastic", k_force=1.0, stoch_sigma=0.7, stoch_tl=0.3, stoch_seed=9)
+    b = {}
+    series = []
+    for n in range(1, 4001):
+        b = ora.ou_update(b, h, n, N, prm)
+        if n > 200:
+            series.append(np.concatenate([b[m] for m in sorted(b) if m[0] > 0 or m[1] > 0 or (m[1] == 0 and m[2] > 0)]))
+    x = np.array(series)
+    parts = np.concatenate([x.real, x.imag], axis=1)   # steps x (independent modes * 3 * 2)
+    a = math.exp(-h / prm.stoch_tl)
+    assert abs(parts.mean()) < 0.06 * prm.stoch_sigma
+    assert abs(parts.var() / prm.stoch_sigma ** 2 - 1.0) < 0.08
+    lag1 = np.mean(parts[1:] * parts[:-1]) / np.mean(parts * parts)
+    assert abs(lag1 - a) < 0.03, (lag1, a)
+
+
+def test_stochastic_forcing_is_solenoidal_and_real():
+    N = 16
+    prm = ora.Params(nu=0.0, forcing_mode="stochastic", k_force=2.0, stoch_sigma=1.0, stoch_tl=0.5, stoch_seed=3)
+    b = {}
+    for n in range(1, 4):
+        b = ora.ou_update(b, 0.1, n, N, prm)
+    f = ora.stochastic_forcing_field(b, N)
+    kx, ky, kz = ora.kgrid(N)
+    assert np.max(np.abs(kx * f[0] + ky * f[1] + kz * f[2])) < 1e-14
+    # the kx = 0 plane holds conjugate pairs, so the physical forcing is real
+    full = _full_from_half(f[0])
+    assert np.max(np.abs(np.fft.ifftn(full).imag)) < 1e-15
+    assert np.count_nonzero(np.abs(f[0]) + np.abs(f[1]) + np.abs(f[2])) == len(b)
+    # integer vectors with 0 < |k|^2 <= 4 and kx >= 0: 10 with kx > 0, 12 on kx = 0
+    assert len(b) == 22
+
+
+def test_stochastic_single_mode_follows_simpson_weights():
+    """A constant forcing on one mode pair from rest: the nonlinear term of a single Fourier
+    mode pair is a gradient, so the step is the IF-RK4 quadrature of the forcing alone,
+    y_1 = h/6 (E(h) + 4 E(h/2) + 1) P(k) b."""
+    N, h, nu = 16, 0.1, 0.05
+    prm = ora.Params(nu=nu, forcing_mode="stochastic", k_force=2.0, stoch_sigma=0.0, stoch_tl=math.inf)
+    v = np.array([0.3 + 0.1j, -0.2 + 0.4j, 0.5 - 0.2j])
+    st = {"b": {(1, 1, 0): v}, "n": 0}
+    y0 = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    y1 = ora.step(y0, prm, h, 1, stoch_state=st)
+    k = np.array([1.0, 1.0, 0.0])
+    pv = v - k * (k @ v) / (k @ k)
+    e1, eh = math.exp(-nu * 2.0 * h), math.exp(-nu * 2.0 * h / 2)
+    want = h / 6.0 * (e1 + 4.0 * eh + 1.0) * pv
+    assert np.max(np.abs(y1[:, 0, 1, 1] - want)) < 1e-15
+    y1[:, 0, 1, 1] = 0.0
+    assert np.max(np.abs(y1)) < 1e-15
+    assert st["n"] == 1
+
+
+def test_stochastic_forcing_with_zero_sigma_is_unforced():
+    N, S = 16, 1
+    y0 = _solenoidal_state(N, S, 4)
+    base = dict(nu=0.02, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),))
+    a = ora.step(y0, ora.Params(**base, forcing_mode="stochastic", stoch_sigma=0.0, stoch_tl=0.2), 0.01, 3)
+    b = ora.step(y0, ora.Params(**base, forcing=False), 0.01, 3)
+    assert np.array_equal(a, b)
