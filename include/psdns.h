@@ -77,8 +77,26 @@ typedef struct {
  * HOLD:  the paper's deterministic scheme, evaluated once after the last stage of every
  *        step: the band modes of u are scaled by sqrt(hold_energy / E_f), which keeps the
  *        band energy at hold_energy (no forcing term inside the stages). */
+/* STOCHASTIC: the stochastic scheme the paper names as an option (Sec. 2.3, after
+ *        Eswaran & Pope).  Every band mode k (k_force <= PSDNS_STOCHASTIC_KF_MAX) carries a
+ *        complex 3-vector b(k), an Ornstein-Uhlenbeck process advanced once per step with
+ *        that step's dt:  b <- a b + stoch_sigma sqrt(1 - a^2) xi,  a = exp(-dt / stoch_tl),
+ *        xi with independent standard normal real and imaginary parts, so each part has
+ *        variance stoch_sigma^2 in the stationary state.  b holds normalised (physical)
+ *        Fourier coefficients: the term N^3 P(k) b (the solenoidal part, in the
+ *        unnormalised state of Eq. (5)) is added to the velocity right-hand side in every
+ *        stage of the step.  On the plane kx = 0, b(0,-ky,-kz) = conj b(0,ky,kz) (a real
+ *        forcing).
+ *        Normals: Box-Muller, sqrt(-2 ln(1-u1)) cos(2 pi u2), on SplitMix64(stoch_seed)
+ *        uniforms (top 53 bits) number 2q and 2q+1, q = ((n C + i) 3 + c) 2 + p for step n
+ *        (1, 2, ... counted by the step record), candidate i = kx + (kf+1)((ky+kf) +
+ *        (2kf+1)(kz+kf)) of C = (kf+1)(2kf+1)^2, component c, real/imaginary part p;
+ *        kf = floor(k_force), capped at k_max.  b lives in the workspace: it is zero when a
+ *        workspace is first used by the plan and after psdns_clear_step_info. */
 #define PSDNS_FORCING_POWER 0
 #define PSDNS_FORCING_HOLD 1
+#define PSDNS_FORCING_STOCHASTIC 2
+#define PSDNS_STOCHASTIC_KF_MAX 4
 
 /* Time integrator (Sec. 2.2-2.3).
  * IF:       classical RK4 in the frame of the viscous/diffusive integrating factor
@@ -96,9 +114,12 @@ typedef struct {
   double k_force;                         /* forced band 0 < |k| <= k_force */
   double schmidt[PSDNS_MAX_SCALARS];      /* Sc_s = nu / D_s, > 0 */
   double mean_grad[PSDNS_MAX_SCALARS][3]; /* g_s = grad <Phi_s>; Eq. (3) has (0, beta, 0) */
-  int32_t forcing;                        /* PSDNS_FORCING_POWER (default 0) or PSDNS_FORCING_HOLD */
+  int32_t forcing;                        /* PSDNS_FORCING_POWER (default 0), _HOLD or _STOCHASTIC */
   int32_t integrator;                     /* PSDNS_INTEGRATOR_IF (default 0) or PSDNS_INTEGRATOR_EXPLICIT */
   double hold_energy;                     /* HOLD: target band energy E_f > 0 */
+  double stoch_sigma;                     /* STOCHASTIC: stationary deviation of each part of b, >= 0 */
+  double stoch_tl;                        /* STOCHASTIC: correlation time T_L > 0 */
+  uint64_t stoch_seed;                    /* STOCHASTIC: SplitMix64 seed of the normal draws */
 } psdns_slot_params;
 
 /* Per-slot stepping record (host copy). */

@@ -127,8 +127,9 @@ class Params:
                   "stochastic": the stochastic band forcing the paper names as an option
               (Sec. 2.3, after Eswaran & Pope): an Ornstein-Uhlenbeck vector b(k) per
               band mode, forcing term P(k) b (see ou_update)
-    stoch_sigma   standard deviation of each real and imaginary part of b in the
-              stationary state of the "stochastic" mode
+    stoch_sigma   standard deviation of each real and imaginary part of b (normalised,
+              physical Fourier coefficients of the forcing) in the stationary state of
+              the "stochastic" mode
     stoch_tl      correlation time T_L of b
     stoch_seed    SplitMix64 seed of the normal draws
     integrator    "if": RK4 in the frame of the viscous/diffusive integrating factor
@@ -273,12 +274,15 @@ def ou_update(b: dict, h: float, n: int, N: int, prm: Params) -> dict:
 
 
 def stochastic_forcing_field(b: dict, N: int) -> np.ndarray:
-    """The forcing term P(k) b(k) on the band, zero elsewhere (half spectrum)."""
+    """The forcing term on the band, zero elsewhere (half spectrum).  b holds normalised
+    (physical) Fourier coefficients of the forcing, so in the unnormalised spectral state
+    of Eq. (5) the term is N^3 P(k) b(k)."""
     f = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    n3 = float(N) ** 3
     for (kx, ky, kz), v in b.items():
         k = np.array([kx, ky, kz], dtype=np.float64)
         pv = v - k * (k @ v) / (k @ k)
-        f[:, kz % N, ky % N, kx] = pv
+        f[:, kz % N, ky % N, kx] = n3 * pv
     return f
 
 

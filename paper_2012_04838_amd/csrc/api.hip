@@ -106,7 +106,7 @@ int spectra_record(int ns, int S) { return ns * (1 + S) + 8 + 4 * S + 16 + 3 * S
 struct Layout {
   Geom g;
   size_t csize;  // bytes per complex
-  size_t off_dyn, off_part, off_stat, off_ystage, off_acc, off_abuf, off_bbuf, ws_bytes, st_bytes;
+  size_t off_dyn, off_fband, off_part, off_stat, off_ystage, off_acc, off_abuf, off_bbuf, ws_bytes, st_bytes;
   long long part_len, stat_len;
   int nbm, rec;
 };
@@ -141,6 +141,8 @@ Layout make_layout(const psdns_plan_params* p) {
   size_t off = 0;
   L.off_dyn = off;
   off = align_up(off + B * sizeof(DynDev), 256);
+  L.off_fband = off;
+  off = align_up(off + B * (size_t)kStochCand * 12 * sizeof(double), 256);
   L.off_part = off;
   off = align_up(off + (size_t)L.part_len * sizeof(double), 256);
   L.off_stat = off;
@@ -232,6 +234,7 @@ Ctx make_ctx(psdns_plan* plan, void* ws) {
   c.slots = plan->slots_dev;
   char* w = static_cast<char*>(ws);
   c.dyn = reinterpret_cast<DynDev*>(w + plan->L.off_dyn);
+  c.fband = reinterpret_cast<double*>(w + plan->L.off_fband);
   c.part = reinterpret_cast<double*>(w + plan->L.off_part);
   c.part_len = plan->L.part_len;
   c.stat = reinterpret_cast<double*>(w + plan->L.off_stat);
@@ -259,10 +262,18 @@ __global__ void k_clear_dyn(DynDev* d, int n) {
   }
 }
 
+__global__ void k_clear_doubles(double* p, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// step records and the stochastic forcing's band vectors start from zero
 psdns_status ensure_ws(psdns_plan* plan, void* ws, hipStream_t s) {
   if (plan->cleared_ws == ws) return PSDNS_OK;
   Ctx c = make_ctx(plan, ws);
   k_clear_dyn<<<(plan->p.batch + 63) / 64, 64, 0, s>>>(c.dyn, plan->p.batch);
+  const long long nb = (long long)plan->p.batch * kStochCand * 12;
+  k_clear_doubles<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(c.fband, nb);
   HIP_TRY(hipGetLastError());
   plan->cleared_ws = ws;
   return PSDNS_OK;
@@ -433,8 +444,17 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
       s.g[i][d] = prm->mean_grad[i][d];
     }
   }
-  if (prm->forcing != PSDNS_FORCING_POWER && prm->forcing != PSDNS_FORCING_HOLD)
-    return fail(PSDNS_E_INVAL, "forcing must be PSDNS_FORCING_POWER or PSDNS_FORCING_HOLD");
+  if (prm->forcing != PSDNS_FORCING_POWER && prm->forcing != PSDNS_FORCING_HOLD &&
+      prm->forcing != PSDNS_FORCING_STOCHASTIC)
+    return fail(PSDNS_E_INVAL, "forcing must be PSDNS_FORCING_POWER, PSDNS_FORCING_HOLD or PSDNS_FORCING_STOCHASTIC");
+  if (prm->forcing == PSDNS_FORCING_STOCHASTIC) {
+    if (!(prm->stoch_sigma >= 0.0) || !std::isfinite(prm->stoch_sigma))
+      return fail(PSDNS_E_INVAL, "stoch_sigma must be finite and >= 0");
+    if (!(prm->stoch_tl > 0.0) || !std::isfinite(prm->stoch_tl))
+      return fail(PSDNS_E_INVAL, "stoch_tl must be finite and > 0");
+    if (!(prm->k_force < PSDNS_STOCHASTIC_KF_MAX + 1.0))
+      return fail(PSDNS_E_INVAL, "k_force must be below PSDNS_STOCHASTIC_KF_MAX + 1 with PSDNS_FORCING_STOCHASTIC");
+  }
   if (prm->forcing == PSDNS_FORCING_HOLD && (!(prm->hold_energy > 0.0) || !std::isfinite(prm->hold_energy)))
     return fail(PSDNS_E_INVAL, "hold_energy must be finite and > 0 with PSDNS_FORCING_HOLD");
   if (prm->integrator != PSDNS_INTEGRATOR_IF && prm->integrator != PSDNS_INTEGRATOR_EXPLICIT)
@@ -442,6 +462,9 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
   s.integrator = prm->integrator;
   s.forcing = prm->forcing;
   s.hold = prm->forcing == PSDNS_FORCING_HOLD ? prm->hold_energy : 0.0;
+  s.sigma = prm->forcing == PSDNS_FORCING_STOCHASTIC ? prm->stoch_sigma : 0.0;
+  s.tl = prm->forcing == PSDNS_FORCING_STOCHASTIC ? prm->stoch_tl : 1.0;
+  s.seed = prm->stoch_seed;
   s.active = active ? 1 : 0;
   plan->slots_host[slot] = s;
   HIP_TRY(hipMemcpy(plan->slots_dev + slot, &s, sizeof(SlotDev), hipMemcpyHostToDevice));

@@ -47,7 +47,16 @@ struct SlotDev {
   double hold;                      // target band energy of PSDNS_FORCING_HOLD
   int integrator;                   // PSDNS_INTEGRATOR_IF or PSDNS_INTEGRATOR_EXPLICIT
   int pad_;
+  double sigma;                     // PSDNS_FORCING_STOCHASTIC: stationary deviation per part
+  double tl;                        // PSDNS_FORCING_STOCHASTIC: correlation time
+  unsigned long long seed;          // PSDNS_FORCING_STOCHASTIC: SplitMix64 seed
 };
+
+// Band table of the stochastic forcing: per slot, kStochCand candidates of 12 FP64 (the
+// vector b and the forcing term N^3 P(k) b, 3 complex each), candidate
+// i = kx + (kf+1)((ky+kf) + (2kf+1)(kz+kf)) for the slot's kf.
+constexpr int kStochKfMax = PSDNS_STOCHASTIC_KF_MAX;
+constexpr int kStochCand = (kStochKfMax + 1) * (2 * kStochKfMax + 1) * (2 * kStochKfMax + 1);
 
 // Per-slot values written on the device while stepping (part of the workspace).
 struct DynDev {
@@ -95,6 +104,7 @@ struct Ctx {
   const void* tw;          // w_N^m = exp(-2 pi i m/N), m = 0..N-1, in the plan precision
   const SlotDev* slots;    // device table [batch]
   DynDev* dyn;             // device [batch]
+  double* fband;           // device [batch][kStochCand][12] FP64 (stochastic forcing: b, P(k) b)
   void* abuf;              // [batch][FA][N][M][PX]
   void* bbuf;              // [batch][FB][N][N][PX]
   void* ystage;            // [batch][F][M][M][PX]

@@ -832,8 +832,9 @@ struct StageArgs {
   cpx<T>* yn;
   cpx<T>* acc;
   cpx<T>* ys;
-  const cpx<T>* sin;  // stage input (y_n at stage 0, y_stage otherwise)
-  cpx<T>* rhs;        // stage < 0 only
+  const cpx<T>* sin;    // stage input (y_n at stage 0, y_stage otherwise)
+  cpx<T>* rhs;          // stage < 0 only
+  const double* fband;  // stochastic forcing table [batch][kStochCand][12] (b, P(k) b)
   int stage;
 };
 
@@ -1013,6 +1014,25 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     fetch(2, c3);
     fft<N, E, false>(c3, lds, j, tw);
 #endif
+    if (sp.forcing == PSDNS_FORCING_STOCHASTIC && valid) {
+      // the stochastic forcing P(k) b of the band modes (projected by k_stochastic_update)
+      // joins the transformed product; the projection below leaves it unchanged
+      int kfs = 0;
+      while ((double)(kfs + 1) * (kfs + 1) <= sp.kf2) ++kfs;
+      if (kfs > g.K) kfs = g.K;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const double k2m_ = k2m(m);
+        if (k2m_ > 0.0 && k2m_ <= sp.kf2) {
+          const int kz = wave_of(j + TT * m, N);
+          const double* f =
+              sa.fband + ((long long)slot * kStochCand + kx + (kfs + 1) * ((ky + kfs) + (2 * kfs + 1) * (kz + kfs))) * 12 + 6;
+          c1[m] = c1[m] + cpx<T>{T(f[0]), T(f[1])};
+          c2[m] = c2[m] + cpx<T>{T(f[2]), T(f[3])};
+          c3[m] = c3[m] + cpx<T>{T(f[4]), T(f[5])};
+        }
+      }
+    }
     const double nu = sp.nu;
     const long long f1 = sslot, f2 = sslot + g.st_field, f3 = sslot + 2 * g.st_field;
 #pragma unroll
@@ -1269,6 +1289,77 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t counte
   return z ^ (z >> 31);
 }
 __device__ __forceinline__ double unit_double(uint64_t x) { return double(x >> 11) * (1.0 / 9007199254740992.0); }
+
+// ---------------------------------------------------------------------------
+// stochastic band forcing (the option of Sec. 2.3 after Eswaran & Pope): once per step,
+// after the step size is known, b <- a b + sigma sqrt(1 - a^2) xi for every band mode,
+// a = exp(-dt / T_L), xi from Box-Muller normals keyed by (step, candidate, component,
+// part); the modes (0, ky, kz) with ky < 0, or ky = 0 and kz < 0, then take the conjugate
+// of their partner so that the forcing is real.  One block per slot.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double normal_at(uint64_t seed, uint64_t q) {
+  const double u1 = unit_double(splitmix64_at(seed, 2 * q));
+  const double u2 = unit_double(splitmix64_at(seed, 2 * q + 1));
+  return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586476925286766559 * u2);
+}
+
+static __global__ void __launch_bounds__(256)
+k_stochastic_update(const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, double* __restrict__ fband,
+                    Geom g) {
+  const int slot = blockIdx.x;
+  const SlotDev& sp = slots[slot];
+  if (!sp.active || sp.forcing != PSDNS_FORCING_STOCHASTIC) return;
+  int kf = 0;
+  while ((double)(kf + 1) * (kf + 1) <= sp.kf2) ++kf;
+  if (kf > g.K) kf = g.K;
+  const int span = 2 * kf + 1;
+  const int ncand = (kf + 1) * span * span;
+  const double h = dyn[slot].dt;
+  const uint64_t n = (uint64_t)dyn[slot].steps;
+  const double a = exp(-h / sp.tl);
+  const double c = sp.sigma * sqrt(fmax(0.0, 1.0 - a * a));
+  // per candidate: b (3 complex) then N^3 P(k) b (3 complex)
+  double* tab = fband + (long long)slot * kStochCand * 12;
+  auto decode = [&](int i, int& kx, int& ky, int& kz) {
+    kx = i % (kf + 1);
+    ky = (i / (kf + 1)) % span - kf;
+    kz = i / ((kf + 1) * span) - kf;
+    const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    return k2 > 0.0 && k2 <= sp.kf2;
+  };
+  for (int i = threadIdx.x; i < ncand; i += blockDim.x) {
+    int kx, ky, kz;
+    if (!decode(i, kx, ky, kz)) continue;
+    if (kx == 0 && (ky < 0 || (ky == 0 && kz < 0))) continue;
+    double* e = tab + i * 12;
+    for (int comp = 0; comp < 3; ++comp) {
+      const uint64_t q = ((n * (uint64_t)ncand + (uint64_t)i) * 3 + (uint64_t)comp) * 2;
+      e[2 * comp] = a * e[2 * comp] + c * normal_at(sp.seed, q);
+      e[2 * comp + 1] = a * e[2 * comp + 1] + c * normal_at(sp.seed, q + 1);
+    }
+    // the term in the unnormalised state: N^3 P(k) b
+    const double n3 = double(g.N) * g.N * g.N;
+    const double k[3] = {double(kx), double(ky), double(kz)};
+    const double k2 = k[0] * k[0] + k[1] * k[1] + k[2] * k[2];
+    const double kbr = (k[0] * e[0] + k[1] * e[2] + k[2] * e[4]) / k2;
+    const double kbi = (k[0] * e[1] + k[1] * e[3] + k[2] * e[5]) / k2;
+    for (int comp = 0; comp < 3; ++comp) {
+      e[6 + 2 * comp] = n3 * (e[2 * comp] - k[comp] * kbr);
+      e[6 + 2 * comp + 1] = n3 * (e[2 * comp + 1] - k[comp] * kbi);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < ncand; i += blockDim.x) {
+    int kx, ky, kz;
+    if (!decode(i, kx, ky, kz)) continue;
+    if (!(kx == 0 && (ky < 0 || (ky == 0 && kz < 0)))) continue;
+    const int p = (kf + 1) * ((-ky + kf) + span * (-kz + kf));  // candidate of (0, -ky, -kz)
+    for (int r = 0; r < 12; r += 2) {
+      tab[i * 12 + r] = tab[p * 12 + r];
+      tab[i * 12 + r + 1] = -tab[p * 12 + r + 1];
+    }
+  }
+}
 
 // Initial energy spectrum shape E(kappa): kind 0 the configured kappa^4 exp(-2 (kappa/kp)^2);
 // kind 1 the paper's spectrum (Sec. 2.3, after Lamorgese et al.) with kp = k_F:
@@ -1828,6 +1919,8 @@ struct Step {
     if (stage == 0) {
       TimedLaunch tl(x.timer, KID_DT, s);
       k_step_dt<<<g.batch, 64, 0, s>>>(x.slots, x.dyn, g, dt_arg);
+      // returns at once for slots without the stochastic forcing
+      k_stochastic_update<<<g.batch, 256, 0, s>>>(x.slots, x.dyn, x.fband, g);
     }
     {
       TimedLaunch tl(x.timer, KID_YFWD, s);
@@ -1839,6 +1932,7 @@ struct Step {
     sa.ys = static_cast<cpx<T>*>(x.ystage);
     sa.sin = sin;
     sa.rhs = static_cast<cpx<T>*>(rhs_out);
+    sa.fband = x.fband;
     sa.stage = stage;
     const int ntile_u = (g.KX + C::Fused::W - 1) / C::Fused::W;
     if (flags & kStageFuse) {

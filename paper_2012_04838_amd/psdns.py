@@ -32,6 +32,7 @@ class PlanParams(ctypes.Structure):
 
 FORCING_POWER = 0
 FORCING_HOLD = 1
+FORCING_STOCHASTIC = 2
 INTEGRATOR_IF = 0
 INTEGRATOR_EXPLICIT = 1
 SPECTRUM_CONFIG = 0
@@ -42,7 +43,8 @@ class SlotParams(ctypes.Structure):
     _fields_ = [("nu", ctypes.c_double), ("power", ctypes.c_double), ("k_force", ctypes.c_double),
                 ("schmidt", ctypes.c_double * MAX_SCALARS),
                 ("mean_grad", (ctypes.c_double * 3) * MAX_SCALARS),
-                ("forcing", _c_int32), ("integrator", _c_int32), ("hold_energy", ctypes.c_double)]
+                ("forcing", _c_int32), ("integrator", _c_int32), ("hold_energy", ctypes.c_double),
+                ("stoch_sigma", ctypes.c_double), ("stoch_tl", ctypes.c_double), ("stoch_seed", ctypes.c_uint64)]
 
 
 class StepInfo(ctypes.Structure):
@@ -210,10 +212,12 @@ class Plan:
     def set_slot(self, slot: int, nu: float, power: float = 0.0, k_force: float = 2.0,
                  schmidt: Sequence[float] = (), mean_grad: Sequence[Sequence[float]] = (),
                  active: bool = True, forcing: int = FORCING_POWER, hold_energy: float = 0.0,
-                 integrator: int = INTEGRATOR_IF) -> None:
+                 integrator: int = INTEGRATOR_IF, stoch_sigma: float = 0.0, stoch_tl: float = 1.0,
+                 stoch_seed: int = 0) -> None:
         sp = SlotParams()
         sp.nu, sp.power, sp.k_force = nu, power, k_force
         sp.forcing, sp.hold_energy, sp.integrator = forcing, hold_energy, integrator
+        sp.stoch_sigma, sp.stoch_tl, sp.stoch_seed = stoch_sigma, stoch_tl, stoch_seed
         for i in range(MAX_SCALARS):
             sp.schmidt[i] = schmidt[i] if i < len(schmidt) else 1.0
             g = mean_grad[i] if i < len(mean_grad) else (0.0, 0.0, 0.0)

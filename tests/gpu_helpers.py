@@ -20,11 +20,14 @@ def make_plan(N, S, prec, batch=1):
 def set_params(plan, slot, prm: "ora.Params", active=True):
     from paper_2012_04838_amd import psdns
     hold = prm.forcing and prm.forcing_mode == "hold"
-    plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing and not hold else 0.0), k_force=prm.k_force,
-                  schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad], active=active,
-                  forcing=psdns.FORCING_HOLD if hold else psdns.FORCING_POWER,
-                  hold_energy=prm.hold_energy if hold else 0.0,
-                  integrator=psdns.INTEGRATOR_EXPLICIT if prm.integrator == "explicit" else psdns.INTEGRATOR_IF)
+    stoch = prm.forcing and prm.forcing_mode == "stochastic"
+    mode = psdns.FORCING_HOLD if hold else (psdns.FORCING_STOCHASTIC if stoch else psdns.FORCING_POWER)
+    plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing and mode == psdns.FORCING_POWER else 0.0),
+                  k_force=prm.k_force, schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad],
+                  active=active, forcing=mode, hold_energy=prm.hold_energy if hold else 0.0,
+                  integrator=psdns.INTEGRATOR_EXPLICIT if prm.integrator == "explicit" else psdns.INTEGRATOR_IF,
+                  stoch_sigma=prm.stoch_sigma if stoch else 0.0, stoch_tl=prm.stoch_tl if stoch else 1.0,
+                  stoch_seed=prm.stoch_seed if stoch else 0)
 
 
 def to_numpy(t):

@@ -645,10 +645,11 @@ def test_stochastic_forcing_is_solenoidal_and_real():
         b = ora.ou_update(b, 0.1, n, N, prm)
     f = ora.stochastic_forcing_field(b, N)
     kx, ky, kz = ora.kgrid(N)
-    assert np.max(np.abs(kx * f[0] + ky * f[1] + kz * f[2])) < 1e-14
+    scale = np.max(np.abs(f))
+    assert np.max(np.abs(kx * f[0] + ky * f[1] + kz * f[2])) < 1e-14 * scale
     # the kx = 0 plane holds conjugate pairs, so the physical forcing is real
     full = _full_from_half(f[0])
-    assert np.max(np.abs(np.fft.ifftn(full).imag)) < 1e-15
+    assert np.max(np.abs(np.fft.ifftn(full).imag)) < 1e-15 * scale
     assert np.count_nonzero(np.abs(f[0]) + np.abs(f[1]) + np.abs(f[2])) == len(b)
     # integer vectors with 0 < |k|^2 <= 4 and kx >= 0: 10 with kx > 0, 12 on kx = 0
     assert len(b) == 22
@@ -657,7 +658,7 @@ def test_stochastic_forcing_is_solenoidal_and_real():
 def test_stochastic_single_mode_follows_simpson_weights():
     """A constant forcing on one mode pair from rest: the nonlinear term of a single Fourier
     mode pair is a gradient, so the step is the IF-RK4 quadrature of the forcing alone,
-    y_1 = h/6 (E(h) + 4 E(h/2) + 1) P(k) b."""
+    y_1 = h/6 (E(h) + 4 E(h/2) + 1) N^3 P(k) b (b is a normalised coefficient)."""
     N, h, nu = 16, 0.1, 0.05
     prm = ora.Params(nu=nu, forcing_mode="stochastic", k_force=2.0, stoch_sigma=0.0, stoch_tl=math.inf)
     v = np.array([0.3 + 0.1j, -0.2 + 0.4j, 0.5 - 0.2j])
@@ -667,10 +668,10 @@ def test_stochastic_single_mode_follows_simpson_weights():
     k = np.array([1.0, 1.0, 0.0])
     pv = v - k * (k @ v) / (k @ k)
     e1, eh = math.exp(-nu * 2.0 * h), math.exp(-nu * 2.0 * h / 2)
-    want = h / 6.0 * (e1 + 4.0 * eh + 1.0) * pv
-    assert np.max(np.abs(y1[:, 0, 1, 1] - want)) < 1e-15
+    want = h / 6.0 * (e1 + 4.0 * eh + 1.0) * N ** 3 * pv
+    assert np.max(np.abs(y1[:, 0, 1, 1] - want)) < 1e-14 * np.max(np.abs(want))
     y1[:, 0, 1, 1] = 0.0
-    assert np.max(np.abs(y1)) < 1e-15
+    assert np.max(np.abs(y1)) < 1e-14 * np.max(np.abs(want))
     assert st["n"] == 1
 
 
