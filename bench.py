@@ -35,7 +35,7 @@ GRAD = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
 MEASURED_TRAFFIC = {
     "src": "7f5d7b0919364429",
     "workload": (512, 2, 32),
-    "schedule": 6,
+    "schedules": (0, 5, 6),  # measured separately; every pass moved the same bytes in each
     "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.0e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
               "z_forward_update_inverse": 5502.6e6},
 }
@@ -60,7 +60,7 @@ def measured_traffic(kernel: str, n: int, s: int, prec: int, schedule: int):
     """Counter bytes per launch of a kernel, if they were taken on these sources, this
     workload and this schedule (spills and tile shapes change the traffic)."""
     t = MEASURED_TRAFFIC
-    if (t["workload"] != (n, s, prec) or t["schedule"] != schedule or kernel not in t["bytes"]
+    if (t["workload"] != (n, s, prec) or schedule not in t["schedules"] or kernel not in t["bytes"]
             or t["src"] != kernel_source_digest()):
         return None
     return t["bytes"][kernel]
