@@ -29,7 +29,15 @@
  *
  * Ownership.  The caller owns every buffer passed in (state, workspace, outputs)
  * and the HIP stream; all of them are device pointers unless stated.  A plan
- * owns only its small twiddle and parameter tables.
+ * owns only its small twiddle and parameter tables (psdns_plan_device_bytes), so
+ * state + workspace + plan tables is the whole device footprint of a plan.
+ *
+ * Workspace records.  Besides transform buffers, a workspace carries per-slot records
+ * that persist across calls: simulated time, step count and flags (psdns_step_info) and
+ * the stochastic-forcing vectors.  The library cannot tell a fresh workspace from one it
+ * has seen, so the caller clears the records with psdns_clear_step_info before the first
+ * use of a workspace with a plan (and whenever its contents are unknown, e.g. memory
+ * reused from another allocation).  psdns_init_field clears the record of its slot.
  *
  * Errors.  Every call returns a psdns_status; nothing is thrown across the ABI.
  * Argument errors are detected before anything is launched.  Launches are
@@ -91,8 +99,8 @@ typedef struct {
  *        uniforms (top 53 bits) number 2q and 2q+1, q = ((n C + i) 3 + c) 2 + p for step n
  *        (1, 2, ... counted by the step record), candidate i = kx + (kf+1)((ky+kf) +
  *        (2kf+1)(kz+kf)) of C = (kf+1)(2kf+1)^2, component c, real/imaginary part p;
- *        kf = floor(k_force), capped at k_max.  b lives in the workspace: it is zero when a
- *        workspace is first used by the plan and after psdns_clear_step_info. */
+ *        kf = floor(k_force), capped at k_max.  b lives in the workspace: it is zero after
+ *        psdns_clear_step_info, psdns_clear_slot_info and psdns_init_field of the slot. */
 #define PSDNS_FORCING_POWER 0
 #define PSDNS_FORCING_HOLD 1
 #define PSDNS_FORCING_STOCHASTIC 2
@@ -141,12 +149,17 @@ typedef struct {
   int32_t elems_col, elems_x; /* FFT elements per thread of the column and x passes (schedule in use) */
   int32_t n_schedules;        /* step schedules compiled for this size (psdns_set_schedule) */
   int32_t schedule;           /* schedule in use */
+  int64_t plan_bytes;         /* device bytes of the plan's own tables (psdns_plan_device_bytes) */
 } psdns_plan_info;
 
 /* Bytes of the compact spectral state y for all slots (caller allocates). 0 on invalid params. */
 size_t psdns_state_bytes(const psdns_plan_params* p);
 /* Bytes of the workspace needed by rhs/step/init/spectra (caller allocates). 0 on invalid params. */
 size_t psdns_workspace_bytes(const psdns_plan_params* p);
+
+/* Device bytes a plan allocates for its own twiddle and slot tables (rounded up to 256-byte
+ * granules); with the state and the workspace, the whole device footprint.  0 on invalid params. */
+size_t psdns_plan_device_bytes(const psdns_plan_params* p);
 
 /* Create a plan (host metadata plus twiddle and slot tables on the current device).
  * All slots start active with nu = 0, P = 0, k_force = 2, Sc = 1, g = 0. */
@@ -161,7 +174,8 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
 /* Rogallo-type random solenoidal field (Sec. 2.3) with the configured spectrum
  * E(k) ~ k^4 exp(-2 (k/k_peak)^2), phases from SplitMix64(seed) keyed by the
  * canonical linear index, scaled to kinetic energy 1/2<u.u> = kinetic_energy;
- * scalars start at zero (Sec. 2.3).  Writes one slot of `state`; uses `ws`. */
+ * scalars start at zero (Sec. 2.3).  Writes one slot of `state`; uses `ws`, and clears the
+ * slot's step record and stochastic-forcing vector there (a new realization starts at t = 0). */
 psdns_status psdns_init_field(psdns_plan* plan, void* state, void* ws, int32_t slot, uint64_t seed,
                               double k_peak, double kinetic_energy, void* hip_stream);
 
@@ -233,8 +247,13 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
 
 /* Copy the per-slot stepping records to host memory `out[batch]` (synchronises the stream). */
 psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_info* out, void* hip_stream);
-/* Reset t, steps and flags of every slot (asynchronous). */
+/* Reset t, steps, flags and the stochastic-forcing vectors of every slot (asynchronous;
+ * a kernel, so it may be recorded in a captured graph).  Required before the first use of
+ * a workspace with a plan. */
 psdns_status psdns_clear_step_info(psdns_plan* plan, void* ws, void* hip_stream);
+/* The same for one slot only, e.g. when a slot is reused for a new run loaded with
+ * psdns_set_state.  PSDNS_E_INVAL for a slot outside [0, batch). */
+psdns_status psdns_clear_slot_info(psdns_plan* plan, void* ws, int32_t slot, void* hip_stream);
 
 /* Convert one slot between the compact state and the canonical layout (device buffers).
  * get: modes outside the retained cube are written as zero.  set: they are ignored. */

@@ -211,7 +211,6 @@ struct psdns_plan {
   SlotDev* slots_dev = nullptr;
   std::vector<SlotDev> slots_host;
   int device = 0;
-  const void* cleared_ws = nullptr;
   EventTimer* timer = nullptr;
   double acc_ms[KID_COUNT] = {0};
   int acc_n[KID_COUNT] = {0};
@@ -267,22 +266,95 @@ __global__ void k_clear_doubles(double* p, long long n) {
   if (i < n) p[i] = 0.0;
 }
 
-// step records and the stochastic forcing's band vectors start from zero
-psdns_status ensure_ws(psdns_plan* plan, void* ws, hipStream_t s) {
-  if (plan->cleared_ws == ws) return PSDNS_OK;
+// Step records and stochastic-forcing vectors of slots [first, first + count) start from zero.
+// A small kernel, not hipMemsetAsync, so that the clear may be recorded in a captured graph.
+psdns_status clear_slots(psdns_plan* plan, void* ws, int first, int count, hipStream_t s) {
   Ctx c = make_ctx(plan, ws);
-  k_clear_dyn<<<(plan->p.batch + 63) / 64, 64, 0, s>>>(c.dyn, plan->p.batch);
-  const long long nb = (long long)plan->p.batch * kStochCand * 12;
-  k_clear_doubles<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(c.fband, nb);
+  k_clear_dyn<<<(count + 63) / 64, 64, 0, s>>>(c.dyn + first, count);
+  const long long per = (long long)kStochCand * 12;
+  const long long nb = (long long)count * per;
+  k_clear_doubles<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(c.fband + first * per, nb);
   HIP_TRY(hipGetLastError());
-  plan->cleared_ws = ws;
   return PSDNS_OK;
+}
+
+// device bytes a plan allocates for itself (twiddle and slot tables)
+size_t plan_table_bytes(const psdns_plan_params* p) {
+  const size_t cs = p->precision == 32 ? 8 : 16;
+  return align_up((size_t)p->n * cs, 256) + align_up(sizeof(SlotDev) * (size_t)p->batch, 256);
 }
 
 psdns_status check_plan(const psdns_plan* plan) {
   if (!plan) return fail(PSDNS_E_INVAL, "plan is NULL");
   return PSDNS_OK;
 }
+
+// The steps of psdns_step on workspace ws (graph replay when allowed and enabled).
+psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int nsteps, hipStream_t s,
+                       bool allow_graph, Timer* timer) {
+  Ctx c = make_ctx(plan, ws);
+  c.timer = timer;
+  // Every stage's last pass also inverts the next stage input along z (it is in its
+  // registers already), so only the first stage of a call runs the standalone z pass;
+  // the very last stage of a direct call skips the unneeded inverse.
+  // With the hold forcing y_{n+1} is rescaled on the band after the last stage, so that
+  // stage cannot run the next step's z inverse: every step then starts with its own.
+  bool hold = false;
+  for (int i = 0; i < plan->p.batch; ++i)
+    hold = hold || (plan->slots_host[i].active && plan->slots_host[i].forcing == PSDNS_FORCING_HOLD);
+  auto one_step = [&](const Ctx& cx, bool first, bool last) {
+    for (int stage = 0; stage < 4; ++stage) {
+      const void* sin = stage == 0 ? state : cx.ystage;
+      int fl = kStageFuse;
+      if ((first || hold) && stage == 0) fl |= kStageZinv;
+      if ((last || hold) && stage == 3) fl &= ~kStageFuse;
+      plan->ops.sched[plan->sched].rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
+    }
+    if (hold) plan->ops.band_hold(cx, state, s);
+  };
+  if (allow_graph && s != nullptr && nsteps > 0) {
+    if (!plan->graph_exec || plan->graph_state != state || plan->graph_ws != ws || plan->graph_dt != dt ||
+        plan->graph_hold != hold) {
+      if (plan->graph_exec) {
+        HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
+        plan->graph_exec = nullptr;
+      }
+      Ctx cc = c;
+      cc.timer = nullptr;  // no event records inside a captured graph
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      one_step(cc, false, false);
+      hipGraph_t graph = nullptr;
+      const hipError_t le = hipGetLastError();
+      const hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (le != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le, "kernel launch during graph capture");
+      }
+      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+      hipError_t ie = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (ie != hipSuccess) {
+        plan->graph_exec = nullptr;
+        return hip_fail(ie, "hipGraphInstantiate");
+      }
+      plan->graph_state = state;
+      plan->graph_ws = ws;
+      plan->graph_hold = hold;
+      plan->graph_dt = dt;
+    }
+    // the captured step expects the z inverse of y_n: run it once, then replay
+    plan->ops.sched[plan->sched].rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
+    HIP_TRY(hipGetLastError());
+    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
+    return PSDNS_OK;
+  }
+  for (int n = 0; n < nsteps; ++n) {
+    one_step(c, n == 0, n == nsteps - 1);
+    HIP_TRY(hipGetLastError());
+  }
+  return PSDNS_OK;
+}
+
 
 }  // namespace
 
@@ -298,6 +370,12 @@ size_t psdns_workspace_bytes(const psdns_plan_params* p) {
   std::string why;
   if (!valid_params(p, &why)) return 0;
   return make_layout(p).ws_bytes;
+}
+
+size_t psdns_plan_device_bytes(const psdns_plan_params* p) {
+  std::string why;
+  if (!valid_params(p, &why)) return 0;
+  return plan_table_bytes(p);
 }
 
 psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
@@ -387,6 +465,7 @@ psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
   out->spectra_doubles = plan->L.rec;
   out->state_bytes = (int64_t)plan->L.st_bytes;
   out->workspace_bytes = (int64_t)plan->L.ws_bytes;
+  out->plan_bytes = (int64_t)plan_table_bytes(&plan->p);
   out->elems_col = plan->ops.sched[plan->sched].ec;
   out->elems_x = plan->ops.sched[plan->sched].ex;
   out->n_schedules = plan->ops.nsched;
@@ -482,7 +561,8 @@ psdns_status psdns_init_field_spectrum(psdns_plan* plan, void* state, void* ws, 
   if (!(kinetic_energy >= 0.0) || !std::isfinite(kinetic_energy))
     return fail(PSDNS_E_INVAL, "kinetic_energy must be >= 0");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
+  // a new realization: its step record and stochastic-forcing vector start from zero
+  if (psdns_status st = clear_slots(plan, ws, slot, 1, s)) return st;
   Ctx c = make_ctx(plan, ws);
   plan->ops.init_field(c, state, slot, seed, k_param, spectrum, kinetic_energy, s);
   HIP_TRY(hipGetLastError());
@@ -511,7 +591,6 @@ psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws,
   if (!state || !out || !ws) return fail(PSDNS_E_INVAL, "state, out and ws must be device pointers");
   if (state == out) return fail(PSDNS_E_INVAL, "out must not alias state");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
   plan->ops.sched[plan->sched].rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, kStageZinv, s);
   HIP_TRY(hipGetLastError());
@@ -524,7 +603,6 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
   if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
   if (reps < 1 || reps > 1000) return fail(PSDNS_E_INVAL, "reps must be in [1, 1000]");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
   c.timer = nullptr;  // the trial launches are not part of the kernel timing record
   std::vector<double> ms(plan->ops.nsched, 0.0);
@@ -568,68 +646,7 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
   if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
   if (nsteps < 0) return fail(PSDNS_E_INVAL, "nsteps must be >= 0");
   if (!(dt != 0.0) || !std::isfinite(dt)) return fail(PSDNS_E_INVAL, "dt must be finite and nonzero");
-  hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
-  Ctx c = make_ctx(plan, ws);
-  // Every stage's last pass also inverts the next stage input along z (it is in its
-  // registers already), so only the first stage of a call runs the standalone z pass;
-  // the very last stage of a direct call skips the unneeded inverse.
-  // With the hold forcing y_{n+1} is rescaled on the band after the last stage, so that
-  // stage cannot run the next step's z inverse: every step then starts with its own.
-  bool hold = false;
-  for (int i = 0; i < plan->p.batch; ++i)
-    hold = hold || (plan->slots_host[i].active && plan->slots_host[i].forcing == PSDNS_FORCING_HOLD);
-  auto one_step = [&](const Ctx& cx, bool first, bool last) {
-    for (int stage = 0; stage < 4; ++stage) {
-      const void* sin = stage == 0 ? state : cx.ystage;
-      int fl = kStageFuse;
-      if ((first || hold) && stage == 0) fl |= kStageZinv;
-      if ((last || hold) && stage == 3) fl &= ~kStageFuse;
-      plan->ops.sched[plan->sched].rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
-    }
-    if (hold) plan->ops.band_hold(cx, state, s);
-  };
-  if (plan->use_graph && s != nullptr && nsteps > 0) {
-    if (!plan->graph_exec || plan->graph_state != state || plan->graph_ws != ws || plan->graph_dt != dt ||
-        plan->graph_hold != hold) {
-      if (plan->graph_exec) {
-        HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
-        plan->graph_exec = nullptr;
-      }
-      Ctx cc = c;
-      cc.timer = nullptr;  // no event records inside a captured graph
-      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      one_step(cc, false, false);
-      hipGraph_t graph = nullptr;
-      const hipError_t le = hipGetLastError();
-      const hipError_t ce = hipStreamEndCapture(s, &graph);
-      if (le != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return hip_fail(le, "kernel launch during graph capture");
-      }
-      if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-      hipError_t ie = hipGraphInstantiate(&plan->graph_exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      if (ie != hipSuccess) {
-        plan->graph_exec = nullptr;
-        return hip_fail(ie, "hipGraphInstantiate");
-      }
-      plan->graph_state = state;
-      plan->graph_ws = ws;
-      plan->graph_hold = hold;
-      plan->graph_dt = dt;
-    }
-    // the captured step expects the z inverse of y_n: run it once, then replay
-    plan->ops.sched[plan->sched].rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
-    HIP_TRY(hipGetLastError());
-    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
-    return PSDNS_OK;
-  }
-  for (int n = 0; n < nsteps; ++n) {
-    one_step(c, n == 0, n == nsteps - 1);
-    HIP_TRY(hipGetLastError());
-  }
-  return PSDNS_OK;
+  return run_steps(plan, state, ws, dt, nsteps, static_cast<hipStream_t>(hip_stream), plan->use_graph, plan->timer);
 }
 
 psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable) {
@@ -671,7 +688,6 @@ psdns_status psdns_pressure(psdns_plan* plan, const void* state, void* ws, void*
   if (!state || !ws || !canonical_out) return fail(PSDNS_E_INVAL, "state, ws and canonical_out must be device pointers");
   if (state == canonical_out) return fail(PSDNS_E_INVAL, "canonical_out must not alias state");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
   std::vector<int> active(plan->p.batch);
   for (int i = 0; i < plan->p.batch; ++i) active[i] = plan->slots_host[i].active;
@@ -686,7 +702,6 @@ psdns_status psdns_spectra(psdns_plan* plan, const void* state, void* ws, double
   if (!state || !ws || !out) return fail(PSDNS_E_INVAL, "state, ws and out must be device pointers");
   if (flags & ~3) return fail(PSDNS_E_INVAL, "flags must be a combination of PSDNS_SPECTRA_SHELLS and PSDNS_SPECTRA_MOMENTS");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, ws, s)) return st;
   Ctx c = make_ctx(plan, ws);
   plan->ops.spectra(c, state, out, flags, s);
   HIP_TRY(hipGetLastError());
@@ -697,7 +712,6 @@ psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_i
   if (psdns_status s = check_plan(plan)) return s;
   if (!ws || !out) return fail(PSDNS_E_INVAL, "ws and out must be non-NULL");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
-  if (psdns_status st = ensure_ws(plan, const_cast<void*>(ws), s)) return st;
   std::vector<DynDev> d(plan->p.batch);
   Ctx c = make_ctx(plan, const_cast<void*>(ws));
   HIP_TRY(hipMemcpyAsync(d.data(), c.dyn, sizeof(DynDev) * d.size(), hipMemcpyDeviceToHost, s));
@@ -716,8 +730,14 @@ psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_i
 psdns_status psdns_clear_step_info(psdns_plan* plan, void* ws, void* hip_stream) {
   if (psdns_status s = check_plan(plan)) return s;
   if (!ws) return fail(PSDNS_E_INVAL, "ws is NULL");
-  plan->cleared_ws = nullptr;
-  return ensure_ws(plan, ws, static_cast<hipStream_t>(hip_stream));
+  return clear_slots(plan, ws, 0, plan->p.batch, static_cast<hipStream_t>(hip_stream));
+}
+
+psdns_status psdns_clear_slot_info(psdns_plan* plan, void* ws, int32_t slot, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!ws) return fail(PSDNS_E_INVAL, "ws is NULL");
+  if (slot < 0 || slot >= plan->p.batch) return fail(PSDNS_E_INVAL, "slot out of range");
+  return clear_slots(plan, ws, slot, 1, static_cast<hipStream_t>(hip_stream));
 }
 
 psdns_status psdns_get_state(psdns_plan* plan, const void* state, int32_t slot, void* canonical_out,

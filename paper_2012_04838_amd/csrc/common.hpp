@@ -43,7 +43,7 @@ struct SlotDev {
   double diff[3 + kMaxScalars];     // diffusivity of each spectral field
   double g[kMaxScalars][3];         // mean scalar gradients
   int active;
-  int forcing;                      // PSDNS_FORCING_POWER or PSDNS_FORCING_HOLD
+  int forcing;                      // PSDNS_FORCING_POWER, _HOLD or _STOCHASTIC
   double hold;                      // target band energy of PSDNS_FORCING_HOLD
   int integrator;                   // PSDNS_INTEGRATOR_IF or PSDNS_INTEGRATOR_EXPLICIT
   int pad_;
@@ -66,7 +66,7 @@ struct DynDev {
   double t;          // simulated time accumulated by psdns_step
   double scratch;    // reduction result used by init_field
   long long steps;   // steps taken by psdns_step
-  int flags;         // PSDNS_FLAG_* bits, sticky until psdns_clear_flags
+  int flags;         // PSDNS_FLAG_* bits, sticky until psdns_clear_step_info / psdns_clear_slot_info
   int pad_;
   // running max of |u1|+|u2|+|u3| over the grid during the stage-0 x pass, as the bits
   // of a non-negative double: their unsigned order is the numeric order (NaN above

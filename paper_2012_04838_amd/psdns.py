@@ -57,7 +57,7 @@ class PlanInfo(ctypes.Structure):
                                              "precision", "batch", "n_shells", "spectra_doubles")] + \
                [("state_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("elems_col", _c_int32), ("elems_x", _c_int32), ("n_schedules", _c_int32),
-                ("schedule", _c_int32)]
+                ("schedule", _c_int32), ("plan_bytes", ctypes.c_int64)]
 
 
 class ScheduleInfo(ctypes.Structure):
@@ -78,6 +78,7 @@ _lib = None
 _SIGS = {
     "psdns_state_bytes": (ctypes.c_size_t, [ctypes.POINTER(PlanParams)]),
     "psdns_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(PlanParams)]),
+    "psdns_plan_device_bytes": (ctypes.c_size_t, [ctypes.POINTER(PlanParams)]),
     "psdns_plan_create": (ctypes.c_int, [ctypes.POINTER(PlanParams), ctypes.POINTER(_c_void_p)]),
     "psdns_plan_destroy": (ctypes.c_int, [_c_void_p]),
     "psdns_plan_get_info": (ctypes.c_int, [_c_void_p, ctypes.POINTER(PlanInfo)]),
@@ -91,6 +92,7 @@ _SIGS = {
     "psdns_step": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, ctypes.c_double, _c_int32, _c_void_p]),
     "psdns_read_step_info": (ctypes.c_int, [_c_void_p, _c_void_p, ctypes.POINTER(StepInfo), _c_void_p]),
     "psdns_clear_step_info": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p]),
+    "psdns_clear_slot_info": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_get_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
@@ -158,6 +160,11 @@ def workspace_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int 
     return int(lib().psdns_workspace_bytes(ctypes.byref(p)))
 
 
+def plan_device_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> int:
+    p = plan_params(n, n_scalars, precision, batch)
+    return int(lib().psdns_plan_device_bytes(ctypes.byref(p)))
+
+
 class Plan:
     """A plan for N^3 grids with S scalars, a precision (32/64) and `batch` slots.
 
@@ -201,8 +208,11 @@ class Plan:
         return torch.zeros(int(self.info.state_bytes), dtype=torch.uint8, device="cuda")
 
     def new_workspace(self):
+        """A workspace with its per-slot records cleared (psdns_clear_step_info)."""
         torch = _torch()
-        return torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")
+        ws = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8, device="cuda")
+        self.clear_step_info(ws)
+        return ws
 
     def canonical_shape(self):
         n = self.n
@@ -251,6 +261,9 @@ class Plan:
 
     def clear_step_info(self, ws) -> None:
         _check(lib().psdns_clear_step_info(self._h, _ptr(ws), _stream()))
+
+    def clear_slot_info(self, ws, slot: int) -> None:
+        _check(lib().psdns_clear_slot_info(self._h, _ptr(ws), slot, _stream()))
 
     def get_state(self, state, slot: int = 0):
         """Canonical [field][kz][ky][kx] complex tensor (device) of one slot."""

@@ -2,18 +2,23 @@
 
 Each request is one realization: a seeded Rogallo initial field (Sec. 2.3) at N^3
 with 0-4 scalars, stepped `steps` times by the integrating-factor RK4 with
-dt from CFL (Eq. (10)), FP32.  Requests with the same (N, S) share one batched
+dt from CFL (Eq. (10)), FP32.  Requests with the same (N, S, CFL) share one batched
 plan (a "group"): every slot of the group is stepped by the same kernel
 launches, each slot with its own parameters and its own dt.  Groups run on their
 own HIP streams, so work of different sizes overlaps on the device.
 
-Admission is by HBM footprint: a group reserves state + workspace for its slot
-capacity when it is created (psdns_state_bytes + psdns_workspace_bytes, the whole
-device footprint), and a request waits until its group has a free slot or the
-memory budget allows creating the group.  Between launches a group retires
-finished slots (their spectra record and, if asked, final state are copied out)
-and admits waiting requests into free slots; a launch advances the group by the
-largest number of steps after which some slot changes state.
+Admission is by HBM footprint: a group reserves, for its slot capacity, the state,
+the workspace and the plan's own tables (psdns_state_bytes + psdns_workspace_bytes +
+psdns_plan_device_bytes, the library's whole device footprint) plus the buffers this
+loop adds (the spectra records and the copies of finished states), and a request
+waits until its group has a free slot or the memory budget allows creating the
+group.  The CFL number is part of the group key because one launch steps every
+slot of a group with the same CFL target.  Between launches a group retires
+finished slots (their spectra record, step flags and, if asked, final state are
+copied out; a run whose record carries a flag, a non-finite velocity or a CFL
+number above 1, is returned with `failed` set) and admits waiting requests into
+free slots; a launch advances the group by the largest number of steps after
+which some slot changes state.
 """
 from __future__ import annotations
 
@@ -50,11 +55,18 @@ class Request:
     k_force: float = 2.0
     schmidt: Tuple[float, ...] = (1.0, 0.7, 1.0, 1.0)
     keep_state: bool = False
+    # forcing of the band (psdns.FORCING_POWER with `power`, or FORCING_STOCHASTIC)
+    forcing: int = psdns.FORCING_POWER
+    stoch_sigma: float = 0.0
+    stoch_tl: float = 1.0
+    stoch_seed: int = 0
     # filled in by the server
     t_admit: float = math.nan
     t_done: float = math.nan
     spectra: Optional[dict] = None
     state: Optional[np.ndarray] = None
+    flags: int = 0                # PSDNS_FLAG_* bits of the run's step record
+    failed: bool = False
 
     @property
     def latency(self) -> float:
@@ -65,14 +77,26 @@ def default_capacity(n: int) -> int:
     return {8: 32, 16: 32, 32: 32, 64: 16, 128: 8, 256: 4, 512: 2}.get(n, 1)
 
 
+def footprint_bytes(n: int, s: int, precision: int, capacity: int) -> int:
+    """Device bytes a group of `capacity` slots holds: the library's state, workspace and
+    plan tables, the spectra records, and at most one canonical state copy per slot
+    (finished states kept for the caller)."""
+    lib_bytes = psdns.state_bytes(n, s, precision, capacity) + psdns.workspace_bytes(n, s, precision, capacity) + \
+        psdns.plan_device_bytes(n, s, precision, capacity)
+    ns = int(round(math.sqrt(3.0) * ((n - 1) // 3))) + 1
+    spectra = capacity * (ns * (1 + s) + 8 + 4 * s + 16 + 3 * s) * 8
+    canon = capacity * (3 + s) * n * n * (n // 2 + 1) * (8 if precision == 32 else 16)
+    return lib_bytes + spectra + canon
+
+
 class Group:
     """One batched plan for a given (N, S), with its buffers and stream."""
 
     def __init__(self, n: int, s: int, capacity: int, precision: int = 32, use_graph: bool = True,
-                 tune_cache: Optional[tune.TuneCache] = None, autotune: bool = True):
+                 tune_cache: Optional[tune.TuneCache] = None, autotune: bool = True, cfl: float = 0.5):
         import torch
 
-        self.n, self.s, self.capacity = n, s, capacity
+        self.n, self.s, self.capacity, self.cfl = n, s, capacity, cfl
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             self.plan = psdns.Plan(n, s, precision, capacity)
@@ -88,7 +112,7 @@ class Group:
                 tune.autotune(self.plan, self.state, self.ws, cache=tune_cache, reps=2)
         self.stream.synchronize()
         self.plan.set_graph(use_graph)
-        self.footprint = int(self.plan.info.state_bytes + self.plan.info.workspace_bytes)
+        self.footprint = footprint_bytes(n, s, precision, capacity)
         self.slots: List[Optional[Request]] = [None] * capacity
         self.remaining = [0] * capacity
         self.event = None          # completion of the last launch
@@ -148,12 +172,11 @@ class Server:
 
     # ---------------------------------------------------------------- admission
     def _group_for(self, req: Request) -> Optional[Group]:
-        key = (req.n, req.n_scalars)
+        key = (req.n, req.n_scalars, req.cfl)
         g = self.groups.get(key)
         if g is not None:
             return g
-        need = psdns.state_bytes(req.n, req.n_scalars, self.precision, self.capacity(req.n)) + \
-            psdns.workspace_bytes(req.n, req.n_scalars, self.precision, self.capacity(req.n))
+        need = footprint_bytes(req.n, req.n_scalars, self.precision, self.capacity(req.n))
         if self.reserved() + need > self.budget:
             # release idle groups to make room
             for k, og in list(self.groups.items()):
@@ -165,7 +188,7 @@ class Server:
         if self.reserved() + need > self.budget:
             return None
         g = Group(req.n, req.n_scalars, self.capacity(req.n), self.precision, self.use_graph,
-                  tune_cache=self.tune_cache, autotune=self.autotune)
+                  tune_cache=self.tune_cache, autotune=self.autotune, cfl=req.cfl)
         self.groups[key] = g
         return g
 
@@ -184,9 +207,11 @@ class Server:
                 continue
             g.plan.set_slot(slot, nu=req.nu, power=req.power, k_force=req.k_force,
                             schmidt=req.schmidt[:req.n_scalars],
-                            mean_grad=[(0.0, 1.0, 0.0)] * req.n_scalars, active=True)
+                            mean_grad=[(0.0, 1.0, 0.0)] * req.n_scalars, active=True, forcing=req.forcing,
+                            stoch_sigma=req.stoch_sigma, stoch_tl=req.stoch_tl, stoch_seed=req.stoch_seed)
             import torch
             with torch.cuda.stream(g.stream):
+                # also starts the slot's step record and stochastic forcing from zero
                 g.plan.init_field(g.state, g.ws, slot, seed=req.seed, k_peak=req.k_peak, kinetic_energy=1.0)
             g.slots[slot] = req
             g.remaining[slot] = req.steps
@@ -203,9 +228,8 @@ class Server:
         est_ms = 21.0 * (g.n / 512.0) ** 3 * (3 + g.s) / 5.0 * len(active)  # FP32 step time model
         by_time = max(1, int(self.launch_ms / max(est_ms, 1e-3)))
         chunk = min(min(g.remaining[i] for i in active), self.max_chunk, by_time)
-        cfl = g.slots[active[0]].cfl
         with torch.cuda.stream(g.stream):
-            g.plan.step(g.state, g.ws, -cfl, chunk)
+            g.plan.step(g.state, g.ws, -g.cfl, chunk)
             ev = torch.cuda.Event()
             ev.record(g.stream)
         g.event, g.inflight = ev, chunk
@@ -222,11 +246,14 @@ class Server:
         with torch.cuda.stream(g.stream):
             raw = g.plan.spectra_raw(g.state, g.ws, psdns.SPECTRA_SHELLS | psdns.SPECTRA_MOMENTS)
             states = {i: g.plan.get_state(g.state, i) for i in finished if g.slots[i].keep_state}
+            info = g.plan.read_step_info(g.ws)  # synchronises the group's stream
         g.stream.synchronize()
         raw = raw.cpu().numpy()
         now = self.now()
         for i in finished:
             req = g.slots[i]
+            req.flags = int(info[i]["flags"])
+            req.failed = req.flags != 0
             req.spectra = psdns.parse_spectra(raw[i], int(g.plan.info.n_shells), g.s)
             if i in states:
                 req.state = states[i].cpu().numpy()
@@ -294,12 +321,14 @@ def summarize(done: List[Request], wall: float, steps_n3: float) -> dict:
     lat = np.array([r.latency for r in done])
     out = {"requests": len(done), "wall_s": wall, "p50_s": float(np.percentile(lat, 50)),
            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
-           "requests_per_s": len(done) / wall, "N3_steps_per_s": steps_n3 / wall}
+           "requests_per_s": len(done) / wall, "N3_steps_per_s": steps_n3 / wall,
+           "failed": int(sum(1 for r in done if r.failed))}
     per = {}
     for n in sorted({r.n for r in done}):
         ln = np.array([r.latency for r in done if r.n == n])
+        work = sum(float(n) ** 3 * r.steps for r in done if r.n == n)
         per[str(n)] = {"requests": int(ln.size), "p50_s": float(np.percentile(ln, 50)),
-                       "p99_s": float(np.percentile(ln, 99))}
+                       "p99_s": float(np.percentile(ln, 99)), "N3_steps_per_s": work / wall}
     out["per_size"] = per
     return out
 

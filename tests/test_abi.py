@@ -32,6 +32,16 @@ def test_sizes_reject_invalid_params():
     assert psdns.state_bytes(512, 5, 64) == 0
     assert psdns.state_bytes(512, 2, 16) == 0
     assert psdns.workspace_bytes(2048, 0, 32) == 0
+    assert psdns.plan_device_bytes(100, 0, 64) == 0
+
+
+def test_plan_device_bytes_cover_the_plan_tables():
+    # twiddles (N complex) and one slot-parameter record per slot, each in 256-byte granules
+    for n, s, prec, b in [(32, 1, 64, 1), (512, 2, 32, 3)]:
+        got = psdns.plan_device_bytes(n, s, prec, b)
+        assert got >= n * (8 if prec == 32 else 16) + b * 8 * 16
+        assert got % 256 == 0
+        assert got < psdns.workspace_bytes(n, s, prec, b)
 
 
 def test_sizes_follow_the_compact_layout():

@@ -164,3 +164,71 @@ def test_every_schedule_repeats_bitwise(prec):
                     print(f"fp{prec} schedule {v} repeat {r}: max difference {d:.3e}", flush=True)
                 assert same, (v, r)
         torch.cuda.synchronize()
+
+
+def _shell_norms(y):
+    """Per-shell L2 norm (over fields and modes, half-spectrum weights) of a state."""
+    N = y.shape[-3]
+    sh = np.broadcast_to(ora.shell_index(N), y.shape[1:])
+    w = np.broadcast_to(ora.half_weights(N), y.shape[1:])
+    e = np.sum(np.abs(y) ** 2, axis=0) * w
+    return np.sqrt(np.bincount(sh.ravel(), weights=e.ravel(), minlength=ora.n_shells(N))[:ora.n_shells(N)])
+
+
+@pytest.mark.parametrize("N,S", [(64, 2), (128, 1)])
+def test_every_schedule_fp32_rhs_per_shell_on_flat_spectrum(N, S):
+    """FP32 right-hand side of every schedule against the FP64 oracle shell by shell, on
+    inputs whose spectrum is flat up to the retained K (so that every mode, not only the
+    low shells, carries O(1) amplitude): the relative error of each shell holding at
+    least 1e-6 of the largest is below the FP32 field bar of 1e-5."""
+    torch = torch_mod()
+    x = inputs.random_spectral_state(N, 3 + S, 70 + N, ora.kmax_retained(N), 1e6)
+    prm = _prm(S)
+    ref = ora.rhs(x, prm)
+    rn = _shell_norms(ref)
+    big = rn >= 1e-6 * rn.max()
+    assert big.sum() >= ora.kmax_retained(N)  # the flat input keeps the shells up to K busy
+    plan = make_plan(N, S, 32)
+    set_params(plan, 0, prm)
+    st, ws, out = plan.new_state(), plan.new_workspace(), plan.new_state()
+    plan.set_state(st, x, 0)
+    x32 = x.astype(np.complex64).astype(np.complex128)
+    ref32 = ora.rhs(x32, prm)  # the FP32 input's exact right-hand side
+    for v in range(plan.n_schedules):
+        plan.set_schedule(v)
+        plan.rhs(st, out, ws)
+        got = to_numpy(plan.get_state(out, 0))
+        torch.cuda.synchronize()
+        err = _shell_norms(got - ref32)[big] / rn[big]
+        print(f"N={N} S={S} schedule {v}: max shell rel error {err.max():.2e} "
+              f"(shell {int(np.argmax(err))}), field rel L2 {rel_l2(got, ref):.2e}", flush=True)
+        assert err.max() < 1e-5, (v, err.max())
+        assert rel_l2(got, ref) < 1e-5
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_every_schedule_repeats_bitwise_at_512(prec):
+    """One 512^3 S = 2 step per schedule, three times from the same initial field: every
+    repeat bitwise equal to the first (the FP64 fused and x passes at their full size)."""
+    torch = torch_mod()
+    N, S = 512, 2
+    prm = ora.Params(nu=7e-4, schmidt=(0.7, 1.0), mean_grad=((0.0, 1.0, 0.0),) * 2, power=0.1, k_force=2.0)
+    plan = make_plan(N, S, prec)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    for v in range(plan.n_schedules):
+        plan.set_schedule(v)
+        first = None
+        for r in range(3):
+            plan.init_field(st, ws, 0, seed=3, k_peak=8.0, kinetic_energy=1.0)
+            plan.step(st, ws, -0.5, 1)
+            if first is None:
+                first = st.clone()
+            else:
+                assert torch.equal(st, first), (v, r)
+        torch.cuda.synchronize()
+        print(f"512^3 fp{prec} schedule {v}: 3 repeats bitwise equal", flush=True)
+        del first
+    del st, ws
+    plan.close()
+    torch.cuda.empty_cache()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2012_04838_amd import psdns
-from paper_2012_04838_amd.serve import Request, Server, make_mix, summarize, viscosity_for
+from paper_2012_04838_amd.serve import Request, Server, footprint_bytes, make_mix, summarize, viscosity_for
 from tests.gpu_helpers import torch_mod
 
 pytestmark = pytest.mark.gpu
@@ -51,7 +51,7 @@ def test_result_same_alone_and_in_mix(autotune, tmp_path):
 
 def test_admission_respects_budget_and_reuses_slots():
     torch = torch_mod()
-    per = psdns.state_bytes(64, 1, 32, 2) + psdns.workspace_bytes(64, 1, 32, 2)
+    per = footprint_bytes(64, 1, 32, 2)
     reqs = [Request(rid=i, n=64, n_scalars=1, steps=4, seed=10 + i, nu=viscosity_for(64)) for i in range(5)]
     srv = Server(hbm_budget=int(1.5 * per), capacity=lambda n: 2, autotune=False)
     done = srv.run(reqs)
@@ -65,7 +65,7 @@ def test_admission_respects_budget_and_reuses_slots():
     big = Request(rid=99, n=128, n_scalars=0, steps=1, seed=1, nu=viscosity_for(128))
     srv.waiting.append(big)
     srv._admit()
-    assert big in srv.waiting and (128, 0) not in srv.groups
+    assert big in srv.waiting and not any(k[0] == 128 for k in srv.groups)
     srv.close()
     s = summarize(done, 1.0, srv.steps_done)
     assert s["p99_s"] >= s["p50_s"] > 0
@@ -77,3 +77,40 @@ def test_viscosity_for_matches_kmax_eta():
         nu = viscosity_for(n)
         eta = (nu ** 3 / 0.1) ** 0.25
         assert abs(eta * n / 3.0 - 1.5) < 1e-12
+
+
+def test_reused_slot_starts_a_fresh_stochastic_run():
+    """A one-slot group serves three stochastically forced requests in turn, so each
+    reuses the slot (and workspace) of the one before.  Each result is bitwise the one
+    the request gives alone: the slot's step count (which keys the random draws) and its
+    Ornstein-Uhlenbeck vectors start from zero for every new request."""
+    torch = torch_mod()
+    reqs = [Request(rid=i, n=32, n_scalars=1, steps=6, seed=40 + i, nu=viscosity_for(32), keep_state=True,
+                    forcing=psdns.FORCING_STOCHASTIC, stoch_sigma=0.05, stoch_tl=0.5, stoch_seed=7)
+            for i in range(3)]
+    srv = Server(capacity=lambda n: 1, autotune=False)
+    done = {r.rid: r for r in srv.run(copy.deepcopy(reqs))}
+    assert len(srv.groups) == 1
+    srv.close()
+    for r in reqs:
+        alone = Server(capacity=lambda n: 1, autotune=False)
+        res = alone.run([copy.deepcopy(r)])[0]
+        alone.close()
+        assert not res.failed and not done[r.rid].failed
+        assert np.array_equal(res.state, done[r.rid].state), r.rid
+    torch.cuda.synchronize()
+
+
+def test_diverging_run_is_reported_failed():
+    """A request whose step record carries a flag (here a CFL number above 1 from a
+    fixed CFL target of 1.5) comes back with `failed` set; the others of its mix do not."""
+    torch = torch_mod()
+    reqs = [Request(rid=0, n=32, n_scalars=0, steps=2, seed=5, nu=viscosity_for(32)),
+            Request(rid=1, n=32, n_scalars=0, steps=2, seed=6, nu=viscosity_for(32), cfl=1.5)]
+    srv = Server(capacity=lambda n: 2, autotune=False)
+    done = {r.rid: r for r in srv.run(reqs)}
+    srv.close()
+    assert not done[0].failed and done[0].flags == 0
+    assert done[1].failed and done[1].flags & psdns.FLAG_CFL
+    assert summarize(list(done.values()), 1.0, 1.0)["failed"] == 1
+    torch.cuda.synchronize()

@@ -106,3 +106,21 @@ def test_energy_budget_from_rhs_matches_spectra():
     dK = float(np.sum(w * np.real(np.conj(y) * F))) / float(N) ** 6
     assert abs(dK - (prm.power - sp["eps"])) < 1e-11 * sp["eps"]
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_shell_binning_of_hand_placed_modes(prec):
+    """Single modes with |k|^2 = 1, 2, 3, 4, 5, 6, 8, 12, 13 fall in shells
+    nint|k| = 1, 1, 2, 2, 2, 2, 3, 3, 4 (the table, not any binning code, decides);
+    each mode carries a distinct energy on u1 and E(s) is the sum placed in shell s."""
+    N = 16
+    modes = [((1, 0, 0), 1), ((1, 1, 0), 1), ((1, 1, 1), 2), ((2, 0, 0), 2), ((2, 1, 0), 2),
+             ((2, 1, 1), 2), ((2, 2, 0), 3), ((2, 2, 2), 3), ((3, 2, 0), 4)]
+    y = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    want = np.zeros(ora.n_shells(N))
+    for i, ((kx, ky, kz), shell) in enumerate(modes):
+        e = 0.01 * (i + 1)
+        y[0, kz % N, ky % N, kx] = float(N) ** 3 * np.sqrt(e)
+        want[shell] += e
+    sp, _, _ = _gpu_spectra(y, ora.Params(nu=0.01), prec, flags=1)
+    np.testing.assert_allclose(sp["E"], want, rtol=1e-14 if prec == 64 else 2e-7, atol=1e-17)

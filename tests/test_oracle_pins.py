@@ -319,6 +319,40 @@ def test_cfl_timestep():
     assert abs(ora.cfl_dt(st, C) - C * (2 * np.pi / N) / U) < 1e-14
 
 
+def test_cfl_velocity_scale_is_max_of_pointwise_sum():
+    """Eq. (10) takes the grid maximum of |u1| + |u2| + |u3| at one point.  On
+    u = (sin z, cos z, c sin x) (solenoidal) that is sqrt(2) + c, reached at z = pi/4,
+    x = pi/2; the sum of the per-component maxima (2 + c) and max |u|
+    (sqrt(1 + c^2)) both differ from it."""
+    N, c, C = 16, 0.5, 0.5
+    X, Y, Z = _grid(N)
+    st = np.stack([ora.to_spectral(f) for f in (np.sin(Z), np.cos(Z), c * np.sin(X))])
+    want = math.sqrt(2.0) + c
+    assert abs(want - (2.0 + c)) > 0.5 and abs(want - math.sqrt(1.0 + c * c)) > 0.5
+    assert abs(ora.max_abs_sum_velocity(st) - want) < 1e-14
+    assert abs(ora.cfl_dt(st, C) - C * (2 * np.pi / N) / want) < 1e-15
+
+
+def test_shell_binning_rounds_the_wavenumber_magnitude():
+    """Hand-placed single modes with |k|^2 = 1, 2, 3, 4, 5, 6, 8, 12, 13 (7 is not a sum of
+    three squares) fall in shells nint|k| = 1, 1, 2, 2, 2, 2, 3, 3, 4.  Each mode carries
+    a distinct energy e_i on u1 (kx > 0, so its conjugate partner doubles it), and E(s)
+    must be the sum of the energies placed in shell s by this table."""
+    N = 16
+    modes = [((1, 0, 0), 1), ((1, 1, 0), 1), ((1, 1, 1), 2), ((2, 0, 0), 2), ((2, 1, 0), 2),
+             ((2, 1, 1), 2), ((2, 2, 0), 3), ((2, 2, 2), 3), ((3, 2, 0), 4)]
+    st = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    want = np.zeros(ora.n_shells(N))
+    for i, ((kx, ky, kz), shell) in enumerate(modes):
+        assert kx * kx + ky * ky + kz * kz in (1, 2, 3, 4, 5, 6, 8, 12, 13)
+        e = 0.01 * (i + 1)
+        # energy of the pair (k, -k): 1/2 * 2 * |u_hat|^2 / N^6 = e
+        st[0, kz % N, ky % N, kx] = float(N) ** 3 * math.sqrt(e)
+        want[shell] += e
+    E = ora.spectra(st, ora.Params(nu=0.01))["E"]
+    np.testing.assert_allclose(E, want, rtol=1e-14, atol=1e-17)
+
+
 # ---------------------------------------------------------------- initial condition
 def test_splitmix64_reference_stream():
     """First two outputs of the SplitMix64 reference generator seeded with 0."""
