@@ -127,6 +127,10 @@ class Params:
                   "stochastic": the stochastic band forcing the paper names as an option
               (Sec. 2.3, after Eswaran & Pope): an Ornstein-Uhlenbeck vector b(k) per
               band mode, forcing term P(k) b (see ou_update)
+                  "alvelius": Alvelius' random band forcing, the other stochastic option of
+              Sec. 2.3 (see alvelius_force): drawn afresh every step, no work against the
+              velocity, power P (`power`) injected by the force-force term, SplitMix64 seed
+              stoch_seed
     stoch_sigma   standard deviation of each real and imaginary part of b (normalised,
               physical Fourier coefficients of the forcing) in the stationary state of
               the "stochastic" mode
@@ -286,6 +290,68 @@ def stochastic_forcing_field(b: dict, N: int) -> np.ndarray:
     return f
 
 
+def transverse_basis(kx: int, ky: int, kz: int):
+    """Unit vectors e1, e2 orthogonal to k and to each other: e1 = k x z_hat / |k x z_hat|
+    (x_hat when k is along z), e2 = k x e1 / |k| (the basis of the initial field)."""
+    k = np.array([kx, ky, kz], dtype=np.float64)
+    kp = math.hypot(kx, ky)
+    e1 = np.array([1.0, 0.0, 0.0]) if kp == 0.0 else np.array([ky / kp, -kx / kp, 0.0])
+    e2 = np.cross(k, e1) / math.sqrt(float(k @ k))
+    return e1, e2
+
+
+def alvelius_force(uhat: np.ndarray, h: float, n: int, prm: Params) -> np.ndarray:
+    """Random band forcing after Alvelius (the second stochastic option Sec. 2.3 names),
+    drawn afresh for step n (1, 2, ...) from the velocity u_hat at the start of the step
+    and held over its four stages; zero outside the band 0 < |k| <= k_F.
+
+    At every band mode the force lies in the plane normal to k:
+        f = F (g_A e^{i theta1} e1 + g_B e^{i theta2} e2),   g_A = sin 2 phi, g_B = cos 2 phi,
+    with phi and psi uniform on [0, 2 pi) (uniforms 2q and 2q+1 of SplitMix64(stoch_seed),
+    q = n C + i for band candidate i of C, the keying of ou_update) and theta2 = theta1 + psi.
+    theta1 solves Re(conj(u_hat) . f) = 0: with xi_j = u_hat . e_j,
+        a = g_A Re xi1 + g_B (Re xi2 cos psi + Im xi2 sin psi),
+        b = g_A Im xi1 + g_B (Im xi2 cos psi - Re xi2 sin psi),
+        a cos theta1 + b sin theta1 = 0  ->  theta1 = atan2(-a, b)  (0 when a = b = 0),
+    so the force does no work on the velocity of its step.  |f|^2 = F^2 at every mode
+    (g_A^2 + g_B^2 = 1); F is the same for all band modes and fixed by the power P that
+    the force-force term injects over a step of size h:
+        (h / 2) sum_band w |f|^2 / N^6 = P   ->   F = N^3 sqrt(2 P / (h W)),  W = sum_band w
+    (w the half-spectrum multiplicity).  On the plane kx = 0 the mode (0, -ky, -kz) takes
+    the conjugate of (0, ky, kz), so the force is real.
+
+    reading: the paper names Alvelius' scheme without its formulas.  This keeps its
+    defining choices (force normal to k, uncorrelated in time, no work against the
+    velocity mode by mode, power set by the force-force term, two random angles per mode)
+    with a spectrum that is flat over the band modes."""
+    N = uhat.shape[-3]
+    cands, C = stochastic_candidates(N, prm.k_force)
+    f = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    if prm.power <= 0.0 or not cands:
+        return f
+    W = float(sum(1 if kx == 0 else 2 for _, kx, _, _ in cands))
+    amp = float(N) ** 3 * math.sqrt(2.0 * prm.power / (h * W))
+    for i, kx, ky, kz in cands:
+        if kx == 0 and (ky < 0 or (ky == 0 and kz < 0)):
+            continue
+        u01 = uniform01(prm.stoch_seed, np.array([2 * (n * C + i), 2 * (n * C + i) + 1], dtype=np.uint64))
+        phi, psi = 2.0 * math.pi * float(u01[0]), 2.0 * math.pi * float(u01[1])
+        ga, gb = math.sin(2.0 * phi), math.cos(2.0 * phi)
+        e1, e2 = transverse_basis(kx, ky, kz)
+        u = uhat[:, kz % N, ky % N, kx]
+        xi1, xi2 = complex(u @ e1), complex(u @ e2)
+        a = ga * xi1.real + gb * (xi2.real * math.cos(psi) + xi2.imag * math.sin(psi))
+        b = ga * xi1.imag + gb * (xi2.imag * math.cos(psi) - xi2.real * math.sin(psi))
+        th1 = math.atan2(-a, b) if (a != 0.0 or b != 0.0) else 0.0
+        th2 = th1 + psi
+        f[:, kz % N, ky % N, kx] = amp * (ga * complex(math.cos(th1), math.sin(th1)) * e1 +
+                                          gb * complex(math.cos(th2), math.sin(th2)) * e2)
+    for i, kx, ky, kz in cands:
+        if kx == 0 and (ky < 0 or (ky == 0 and kz < 0)):
+            f[:, kz % N, ky % N, 0] = np.conj(f[:, (-kz) % N, (-ky) % N, 0])
+    return f
+
+
 # --------------------------------------------------------------------------
 # Right-hand side (Eqs. (6)-(8))
 # --------------------------------------------------------------------------
@@ -427,14 +493,16 @@ def step(state: np.ndarray, prm: Params, dt: float | None = None, nsteps: int = 
     With the "stochastic" forcing, stoch_state = {"b": {mode: vector}, "n": steps so far}
     carries the Ornstein-Uhlenbeck process across calls (a fresh process when None):
     every step first draws b with its own h (ou_update), then holds P(k) b over the four
-    stages.
+    stages.  With the "alvelius" forcing every step draws its force from y_n with its own
+    h and step number stoch_state["n"] (alvelius_force) and holds it over the stages.
     """
     N = state.shape[-3]
     L = linear_rates(N, prm)
     y = state.copy()
     dts = []
     stoch = prm.forcing and prm.forcing_mode == "stochastic"
-    if stoch and stoch_state is None:
+    alv = prm.forcing and prm.forcing_mode == "alvelius"
+    if (stoch or alv) and stoch_state is None:
         stoch_state = {"b": {}, "n": 0}
     for _ in range(nsteps):
         h = dt if cfl is None else cfl_dt(y, cfl)
@@ -444,6 +512,9 @@ def step(state: np.ndarray, prm: Params, dt: float | None = None, nsteps: int = 
             stoch_state["n"] += 1
             stoch_state["b"] = ou_update(stoch_state["b"], h, stoch_state["n"], N, prm)
             fvec = stochastic_forcing_field(stoch_state["b"], N)
+        if alv:
+            stoch_state["n"] += 1
+            fvec = alvelius_force(y[:3], h, stoch_state["n"], prm)
         if prm.integrator == "explicit":
             # the paper's scheme (Sec. 2.3): classical RK4 on the full right-hand side
             k1 = rhs(y, prm, form, fvec)

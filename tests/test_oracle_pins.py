@@ -716,3 +716,87 @@ def test_stochastic_forcing_with_zero_sigma_is_unforced():
     a = ora.step(y0, ora.Params(**base, forcing_mode="stochastic", stoch_sigma=0.0, stoch_tl=0.2), 0.01, 3)
     b = ora.step(y0, ora.Params(**base, forcing=False), 0.01, 3)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- Alvelius random forcing (Sec. 2.3)
+def _alv_prm(power=0.3, k_force=2.5, seed=9):
+    return ora.Params(nu=0.0, power=power, k_force=k_force, forcing_mode="alvelius", stoch_seed=seed)
+
+
+def test_alvelius_force_does_no_work_and_is_transverse():
+    """At every band mode Re(conj(u_hat) . f) = 0 (no force-velocity correlation) and
+    k . f = 0; outside the band f = 0."""
+    N = 16
+    y = _solenoidal_state(N, 0, 6)
+    f = ora.alvelius_force(y, 0.01, 3, _alv_prm())
+    kx, ky, kz = ora.kgrid(N)
+    band = ora.band_mask(N, 2.5)
+    work = np.real(np.sum(np.conj(y) * f, axis=0))
+    scale = np.max(np.abs(y)) * np.max(np.abs(f))
+    assert np.max(np.abs(work[band])) <= 1e-13 * scale
+    assert np.max(np.abs(kx * f[0] + ky * f[1] + kz * f[2])) <= 1e-12 * np.max(np.abs(f))
+    assert np.all(f[:, ~band] == 0)
+    assert np.count_nonzero(np.abs(f[0]) + np.abs(f[1]) + np.abs(f[2])) == int(band.sum())
+
+
+@pytest.mark.parametrize("h", [0.01, 0.0013])
+def test_alvelius_force_force_power_is_exact(h):
+    """(h / 2) sum w |f|^2 / N^6 = P for every draw: the power injected by the
+    force-force term does not depend on the velocity or on the random angles."""
+    N, P = 16, 0.3
+    for n, seed in ((1, 9), (7, 2)):
+        y = _solenoidal_state(N, 0, seed)
+        f = ora.alvelius_force(y, h, n, _alv_prm(P, seed=seed))
+        w = ora.half_weights(N)
+        inj = 0.5 * h * float(np.sum(w * np.sum(np.abs(f) ** 2, axis=0))) / float(N) ** 6
+        assert abs(inj - P) <= 1e-13 * P, (inj, P)
+    # a velocity that vanishes on the band still receives the same power
+    z = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
+    f = ora.alvelius_force(z, h, 1, _alv_prm(P))
+    inj = 0.5 * h * float(np.sum(ora.half_weights(N) * np.sum(np.abs(f) ** 2, axis=0))) / float(N) ** 6
+    assert abs(inj - P) <= 1e-13 * P
+
+
+def test_alvelius_force_is_real_and_redrawn_each_step():
+    N = 16
+    y = _solenoidal_state(N, 0, 8)
+    prm = _alv_prm()
+    f1 = ora.alvelius_force(y, 0.01, 1, prm)
+    for c in range(3):
+        phys = np.fft.ifftn(_full_from_half(f1[c]))
+        assert np.max(np.abs(phys.imag)) <= 1e-14 * np.max(np.abs(phys.real))
+    f2 = ora.alvelius_force(y, 0.01, 2, prm)
+    assert not np.allclose(f1, f2)
+    assert np.array_equal(f1, ora.alvelius_force(y, 0.01, 1, prm))
+
+
+def test_alvelius_step_injects_power_times_step():
+    """Inviscid step with the force held over the stages.  For u' = NL(u) + f with an
+    energy-conserving NL and f orthogonal to u0, the energy gained over h is
+        (h^2/2) (|f|^2 + <NL(u0), f>) + O(h^3 |f|^2),   (h^2/2) |f|^2 = P h,
+    so after removing the draw's force-nonlinear correlation the gain is P h to a relative
+    O(h): that remainder shrinks about fourfold when h does (f ~ h^-1/2), while the plain
+    gain approaches P h only like h^(1/2)."""
+    N, P = 16, 0.3
+    y0 = _solenoidal_state(N, 0, 5, kp=2.0, energy=0.5)
+    w = ora.half_weights(N)
+    rem = []
+    for h in (0.02, 0.005, 0.00125):
+        prm = _alv_prm(P)
+        y1 = ora.step(y0, prm, h, 1)
+        f = ora.alvelius_force(y0, h, 1, prm)
+        g0 = ora.nonlinear(y0, prm)
+        corr = 0.5 * h * h * float(np.sum(w * np.real(np.sum(np.conj(g0) * f, axis=0)))) / float(N) ** 6
+        dE = ora.kinetic_energy_of(y1) - ora.kinetic_energy_of(y0)
+        rem.append(abs((dE - corr) / (P * h) - 1.0))
+    assert rem[0] < 1e-3, rem
+    assert rem[1] < rem[0] / 2.5 and rem[2] < rem[1] / 2.5, rem
+
+
+def test_alvelius_with_zero_power_is_unforced():
+    N, S = 16, 1
+    y0 = _solenoidal_state(N, S, 4)
+    base = dict(nu=0.02, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),))
+    a = ora.step(y0, ora.Params(**base, forcing_mode="alvelius", power=0.0), 0.01, 3)
+    b = ora.step(y0, ora.Params(**base, forcing=False), 0.01, 3)
+    assert np.array_equal(a, b)
