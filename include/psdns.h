@@ -205,6 +205,27 @@ psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws,
 psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps,
                         void* hip_stream);
 
+/* Allocation-free stepping, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same steps as
+ * psdns_step on a workspace cleared with psdns_clear_step_info, but the workspace is a
+ * static device array of PSDNS_NOALLOC_MAX_WORKSPACE_BYTES inside the library (one per
+ * GPU, held until the process ends), so the call allocates nothing and takes no `ws`;
+ * the caller still passes the state (and, optionally, the record output).  Steps are
+ * launched directly (no graph of the plan's own).
+ *  - PSDNS_E_INVAL (nothing launched) if psdns_workspace_bytes of the plan exceeds
+ *    PSDNS_NOALLOC_MAX_WORKSPACE_BYTES, if the current device is not the plan's, or for
+ *    the arguments psdns_step rejects.
+ *  - Every call starts the step records and stochastic-forcing vectors of all slots from
+ *    zero (the array keeps the last call's contents otherwise).  If info_out is not NULL
+ *    it is a device buffer of batch psdns_step_info records that receives the records of
+ *    this call after its last step (stream-ordered; psdns_read_step_info does not see
+ *    them).
+ *  - All calls on one GPU share the array: calls that may overlap in time on one GPU
+ *    (other streams, other threads or plans) race and must be ordered by the caller. */
+#define PSDNS_NOALLOC_MAX_WORKSPACE_BYTES (256ull << 20)
+psdns_status psdns_step_noalloc(psdns_plan* plan, void* state, double dt, int32_t nsteps, psdns_step_info* info_out,
+                                void* hip_stream);
+
 /* Step through a captured HIP graph (off by default).  When enabled, psdns_step on a
  * non-default stream captures the launches of one RK4 step the first time it sees a given
  * (state, ws, dt) and then replays that graph once per step; a different state, workspace

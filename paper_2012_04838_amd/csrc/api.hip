@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -356,6 +357,50 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
 }
 
 
+// Step records of every slot into a caller's device buffer (psdns_step_noalloc).
+__global__ void k_export_info(const DynDev* __restrict__ d, const SlotDev* __restrict__ slots,
+                              psdns_step_info* __restrict__ out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    psdns_step_info r;
+    r.t = d[i].t;
+    r.dt = d[i].dt;
+    r.max_u = d[i].max_u;
+    r.steps = d[i].steps;
+    r.flags = d[i].flags;
+    r.active = slots[i].active;
+    out[i] = r;
+  }
+}
+
+}  // namespace
+
+// Workspace of psdns_step_noalloc: a fixed device array, one copy per GPU, held until the
+// process ends.  In host code `scratch` names a host-side handle, not device memory; its
+// device address is looked up once per device (hipGetSymbolAddress with that device
+// current) and only that address is used.
+static __device__ __align__(256) unsigned char scratch[PSDNS_NOALLOC_MAX_WORKSPACE_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+psdns_status scratch_of_device(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(PSDNS_E_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(PSDNS_E_HIP, "hipGetSymbolAddress(scratch) returned no address");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return PSDNS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -647,6 +692,33 @@ psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int3
   if (nsteps < 0) return fail(PSDNS_E_INVAL, "nsteps must be >= 0");
   if (!(dt != 0.0) || !std::isfinite(dt)) return fail(PSDNS_E_INVAL, "dt must be finite and nonzero");
   return run_steps(plan, state, ws, dt, nsteps, static_cast<hipStream_t>(hip_stream), plan->use_graph, plan->timer);
+}
+
+psdns_status psdns_step_noalloc(psdns_plan* plan, void* state, double dt, int32_t nsteps, psdns_step_info* info_out,
+                                void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state) return fail(PSDNS_E_INVAL, "state must be a device pointer");
+  if (nsteps < 0) return fail(PSDNS_E_INVAL, "nsteps must be >= 0");
+  if (!(dt != 0.0) || !std::isfinite(dt)) return fail(PSDNS_E_INVAL, "dt must be finite and nonzero");
+  if (plan->L.ws_bytes > (size_t)PSDNS_NOALLOC_MAX_WORKSPACE_BYTES)
+    return fail(PSDNS_E_INVAL, "the plan's workspace (" + std::to_string(plan->L.ws_bytes) +
+                                   " bytes) exceeds the static scratch of psdns_step_noalloc (" +
+                                   std::to_string((size_t)PSDNS_NOALLOC_MAX_WORKSPACE_BYTES) + " bytes)");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != plan->device) return fail(PSDNS_E_INVAL, "the current device is not the plan's device");
+  void* ws = nullptr;
+  if (psdns_status st = scratch_of_device(dev, &ws)) return st;
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  // the array keeps the last call's contents: every call starts its records from zero
+  if (psdns_status st = clear_slots(plan, ws, 0, plan->p.batch, s)) return st;
+  if (psdns_status st = run_steps(plan, state, ws, dt, nsteps, s, false, nullptr)) return st;
+  if (info_out) {
+    const int b = plan->p.batch;
+    k_export_info<<<(b + 63) / 64, 64, 0, s>>>(make_ctx(plan, ws).dyn, plan->slots_dev, info_out, b);
+    HIP_TRY(hipGetLastError());
+  }
+  return PSDNS_OK;
 }
 
 psdns_status psdns_set_graph(psdns_plan* plan, int32_t enable) {

@@ -97,6 +97,7 @@ _SIGS = {
     "psdns_set_state": (ctypes.c_int, [_c_void_p, _c_void_p, _c_int32, _c_void_p, _c_void_p]),
     "psdns_spectra": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_int32, _c_void_p]),
     "psdns_set_graph": (ctypes.c_int, [_c_void_p, _c_int32]),
+    "psdns_step_noalloc": (ctypes.c_int, [_c_void_p, _c_void_p, ctypes.c_double, _c_int32, _c_void_p, _c_void_p]),
     "psdns_pressure": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_void_p, _c_void_p]),
     "psdns_run": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, ctypes.c_double, _c_int32, _c_int32, _c_void_p,
                                  _c_int32, _c_void_p]),
@@ -254,6 +255,13 @@ class Plan:
         """dt > 0: fixed step; dt < 0: CFL target -dt (Eq. (10))."""
         _check(lib().psdns_step(self._h, _ptr(state), _ptr(ws), dt, nsteps, _stream()))
 
+    def step_noalloc(self, state, dt: float, nsteps: int = 1, info=None) -> None:
+        """Steps without a caller workspace (the library's static scratch); `info`, if given,
+        is a device uint8 tensor of batch * sizeof(StepInfo) bytes that receives the records
+        (parse with step_info_from_bytes)."""
+        _check(lib().psdns_step_noalloc(self._h, _ptr(state), dt, nsteps,
+                                        _ptr(info) if info is not None else None, _stream()))
+
     def read_step_info(self, ws):
         arr = (StepInfo * self.batch)()
         _check(lib().psdns_read_step_info(self._h, _ptr(ws), arr, _stream()))
@@ -365,6 +373,12 @@ class Plan:
         cnt = _c_int32()
         _check(lib().psdns_get_timing(self._h, arr, 16, ctypes.byref(cnt)))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
+
+
+def step_info_from_bytes(raw: bytes, batch: int):
+    """Records written by psdns_step_noalloc (psdns_step_info[batch]) as dicts."""
+    arr = (StepInfo * batch).from_buffer_copy(raw)
+    return [dict(t=a.t, dt=a.dt, max_u=a.max_u, steps=a.steps, flags=a.flags, active=a.active) for a in arr]
 
 
 def parse_spectra(r, ns: int, S: int) -> dict:
