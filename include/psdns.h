@@ -101,9 +101,24 @@ typedef struct {
  *        (2kf+1)(kz+kf)) of C = (kf+1)(2kf+1)^2, component c, real/imaginary part p;
  *        kf = floor(k_force), capped at k_max.  b lives in the workspace: it is zero after
  *        psdns_clear_step_info, psdns_clear_slot_info and psdns_init_field of the slot. */
+/* ALVELIUS: the other stochastic scheme the paper names (Sec. 2.3, after Alvelius): a force
+ *        drawn afresh every step from y_n and held over the four stages of that step, zero
+ *        outside the band (k_force below PSDNS_STOCHASTIC_KF_MAX + 1).  At band mode k
+ *          f = F (g_A e^{i th1} e1 + g_B e^{i th2} e2),  e1 = k x z_hat / |k x z_hat| (x_hat
+ *        for k along z), e2 = k x e1 / |k|, g_A = sin 2 phi, g_B = cos 2 phi, th2 = th1 + psi,
+ *        phi = 2 pi u_{2q}, psi = 2 pi u_{2q+1} from the SplitMix64(stoch_seed) uniforms (top
+ *        53 bits), q = n C + i (step n and candidate i of C as for STOCHASTIC), and
+ *        th1 = atan2(-a, b) (0 if a = b = 0) with xi_j = u_hat . e_j,
+ *          a = g_A Re xi1 + g_B (Re xi2 cos psi + Im xi2 sin psi),
+ *          b = g_A Im xi1 + g_B (Im xi2 cos psi - Re xi2 sin psi),
+ *        so that Re(conj(u_hat) . f) = 0: the force does no work on the velocity of its step.
+ *        F = N^3 sqrt(2 power / (dt W)), W the band modes counted twice for kx > 0 and once
+ *        for kx = 0, so that the force-force term injects `power`:
+ *        (dt / 2) sum w |f|^2 / N^6 = power.  On kx = 0, f(0,-ky,-kz) = conj f(0,ky,kz). */
 #define PSDNS_FORCING_POWER 0
 #define PSDNS_FORCING_HOLD 1
 #define PSDNS_FORCING_STOCHASTIC 2
+#define PSDNS_FORCING_ALVELIUS 3
 #define PSDNS_STOCHASTIC_KF_MAX 4
 
 /* Time integrator (Sec. 2.2-2.3).
@@ -118,16 +133,16 @@ typedef struct {
 /* Physical parameters of one slot (Sec. 2.1, Sec. 2.3, Table 2). */
 typedef struct {
   double nu;                              /* kinematic viscosity, >= 0 */
-  double power;                           /* forcing power P >= 0 (POWER); 0 gives decaying turbulence */
+  double power;                           /* forcing power P >= 0 (POWER, ALVELIUS); 0 gives decaying turbulence */
   double k_force;                         /* forced band 0 < |k| <= k_force */
   double schmidt[PSDNS_MAX_SCALARS];      /* Sc_s = nu / D_s, > 0 */
   double mean_grad[PSDNS_MAX_SCALARS][3]; /* g_s = grad <Phi_s>; Eq. (3) has (0, beta, 0) */
-  int32_t forcing;                        /* PSDNS_FORCING_POWER (default 0), _HOLD or _STOCHASTIC */
+  int32_t forcing;                        /* PSDNS_FORCING_POWER (default 0), _HOLD, _STOCHASTIC or _ALVELIUS */
   int32_t integrator;                     /* PSDNS_INTEGRATOR_IF (default 0) or PSDNS_INTEGRATOR_EXPLICIT */
   double hold_energy;                     /* HOLD: target band energy E_f > 0 */
   double stoch_sigma;                     /* STOCHASTIC: stationary deviation of each part of b, >= 0 */
   double stoch_tl;                        /* STOCHASTIC: correlation time T_L > 0 */
-  uint64_t stoch_seed;                    /* STOCHASTIC: SplitMix64 seed of the normal draws */
+  uint64_t stoch_seed;                    /* STOCHASTIC, ALVELIUS: SplitMix64 seed of the random draws */
 } psdns_slot_params;
 
 /* Per-slot stepping record (host copy). */

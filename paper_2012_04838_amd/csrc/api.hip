@@ -569,8 +569,12 @@ psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_par
     }
   }
   if (prm->forcing != PSDNS_FORCING_POWER && prm->forcing != PSDNS_FORCING_HOLD &&
-      prm->forcing != PSDNS_FORCING_STOCHASTIC)
-    return fail(PSDNS_E_INVAL, "forcing must be PSDNS_FORCING_POWER, PSDNS_FORCING_HOLD or PSDNS_FORCING_STOCHASTIC");
+      prm->forcing != PSDNS_FORCING_STOCHASTIC && prm->forcing != PSDNS_FORCING_ALVELIUS)
+    return fail(PSDNS_E_INVAL,
+                "forcing must be PSDNS_FORCING_POWER, PSDNS_FORCING_HOLD, PSDNS_FORCING_STOCHASTIC or "
+                "PSDNS_FORCING_ALVELIUS");
+  if (prm->forcing == PSDNS_FORCING_ALVELIUS && !(prm->k_force < PSDNS_STOCHASTIC_KF_MAX + 1.0))
+    return fail(PSDNS_E_INVAL, "k_force must be below PSDNS_STOCHASTIC_KF_MAX + 1 with PSDNS_FORCING_ALVELIUS");
   if (prm->forcing == PSDNS_FORCING_STOCHASTIC) {
     if (!(prm->stoch_sigma >= 0.0) || !std::isfinite(prm->stoch_sigma))
       return fail(PSDNS_E_INVAL, "stoch_sigma must be finite and >= 0");

@@ -1014,8 +1014,8 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     fetch(2, c3);
     fft<N, E, false>(c3, lds, j, tw);
 #endif
-    if (sp.forcing == PSDNS_FORCING_STOCHASTIC && valid) {
-      // the stochastic forcing P(k) b of the band modes (projected by k_stochastic_update)
+    if ((sp.forcing == PSDNS_FORCING_STOCHASTIC || sp.forcing == PSDNS_FORCING_ALVELIUS) && valid) {
+      // the stochastic forcing term of the band modes (solenoidal, from k_stochastic_update)
       // joins the transformed product; the projection below leaves it unchanged
       int kfs = 0;
       while ((double)(kfs + 1) * (kfs + 1) <= sp.kf2) ++kfs;
@@ -1303,12 +1303,67 @@ __device__ __forceinline__ double normal_at(uint64_t seed, uint64_t q) {
   return sqrt(-2.0 * log(1.0 - u1)) * cos(6.283185307179586476925286766559 * u2);
 }
 
-static __global__ void __launch_bounds__(256)
-k_stochastic_update(const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, double* __restrict__ fband,
-                    Geom g) {
+// Alvelius-type band forcing (the second stochastic option of Sec. 2.3), drawn once per step
+// from y_n with that step's h: at band mode k, f = F (g_A e^{i th1} e1 + g_B e^{i th2} e2),
+// g_A = sin 2 phi, g_B = cos 2 phi, phi and psi uniform (SplitMix64 uniforms 2q, 2q + 1,
+// q = n C + i), th2 = th1 + psi, th1 = atan2(-a, b) (0 when a = b = 0) so that
+// Re(conj(u_hat) . f) = 0, with xi_j = u_hat . e_j and
+//   a = g_A Re xi1 + g_B (Re xi2 cos psi + Im xi2 sin psi),
+//   b = g_A Im xi1 + g_B (Im xi2 cos psi - Re xi2 sin psi);
+// F = N^3 sqrt(2 P / (h W)), W the half-spectrum count of band modes, so that the
+// force-force term injects P: (h/2) sum w |f|^2 / N^6 = P.  Written to the forcing-term
+// entries of the band table.
+template <typename T>
+__device__ void alvelius_mode(int kx, int ky, int kz, const cpx<T>* __restrict__ ybase, long long stf, int M, int PX,
+                              uint64_t seed, uint64_t q, double amp, double* __restrict__ e) {
+  const double two_pi = 6.283185307179586476925286766559;
+  const double phi = two_pi * unit_double(splitmix64_at(seed, 2 * q));
+  const double psi = two_pi * unit_double(splitmix64_at(seed, 2 * q + 1));
+  const double ga = sin(2.0 * phi), gb = cos(2.0 * phi);
+  const double fx = kx, fy = ky, fz = kz;
+  const double kmag = sqrt(fx * fx + fy * fy + fz * fz);
+  const double kperp = sqrt(fx * fx + fy * fy);
+  double e1[3], e2[3];
+  if (kperp == 0.0) {
+    e1[0] = 1.0; e1[1] = 0.0; e1[2] = 0.0;
+  } else {
+    e1[0] = fy / kperp; e1[1] = -fx / kperp; e1[2] = 0.0;
+  }
+  e2[0] = (fy * e1[2] - fz * e1[1]) / kmag;
+  e2[1] = (fz * e1[0] - fx * e1[2]) / kmag;
+  e2[2] = (fx * e1[1] - fy * e1[0]) / kmag;
+  const int kyc = ky >= 0 ? ky : ky + M, kzc = kz >= 0 ? kz : kz + M;
+  const long long o = st_row(kzc, kyc, M, PX) + kx;
+  double x1r = 0.0, x1i = 0.0, x2r = 0.0, x2i = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const cpx<T> u = ybase[o + c * stf];
+    x1r += double(u.x) * e1[c];
+    x1i += double(u.y) * e1[c];
+    x2r += double(u.x) * e2[c];
+    x2i += double(u.y) * e2[c];
+  }
+  const double cp = cos(psi), sp = sin(psi);
+  const double a = ga * x1r + gb * (x2r * cp + x2i * sp);
+  const double b = ga * x1i + gb * (x2i * cp - x2r * sp);
+  const double th1 = (a != 0.0 || b != 0.0) ? atan2(-a, b) : 0.0;
+  const double th2 = th1 + psi;
+  const double ar = amp * ga * cos(th1), ai = amp * ga * sin(th1);
+  const double br = amp * gb * cos(th2), bi = amp * gb * sin(th2);
+  for (int c = 0; c < 6; ++c) e[c] = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    e[6 + 2 * c] = ar * e1[c] + br * e2[c];
+    e[6 + 2 * c + 1] = ai * e1[c] + bi * e2[c];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_stochastic_update(const cpx<T>* __restrict__ yn, const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn,
+                    double* __restrict__ fband, Geom g) {
   const int slot = blockIdx.x;
   const SlotDev& sp = slots[slot];
-  if (!sp.active || sp.forcing != PSDNS_FORCING_STOCHASTIC) return;
+  if (!sp.active || (sp.forcing != PSDNS_FORCING_STOCHASTIC && sp.forcing != PSDNS_FORCING_ALVELIUS)) return;
+  const bool alv = sp.forcing == PSDNS_FORCING_ALVELIUS;
   int kf = 0;
   while ((double)(kf + 1) * (kf + 1) <= sp.kf2) ++kf;
   if (kf > g.K) kf = g.K;
@@ -1318,7 +1373,7 @@ k_stochastic_update(const SlotDev* __restrict__ slots, const DynDev* __restrict_
   const uint64_t n = (uint64_t)dyn[slot].steps;
   const double a = exp(-h / sp.tl);
   const double c = sp.sigma * sqrt(fmax(0.0, 1.0 - a * a));
-  // per candidate: b (3 complex) then N^3 P(k) b (3 complex)
+  // per candidate: b (3 complex) then the forcing term (3 complex)
   double* tab = fband + (long long)slot * kStochCand * 12;
   auto decode = [&](int i, int& kx, int& ky, int& kz) {
     kx = i % (kf + 1);
@@ -1327,11 +1382,27 @@ k_stochastic_update(const SlotDev* __restrict__ slots, const DynDev* __restrict_
     const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
     return k2 > 0.0 && k2 <= sp.kf2;
   };
+  double amp = 0.0;
+  if (alv) {
+    // W: band modes counted with their half-spectrum multiplicity (the same count on every thread)
+    double wsum = 0.0;
+    for (int i = 0; i < ncand; ++i) {
+      int kx, ky, kz;
+      if (decode(i, kx, ky, kz)) wsum += kx == 0 ? 1.0 : 2.0;
+    }
+    const double n3 = double(g.N) * g.N * g.N;
+    amp = (sp.power > 0.0 && h > 0.0 && wsum > 0.0) ? n3 * sqrt(2.0 * sp.power / (h * wsum)) : 0.0;
+  }
+  const cpx<T>* ybase = yn + (long long)slot * g.F * g.st_field;
   for (int i = threadIdx.x; i < ncand; i += blockDim.x) {
     int kx, ky, kz;
     if (!decode(i, kx, ky, kz)) continue;
     if (kx == 0 && (ky < 0 || (ky == 0 && kz < 0))) continue;
     double* e = tab + i * 12;
+    if (alv) {
+      alvelius_mode<T>(kx, ky, kz, ybase, g.st_field, g.M, g.PX, sp.seed, n * (uint64_t)ncand + (uint64_t)i, amp, e);
+      continue;
+    }
     for (int comp = 0; comp < 3; ++comp) {
       const uint64_t q = ((n * (uint64_t)ncand + (uint64_t)i) * 3 + (uint64_t)comp) * 2;
       e[2 * comp] = a * e[2 * comp] + c * normal_at(sp.seed, q);
@@ -1920,7 +1991,7 @@ struct Step {
       TimedLaunch tl(x.timer, KID_DT, s);
       k_step_dt<<<g.batch, 64, 0, s>>>(x.slots, x.dyn, g, dt_arg);
       // returns at once for slots without the stochastic forcing
-      k_stochastic_update<<<g.batch, 256, 0, s>>>(x.slots, x.dyn, x.fband, g);
+      k_stochastic_update<T><<<g.batch, 256, 0, s>>>(static_cast<const cpx<T>*>(state), x.slots, x.dyn, x.fband, g);
     }
     {
       TimedLaunch tl(x.timer, KID_YFWD, s);

@@ -33,6 +33,7 @@ class PlanParams(ctypes.Structure):
 FORCING_POWER = 0
 FORCING_HOLD = 1
 FORCING_STOCHASTIC = 2
+FORCING_ALVELIUS = 3
 INTEGRATOR_IF = 0
 INTEGRATOR_EXPLICIT = 1
 SPECTRUM_CONFIG = 0

@@ -9,3 +9,10 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running check (large grids)")
+
+
+
+def pytest_sessionstart(session):
+    # lets tests.gpu_helpers.progress print past the output capture
+    import tests.gpu_helpers as helpers
+    helpers.CAPTURE_MANAGER = session.config.pluginmanager.getplugin("capturemanager")

@@ -5,6 +5,18 @@ import numpy as np
 
 import oracle as ora
 
+CAPTURE_MANAGER = None  # set by conftest at session start
+
+
+def progress(msg: str) -> None:
+    """Print a progress line at once, past pytest's output capture, so that a long GPU
+    test is visibly alive while it runs."""
+    if CAPTURE_MANAGER is not None:
+        with CAPTURE_MANAGER.global_and_fixture_disabled():
+            print(msg, flush=True)
+    else:
+        print(msg, flush=True)
+
 
 def torch_mod():
     import torch
@@ -21,13 +33,16 @@ def set_params(plan, slot, prm: "ora.Params", active=True):
     from paper_2012_04838_amd import psdns
     hold = prm.forcing and prm.forcing_mode == "hold"
     stoch = prm.forcing and prm.forcing_mode == "stochastic"
-    mode = psdns.FORCING_HOLD if hold else (psdns.FORCING_STOCHASTIC if stoch else psdns.FORCING_POWER)
-    plan.set_slot(slot, nu=prm.nu, power=(prm.power if prm.forcing and mode == psdns.FORCING_POWER else 0.0),
+    alv = prm.forcing and prm.forcing_mode == "alvelius"
+    mode = psdns.FORCING_HOLD if hold else (psdns.FORCING_STOCHASTIC if stoch else
+                                            (psdns.FORCING_ALVELIUS if alv else psdns.FORCING_POWER))
+    powered = prm.forcing and mode in (psdns.FORCING_POWER, psdns.FORCING_ALVELIUS)
+    plan.set_slot(slot, nu=prm.nu, power=(prm.power if powered else 0.0),
                   k_force=prm.k_force, schmidt=list(prm.schmidt), mean_grad=[list(g) for g in prm.mean_grad],
                   active=active, forcing=mode, hold_energy=prm.hold_energy if hold else 0.0,
                   integrator=psdns.INTEGRATOR_EXPLICIT if prm.integrator == "explicit" else psdns.INTEGRATOR_IF,
                   stoch_sigma=prm.stoch_sigma if stoch else 0.0, stoch_tl=prm.stoch_tl if stoch else 1.0,
-                  stoch_seed=prm.stoch_seed if stoch else 0)
+                  stoch_seed=prm.stoch_seed if (stoch or alv) else 0)
 
 
 def to_numpy(t):

@@ -22,13 +22,13 @@ import numpy as np
 import pytest
 
 import oracle as ora
-from tests.gpu_helpers import make_plan, rel_l2, set_params, to_numpy, torch_mod
+from tests.gpu_helpers import make_plan, progress, rel_l2, set_params, to_numpy, torch_mod
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
 def _log(msg):
-    print(f"[configs] {msg}", flush=True)
+    progress(f"[configs] {msg}")
 
 
 def _device_rel_l2(torch, a32, b64):
