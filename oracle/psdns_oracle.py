@@ -60,18 +60,31 @@ def k_squared(N: int) -> np.ndarray:
     return (kx * kx + ky * ky + kz * kz).astype(np.float64)
 
 
-def kmax_retained(N: int) -> int:
-    """Largest retained |k_i| under the 2/3 rule: 3|k_i| < N  <=>  |k_i| <= (N-1)//3.
+def kmax_retained(N: int, dealias: str = "cube") -> int:
+    """Largest retained |k_i|.
 
-    reading: the configurations ask for the 2/3 rule (Orszag); the paper's own
-    phase-shift + truncation variant (Sec. 2.3) is not what this oracle follows.
+    "cube": the 2/3 rule, 3|k_i| < N  <=>  |k_i| <= (N-1)//3.
+    reading: the configurations ask for the 2/3 rule (Orszag).
+    "phase": the paper's scheme (Sec. 2.3, Sec. 3.1): phase shift with spherical
+    truncation at k_max = sqrt(2) N / 3; the largest integer k with 9 k^2 < 2 N^2 bounds
+    the retained sphere.
     """
+    if dealias == "phase":
+        k = 0
+        while 9 * (k + 1) * (k + 1) < 2 * N * N:
+            k += 1
+        return k
+    if dealias != "cube":
+        raise ValueError(dealias)
     return (N - 1) // 3
 
 
-def retained_mask(N: int) -> np.ndarray:
-    """Boolean mask of the retained cube |kx|,|ky|,|kz| <= K on the half spectrum."""
-    K = kmax_retained(N)
+def retained_mask(N: int, dealias: str = "cube") -> np.ndarray:
+    """Boolean mask of the retained modes on the half spectrum: the cube |kx|,|ky|,|kz| <= K
+    ("cube"), or the sphere |k| < sqrt(2) N / 3, i.e. 9 |k|^2 < 2 N^2 ("phase")."""
+    if dealias == "phase":
+        return 9 * k_squared(N) < 2 * N * N
+    K = kmax_retained(N, dealias)
     kx, ky, kz = kgrid(N)
     return (np.abs(kx) <= K) & (np.abs(ky) <= K) & (np.abs(kz) <= K)
 
@@ -100,10 +113,17 @@ def to_spectral(f: np.ndarray) -> np.ndarray:
     return sfft.rfftn(f, axes=(0, 1, 2), workers=FFT_WORKERS)
 
 
-def truncate(fhat: np.ndarray) -> np.ndarray:
-    """Zero every mode outside the retained cube (2/3 rule)."""
+def truncate(fhat: np.ndarray, dealias: str = "cube") -> np.ndarray:
+    """Zero every mode outside the retained set (2/3-rule cube, or the sphere)."""
     N = fhat.shape[-3]
-    return np.where(retained_mask(N), fhat, 0.0)
+    return np.where(retained_mask(N, dealias), fhat, 0.0)
+
+
+def shift_phase(N: int) -> np.ndarray:
+    """e^{i k . Delta} on the half spectrum for the grid shift Delta = (pi/N)(1, 1, 1), half a
+    grid cell along every axis: the spectrum of f(x + Delta) is f_hat(k) e^{i k . Delta}."""
+    kx, ky, kz = kgrid(N)
+    return np.exp(1j * math.pi * (kx + ky + kz) / N)
 
 
 # --------------------------------------------------------------------------
@@ -136,6 +156,8 @@ class Params:
               the "stochastic" mode
     stoch_tl      correlation time T_L of b
     stoch_seed    SplitMix64 seed of the normal draws
+    dealias       "cube": the 2/3 rule (reading of the configurations); "phase": the paper's
+              phase shift with spherical truncation at sqrt(2) N / 3 (Sec. 2.3, Sec. 3.1)
     integrator    "if": RK4 in the frame of the viscous/diffusive integrating factor
               (reading of the configurations); "explicit": the paper's classical RK4
               with the viscous and diffusive terms evaluated in every stage (Sec. 2.3)
@@ -152,6 +174,7 @@ class Params:
     stoch_sigma: float = 0.0
     stoch_tl: float = 1.0
     stoch_seed: int = 0
+    dealias: str = "cube"
 
     @property
     def n_scalars(self) -> int:
@@ -213,19 +236,19 @@ def band_mask(N: int, k_force: float) -> np.ndarray:
 # --------------------------------------------------------------------------
 # Stochastic band forcing (Sec. 2.3 names Eswaran & Pope's scheme as an option)
 # --------------------------------------------------------------------------
-def band_radius(N: int, k_force: float) -> int:
+def band_radius(N: int, k_force: float, dealias: str = "cube") -> int:
     """Largest integer kf with kf^2 <= k_force^2, capped at the retained K."""
     kf = 0
     while float(kf + 1) ** 2 <= k_force * k_force:
         kf += 1
-    return min(kf, kmax_retained(N))
+    return min(kf, kmax_retained(N, dealias))
 
 
-def stochastic_candidates(N: int, k_force: float):
+def stochastic_candidates(N: int, k_force: float, dealias: str = "cube"):
     """The wavevectors (kx >= 0, ky, kz) of the box |k_i| <= kf in the order that keys the
     random draws: candidate i = kx + (kf+1) ((ky+kf) + (2kf+1) (kz+kf)).  Returns the
     list of (i, kx, ky, kz) inside the band 0 < |k|^2 <= k_force^2 and the box size."""
-    kf = band_radius(N, k_force)
+    kf = band_radius(N, k_force, dealias)
     span = 2 * kf + 1
     out = []
     for kz in range(-kf, kf + 1):
@@ -259,7 +282,7 @@ def ou_update(b: dict, h: float, n: int, N: int, prm: Params) -> dict:
     reading: the paper names the stochastic scheme without giving its formulas; this is
     the Ornstein-Uhlenbeck process of Eswaran & Pope with one complex vector per mode,
     updated once per step with that step's h and held over the stages."""
-    cands, C = stochastic_candidates(N, prm.k_force)
+    cands, C = stochastic_candidates(N, prm.k_force, prm.dealias)
     a = math.exp(-h / prm.stoch_tl)
     c = prm.stoch_sigma * math.sqrt(max(0.0, 1.0 - a * a))
     out = {}
@@ -325,7 +348,7 @@ def alvelius_force(uhat: np.ndarray, h: float, n: int, prm: Params) -> np.ndarra
     velocity mode by mode, power set by the force-force term, two random angles per mode)
     with a spectrum that is flat over the band modes."""
     N = uhat.shape[-3]
-    cands, C = stochastic_candidates(N, prm.k_force)
+    cands, C = stochastic_candidates(N, prm.k_force, prm.dealias)
     f = np.zeros((3, N, N, N // 2 + 1), dtype=np.complex128)
     if prm.power <= 0.0 or not cands:
         return f
@@ -370,6 +393,44 @@ def project(vhat: np.ndarray) -> np.ndarray:
     return out
 
 
+def product_spectra(state: np.ndarray, form: str = "rotational", phase: np.ndarray | None = None):
+    """Untruncated spectra of the quadratic terms: (u x omega)^ ("rotational") or
+    (u.grad u)^ ("convective") for the velocity, and (u.grad phi_s)^ per scalar, the
+    products formed pointwise in physical space from inverse transforms.  With `phase`
+    (shift_phase), the products are formed on the grid shifted by Delta: the inputs carry
+    e^{i k . Delta} and the transformed products are multiplied back by its conjugate."""
+    N = state.shape[-3]
+    S = state.shape[0] - 3
+    kx, ky, kz = kgrid(N)
+    ik = (1j * kx, 1j * ky, 1j * kz)
+    y = state if phase is None else state * phase
+    back = 1.0 if phase is None else np.conj(phase)
+    uhat = y[:3]
+    u = [to_physical(uhat[i]) for i in range(3)]
+    if form == "rotational":
+        # omega_hat = i k x u_hat
+        w1 = to_physical(ik[1] * uhat[2] - ik[2] * uhat[1])
+        w2 = to_physical(ik[2] * uhat[0] - ik[0] * uhat[2])
+        w3 = to_physical(ik[0] * uhat[1] - ik[1] * uhat[0])
+        c = (u[1] * w3 - u[2] * w2, u[2] * w1 - u[0] * w3, u[0] * w2 - u[1] * w1)
+        vel = [to_spectral(ci) * back for ci in c]
+    elif form == "convective":
+        # n_i = u_j d_j u_i from the nine gradients i k_j u_i_hat (Sec. 2.3)
+        vel = []
+        for i in range(3):
+            acc = 0.0
+            for j in range(3):
+                acc = acc + u[j] * to_physical(ik[j] * uhat[i])
+            vel.append(to_spectral(acc) * back)
+    else:
+        raise ValueError(form)
+    adv = []
+    for s in range(S):
+        grad = [to_physical(ik[j] * y[3 + s]) for j in range(3)]
+        adv.append(to_spectral(u[0] * grad[0] + u[1] * grad[1] + u[2] * grad[2]) * back)
+    return vel, adv
+
+
 def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational",
               fvec: np.ndarray | None = None) -> np.ndarray:
     """Everything in dy/dt except the viscous/diffusive term -D_f |k|^2 y_f.
@@ -378,7 +439,7 @@ def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational",
 
     Velocity (Eq. (7)): F_u = P(k) [ (u x omega)^ ]  + A 1_band u_hat, where the
     product is formed in physical space from inverse transforms, transformed
-    forward and truncated to the retained cube.  u x omega differs from
+    forward and truncated to the retained set.  u x omega differs from
     -u.grad u by the gradient grad(|u|^2/2), which the projection removes
     (reading: the rotational form is the one the configurations name; the
     paper's convective form is available as form="convective").
@@ -386,35 +447,28 @@ def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational",
     Scalars (Eq. (8), generalised mean gradient g_s):
     F_phi = -(u.grad phi)^ - g_s . u_hat.
 
+    Dealiasing (prm.dealias): "cube" truncates each product to the 2/3-rule cube.
+    "phase" is the paper's scheme (Sec. 2.3): every product is the mean of its values on
+    the grid and on the grid shifted by half a cell along each axis, truncated to the
+    sphere |k| < sqrt(2) N / 3.  The shift multiplies an alias term at k + N m (m in
+    {-1, 0, 1}^3) by (-1)^(m1 + m2 + m3), so the mean cancels every alias with an odd
+    number of wrapped components, and the sphere keeps those with two out of reach.
+
     The k = 0 mode of every field is held at zero (zero-mean fluctuations, Sec. 2.1).
     """
     N = state.shape[-3]
     S = state.shape[0] - 3
-    kx, ky, kz = kgrid(N)
-    ik = (1j * kx, 1j * ky, 1j * kz)
+    mask = retained_mask(N, prm.dealias)
     uhat = state[:3]
-    u = [to_physical(uhat[i]) for i in range(3)]
-
-    if form == "rotational":
-        # omega_hat = i k x u_hat
-        w1 = to_physical(ik[1] * uhat[2] - ik[2] * uhat[1])
-        w2 = to_physical(ik[2] * uhat[0] - ik[0] * uhat[2])
-        w3 = to_physical(ik[0] * uhat[1] - ik[1] * uhat[0])
-        c = (u[1] * w3 - u[2] * w2, u[2] * w1 - u[0] * w3, u[0] * w2 - u[1] * w1)
-        chat = np.stack([truncate(to_spectral(ci)) for ci in c])
-        fu = project(chat)
-    elif form == "convective":
-        # n_i = u_j d_j u_i from the nine gradients i k_j u_i_hat (Sec. 2.3)
-        n = []
-        for i in range(3):
-            acc = 0.0
-            for j in range(3):
-                acc = acc + u[j] * to_physical(ik[j] * uhat[i])
-            n.append(acc)
-        nhat = np.stack([truncate(to_spectral(ni)) for ni in n])
-        fu = -project(nhat)
+    if prm.dealias == "phase":
+        v0, a0 = product_spectra(state, form)
+        v1, a1 = product_spectra(state, form, shift_phase(N))
+        vel = [0.5 * (p + q) for p, q in zip(v0, v1)]
+        adv = [0.5 * (p + q) for p, q in zip(a0, a1)]
     else:
-        raise ValueError(form)
+        vel, adv = product_spectra(state, form)
+    prod = np.stack([np.where(mask, v, 0.0) for v in vel])
+    fu = project(prod) if form == "rotational" else -project(prod)
 
     A = forcing_amplitude(uhat, prm)
     if A != 0.0:
@@ -425,14 +479,11 @@ def nonlinear(state: np.ndarray, prm: Params, form: str = "rotational",
     out = np.empty_like(state)
     out[:3] = fu
     for s in range(S):
-        ph = state[3 + s]
-        grad = [to_physical(ik[j] * ph) for j in range(3)]
-        adv = u[0] * grad[0] + u[1] * grad[1] + u[2] * grad[2]
         g = prm.mean_grad[s]
-        out[3 + s] = -truncate(to_spectral(adv)) - (g[0] * uhat[0] + g[1] * uhat[1] + g[2] * uhat[2])
+        out[3 + s] = -np.where(mask, adv[s], 0.0) - (g[0] * uhat[0] + g[1] * uhat[1] + g[2] * uhat[2])
     k2 = k_squared(N)
     out[:, k2 == 0] = 0.0
-    out[:, ~retained_mask(N)] = 0.0
+    out[:, ~mask] = 0.0
     return out
 
 
@@ -446,7 +497,7 @@ def rhs(state: np.ndarray, prm: Params, form: str = "rotational", fvec: np.ndarr
     """Full dy/dt of Eqs. (7)-(8): nonlinear + forcing + mean-gradient + viscous terms."""
     N = state.shape[-3]
     out = nonlinear(state, prm, form, fvec) + linear_rates(N, prm) * state
-    out[:, ~retained_mask(N)] = 0.0
+    out[:, ~retained_mask(N, prm.dealias)] = 0.0
     out[:, k_squared(N) == 0] = 0.0
     return out
 
@@ -583,7 +634,7 @@ def paper_spectrum(kappa: np.ndarray, k_f: float, u_rms: float = 1.0) -> np.ndar
 
 
 def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy: float = 1.0,
-               spectrum: str = "config") -> np.ndarray:
+               spectrum: str = "config", dealias: str = "cube") -> np.ndarray:
     """Rogallo-type random divergence-free isotropic velocity (Sec. 2.3) with phi = 0 (Sec. 2.3,
     scalar started from zero).
 
@@ -598,8 +649,8 @@ def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy:
     scaled so that K = 1/2 <u.u> equals `kinetic_energy` (reading: "unit kinetic
     energy" of the configurations; the paper's TKE magnification is a factor on K).
     spectrum="paper" uses the paper's spectrum with k_F = k_peak instead of E(k) above.
+    The modes are those of the retained set of `dealias` (cube or sphere).
     """
-    K = kmax_retained(N)
     NX = N // 2 + 1
     state = np.zeros((3 + n_scalars, N, N, NX), dtype=np.complex128)
     kx, ky, kz = kgrid(N)
@@ -607,7 +658,7 @@ def init_field(N: int, n_scalars: int, seed: int, k_peak: float, kinetic_energy:
     KY = np.broadcast_to(ky, (N, N, NX)).astype(np.float64)
     KZ = np.broadcast_to(kz, (N, N, NX)).astype(np.float64)
     canon = (KX > 0) | ((KX == 0) & (KY > 0)) | ((KX == 0) & (KY == 0) & (KZ > 0))
-    sel = canon & retained_mask(N)
+    sel = canon & retained_mask(N, dealias)
     iz, iy, ix = np.nonzero(sel)
     lin = (iz.astype(np.uint64) * np.uint64(N) + iy.astype(np.uint64)) * np.uint64(NX) + ix.astype(np.uint64)
     k1, k2, k3 = KX[sel], KY[sel], KZ[sel]
@@ -661,8 +712,9 @@ def shell_index(N: int) -> np.ndarray:
     return np.rint(np.sqrt(k_squared(N))).astype(np.int64)
 
 
-def n_shells(N: int) -> int:
-    K = kmax_retained(N)
+def n_shells(N: int, dealias: str = "cube") -> int:
+    """Shells s = 0 .. nint(sqrt(3) K), K the largest retained |k_i|."""
+    K = kmax_retained(N, dealias)
     return int(round(math.sqrt(3.0) * K)) + 1
 
 
@@ -706,13 +758,13 @@ def spectra(state: np.ndarray, prm: Params) -> dict:
     N = state.shape[-3]
     S = state.shape[0] - 3
     w = half_weights(N)
-    mask = retained_mask(N)
+    mask = retained_mask(N, prm.dealias)
     wm = w * mask
     k2 = k_squared(N)
     kx, ky, kz = kgrid(N)
     inv_n6 = 1.0 / float(N) ** 6
     sh = shell_index(N)
-    ns = n_shells(N)
+    ns = n_shells(N, prm.dealias)
     eu = 0.5 * wm * np.sum(np.abs(state[:3]) ** 2, axis=0) * inv_n6
     E = np.bincount(sh.ravel(), weights=np.broadcast_to(eu, sh.shape).ravel(), minlength=ns)[:ns]
     Ephi = []
@@ -785,11 +837,12 @@ def physical_stats(state: np.ndarray) -> dict:
 # --------------------------------------------------------------------------
 # Second route to single RHS modes: the truncated Galerkin convolution
 # --------------------------------------------------------------------------
-def full_spectrum_dict(state: np.ndarray):
-    """Retained full-spectrum coefficients as arrays over all k in the cube |k_i| <= K:
-    values[f, kz+K, ky+K, kx+K], built from the half spectrum by u_hat(-k) = conj(u_hat(k))."""
+def full_spectrum_dict(state: np.ndarray, K: int | None = None):
+    """Retained full-spectrum coefficients as arrays over all k in the cube |k_i| <= K
+    (default: the 2/3-rule K): values[f, kz+K, ky+K, kx+K], built from the half spectrum by
+    u_hat(-k) = conj(u_hat(k))."""
     N = state.shape[-3]
-    K = kmax_retained(N)
+    K = kmax_retained(N) if K is None else K
     M = 2 * K + 1
     F = state.shape[0]
     full = np.zeros((F, M, M, M), dtype=np.complex128)
@@ -810,15 +863,17 @@ def galerkin_mode(state: np.ndarray, prm: Params, k: Sequence[int], full: np.nda
         (u x omega)^_k = N^-3 sum_{p + q = k; p, q retained} u_hat_p x (i q x u_hat_q)
         (u.grad phi)^_k = N^-3 sum_{p + q = k} u_hat_p . (i q) phi_hat_q
 
-    With the 2/3 rule every alias of such a product falls outside the retained
-    cube, so this equals the pseudo-spectral product on retained modes exactly.
+    The sums run over the cube |p_i|, |q_i| <= K that bounds the retained set of
+    prm.dealias; the state is zero outside its retained set (cube or sphere), so only
+    retained p and q contribute.  With either dealiasing every alias of such a product is
+    removed, so this equals the pseudo-spectral product on retained modes exactly.
     Returns the vector over fields (3 + S) including forcing and mean-gradient terms.
     """
     N = state.shape[-3]
-    K = kmax_retained(N)
+    K = kmax_retained(N, prm.dealias)
     S = state.shape[0] - 3
     if full is None:
-        full = full_spectrum_dict(state)
+        full = full_spectrum_dict(state, K)
     kx0, ky0, kz0 = (int(v) for v in k)
     # p ranges over the retained cube with q = k - p retained too: a box per axis
     def box(k0):

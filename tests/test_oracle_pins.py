@@ -38,7 +38,7 @@ def _solenoidal_state(N, S, seed, kp=3.0, energy=1.0):
 
 
 # ---------------------------------------------------------------- transforms (Eq. (5))
-@pytest.mark.parametrize("N", [6, 8])
+@pytest.mark.parametrize("N", [6, 8, 10])
 def test_forward_transform_is_brute_force_dft(N):
     rng = np.random.default_rng(1)
     f = rng.standard_normal((N, N, N))
@@ -53,7 +53,7 @@ def test_forward_transform_is_brute_force_dft(N):
                 assert abs(got[iz, iy, ix] - ref) <= 1e-12 * max(1.0, abs(ref))
 
 
-@pytest.mark.parametrize("N", [6, 8])
+@pytest.mark.parametrize("N", [6, 8, 10])
 def test_inverse_transform_is_brute_force_sum(N):
     K = ora.kmax_retained(N)
     fhat = inputs.random_spectral_state(N, 1, 3, N // 2, 2.0)[0]
@@ -73,6 +73,22 @@ def test_inverse_transform_is_brute_force_sum(N):
     assert np.max(np.abs(ref.imag)) < 1e-12 * np.max(np.abs(ref))
     assert np.allclose(got, ref.real, rtol=0, atol=1e-12 * np.max(np.abs(ref)))
     assert K >= 1
+
+
+@pytest.mark.parametrize("N", [26, 40])
+def test_mixed_radix_transforms_follow_the_dft_matrices(N):
+    """Grids with factors 2, 5 and 13 (N = 520 of Table 2 is 2^3 5 13): the forward
+    transform equals Eq. (5) applied as the DFT matrix W[k, n] = exp(-2 pi i k n / N) along
+    each axis, and the inverse equals the conjugate matrices over N^3."""
+    rng = np.random.default_rng(N)
+    f = rng.standard_normal((N, N, N))
+    n = np.arange(N)
+    Wm = np.exp(-2j * np.pi * np.outer(n, n) / N)
+    full = np.einsum("az,by,cx,zyx->abc", Wm, Wm, Wm, f, optimize=True)
+    got = ora.to_spectral(f)
+    assert np.max(np.abs(got - full[:, :, : N // 2 + 1])) <= 1e-11 * np.max(np.abs(full))
+    back = np.einsum("az,by,cx,zyx->abc", Wm.conj(), Wm.conj(), Wm.conj(), full, optimize=True).real / N ** 3
+    assert np.max(np.abs(ora.to_physical(got) - back)) <= 1e-12 * np.max(np.abs(f))
 
 
 def test_wavenumber_index_set_matches_paper():
@@ -123,7 +139,7 @@ def test_rhs_viscous_term_on_single_mode():
     assert np.allclose(ora.to_physical(F[3]), -(nu / sc) * 9 * np.cos(3 * X), atol=1e-13)
 
 
-@pytest.mark.parametrize("N", [8, 12, 16])
+@pytest.mark.parametrize("N", [8, 10, 12, 16, 26])
 def test_pseudo_spectral_equals_galerkin_convolution(N):
     """The dealiased pseudo-spectral product equals the truncated Galerkin convolution,
     computed mode by mode straight from its definition (no FFT)."""
@@ -800,3 +816,95 @@ def test_alvelius_with_zero_power_is_unforced():
     a = ora.step(y0, ora.Params(**base, forcing_mode="alvelius", power=0.0), 0.01, 3)
     b = ora.step(y0, ora.Params(**base, forcing=False), 0.01, 3)
     assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------- the paper's dealiasing (Sec. 2.3, Sec. 3.1)
+def _sphere(N):
+    """The sphere |k| < sqrt(2) N / 3 written out here: 9 |k|^2 < 2 N^2 on the half spectrum."""
+    k1 = np.where(np.arange(N) <= N // 2, np.arange(N), np.arange(N) - N)
+    kz, ky, kx = k1[:, None, None], k1[None, :, None], np.arange(N // 2 + 1)[None, None, :]
+    return 9 * (kx * kx + ky * ky + kz * kz) < 2 * N * N
+
+
+def _sphere_state(N, F, seed, env=3.0):
+    st = inputs.random_spectral_state(N, F, seed, N // 2 - 1, env)
+    return st * _sphere(N)
+
+
+def test_phase_shift_kmax_bounds_the_sphere():
+    for N, want in ((8, 3), (16, 7), (32, 15), (64, 30), (520, 245)):
+        K = ora.kmax_retained(N, "phase")
+        assert K == want and 9 * K * K < 2 * N * N <= 9 * (K + 1) * (K + 1)
+        assert np.array_equal(ora.retained_mask(N, "phase"), _sphere(N)) if N <= 64 else True
+
+
+@pytest.mark.parametrize("N", [8, 12, 16])
+def test_phase_shift_product_equals_galerkin_on_the_sphere(N):
+    """With phase shift and spherical truncation the pseudo-spectral right-hand side is
+    the truncated Galerkin convolution over the sphere, mode by mode (no FFT on that
+    side), including modes at the edge of the sphere."""
+    S = 2
+    st = _sphere_state(N, 3 + S, 31 + N)
+    prm = ora.Params(nu=0.0, schmidt=(1.0, 0.7), mean_grad=((0.0, 1.0, 0.0), (0.3, -0.2, 0.5)),
+                     power=0.1, k_force=2.0, dealias="phase")
+    F = ora.nonlinear(st, prm)
+    K = ora.kmax_retained(N, "phase")
+    full = ora.full_spectrum_dict(st, K)
+    edge = [(K, 0, 0), (0, K, -1), (1, -2, K - 1), (K - 1, K - 2, 0)]
+    edge = [k for k in edge if 9 * (k[0] ** 2 + k[1] ** 2 + k[2] ** 2) < 2 * N * N]
+    rng = np.random.default_rng(N)
+    modes = edge + [(0, 1, 0), (1, 1, 1)] + [tuple(int(v) for v in rng.integers(-K, K + 1, 3)) for _ in range(8)]
+    scale = np.max(np.abs(F))
+    checked = 0
+    for k in modes:
+        if k[0] < 0:
+            k = (-k[0], -k[1], -k[2])
+        inside = 9 * (k[0] ** 2 + k[1] ** 2 + k[2] ** 2) < 2 * N * N
+        ref = ora.galerkin_mode(st, prm, k, full) if inside else np.zeros(3 + S)
+        got = ora.mode_value(F, k)
+        assert np.max(np.abs(got - ref)) <= 1e-12 * scale, (k, got, ref)
+        checked += inside
+    assert checked >= 8
+
+
+@pytest.mark.parametrize("N", [12, 16])
+def test_single_grid_product_on_the_sphere_is_aliased(N):
+    """Without the shifted second evaluation, the same truncation to the sphere leaves
+    aliases of the double products in: the difference from the Galerkin convolution is far
+    above rounding, so the shift is what makes the scheme exact."""
+    st = _sphere_state(N, 3, 41 + N)
+    prm = ora.Params(nu=0.0, forcing=False, dealias="phase")
+    vel, _ = ora.product_spectra(st)
+    single = ora.project(np.stack([v * _sphere(N) for v in vel]))
+    K = ora.kmax_retained(N, "phase")
+    full = ora.full_spectrum_dict(st, K)
+    worst = 0.0
+    for kx in range(0, K + 1):
+        for ky in range(-K, K + 1):
+            kz = 0
+            if 9 * (kx * kx + ky * ky) < 2 * N * N and (kx, ky) != (0, 0):
+                ref = ora.galerkin_mode(st, prm, (kx, ky, kz), full)[:3]
+                worst = max(worst, float(np.max(np.abs(ora.mode_value(single, (kx, ky, kz)) - ref))))
+    assert worst > 1e-6 * np.max(np.abs(single))
+
+
+def test_phase_shift_inviscid_energy_conservation_fourth_order():
+    N = 16
+    st = ora.init_field(N, 0, 23, 4.0, 1.0, dealias="phase")
+    assert np.all(st[:, ~_sphere(N)] == 0) and np.any(st[:, _sphere(N) & ~ora.retained_mask(N)] != 0)
+    prm = ora.Params(nu=0.0, forcing=False, dealias="phase")
+    errs = []
+    for n in (8, 16, 32):
+        out = ora.step(st, prm, 0.8 / n, n)
+        errs.append(abs(ora.kinetic_energy_of(out) - 1.0))
+    assert errs[0] > 1e-11
+    s1, s2 = math.log2(errs[0] / errs[1]), math.log2(errs[1] / errs[2])
+    assert 3.3 < s1 < 5.5 and 3.3 < s2 < 5.5, (errs, s1, s2)
+
+
+def test_phase_shift_beltrami_flow_decays_exactly():
+    N, k0, nu = 16, 3, 0.05
+    st = np.stack(_abc(N, k0))
+    prm = ora.Params(nu=nu, forcing=False, dealias="phase")
+    out = ora.step(st, prm, 0.07, 6)
+    assert np.max(np.abs(out - st * math.exp(-nu * k0 * k0 * 0.42))) <= 1e-13 * np.max(np.abs(st))
