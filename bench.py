@@ -6,7 +6,14 @@ with spectrum peak k_p = 8 and unit kinetic energy, RK4 with the integrating
 factor and dt from CFL = 0.5 every step.  FP32 is the reported value; the same
 run in FP64 is reported beside it.  Inputs are resident in HBM before timing.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-tune] [--n 512] [--scalars 2]
+Timing: the timed region is K steps replayed from a captured HIP graph on one stream
+(value and ms_per_step).  Two further untimed passes of K steps give the median of
+single graph replays (per-step events) and the per-kernel durations of eager steps
+(per-kernel events, for the roofline).  A second leg runs 1024^3 with one scalar
+(nu = 3e-4) in FP32 and FP64.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-fp64] [--no-tune]
+                       [--n 512] [--scalars 2] [--no-1024] [--serve-requests R]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -95,13 +102,27 @@ def step_bytes(n: int, s: int, prec: int) -> float:
     return 4.0 * (kb["y_inverse"] + kb["x_pass"] + kb["y_forward"] + kb["z_forward_update_inverse"])
 
 
-def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3, schedule=-1):
+def survey_step_bytes(n: int, s: int, prec: int) -> float:
+    """The reference byte model of one RK4 step: five passes per stage, each reading and
+    writing its fields once (6+3S fields through the inverse passes, 3+S through the
+    forward passes), retained modes only, and 13 (3+S) compact-state transfers per step
+    for y_n, the accumulator and the stage input."""
+    K = (n - 1) // 3
+    M, KX = 2 * K + 1, K + 1
+    F, FB = 3 + s, 6 + 3 * s
+    hc, a_, b_ = M * M * KX, n * M * KX, n * n * KX
+    entries = 4 * (F * hc + 2 * FB * a_ + 2 * FB * b_ + 2 * F * b_ + 2 * F * a_) + 13 * F * hc
+    return entries * (8 if prec == 32 else 16)
+
+
+def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3, schedule=-1, nu=None, schmidt=None):
     import torch
 
     from paper_2012_04838_amd import psdns
 
     plan = psdns.Plan(n, s, prec, 1)
-    plan.set_slot(0, nu=NU, power=POWER, k_force=KF, schmidt=SCHMIDT[:s], mean_grad=GRAD[:s])
+    plan.set_slot(0, nu=NU if nu is None else nu, power=POWER, k_force=KF,
+                  schmidt=SCHMIDT[:s] if schmidt is None else schmidt, mean_grad=GRAD[:s])
     st = plan.new_state()
     ws = plan.new_workspace()
     plan.init_field(st, ws, 0, seed=seed, k_peak=KP, kinetic_energy=1.0)
@@ -113,53 +134,80 @@ def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3, schedule=-1):
         # autotuner (outside the timed region): every compiled schedule on this state
         best, ms_each = plan.tune(st, ws, tune_reps)
         sched = {"chosen": best, "ms_per_stage": ms_each, "chosen_desc": plan.schedule_info(best)}
-    plan.step(st, ws, -0.5, warmup)
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    plan.set_timing(True)
-    plan.get_timing()  # clear
+    stream = torch.cuda.Stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        # timed region: K steps replayed from the captured step graph
+        plan.set_graph(True)
+        plan.step(st, ws, -0.5, warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record(stream)
+        plan.step(st, ws, -0.5, steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        # untimed pass: the same replays with an event pair around each (per-step median)
+        plan.set_timing(True)
+        plan.get_timing()
+        plan.step(st, ws, -0.5, steps)
+        graph_t = plan.get_timing(detail=True)
+        # untimed pass: eager steps with an event pair around each kernel (roofline)
+        plan.set_graph(False)
+        plan.step(st, ws, -0.5, steps)
+        timing = plan.get_timing()
+        plan.set_timing(False)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    plan.step(st, ws, -0.5, steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    timing = plan.get_timing()
-    plan.set_timing(False)
     info = plan.read_step_info(ws)[0]
     ok = info["flags"] == 0 and math.isfinite(info["max_u"])
     del st, ws
     plan.close()
     torch.cuda.empty_cache()
-    return {"ms_total": ms, "wall_s": wall, "timing": timing, "info": info, "finite": ok, "schedule": sched}
+    step = graph_t.get("step", {})
+    return {"ms_total": ms, "wall_s": wall, "timing": timing, "info": info, "finite": ok, "schedule": sched,
+            "graph_step_median_ms": step.get("median_ms"), "graph_step_min_ms": step.get("min_ms"),
+            "graph_steps_timed": step.get("launches")}
 
 
 def copy_reference(gbytes: float, reps: int = 5):
-    """Plain device-to-device copy of a known size: measured copy bandwidth, and the
-    reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters."""
+    """Copy bandwidth of a known size: torch's device copy and the library's own streaming
+    kernel over a sweep of grid sizes (the best is the achievable-bandwidth reference);
+    the torch copy is also the dispatch that scales the FETCH_SIZE / WRITE_SIZE counters."""
     import torch
 
-    n = int(gbytes * 1e9) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    from paper_2012_04838_amd import psdns
+
+    n = int(gbytes * 1e9) // 16 * 16
+    a = torch.ones(n // 4, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    nbytes = 2 * 4 * n
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms = timed(lambda: b.copy_(a))
+    out = {"bytes_read": n, "bytes_written": n, "ms": ms, "GBs": 2 * n / (ms * 1e-3) / 1e9}
+    kern = {}
+    for blocks in (1024, 2048, 4096, 8192, 16384):
+        kms = timed(lambda: psdns.stream_copy(b.view(torch.uint8), a.view(torch.uint8), blocks))
+        kern[str(blocks)] = 2 * n / (kms * 1e-3) / 1e9
+    assert torch.equal(a, b)
+    best = max(kern, key=lambda k: kern[k])
+    out["stream_copy_GBs"] = kern
+    out["stream_copy_best"] = {"blocks": int(best), "GBs": kern[best]}
     del a, b
     torch.cuda.empty_cache()
-    return {"bytes_read": 4 * n, "bytes_written": 4 * n, "ms": ms, "GBs": nbytes / (ms * 1e-3) / 1e9}
+    return out
 
 
 def serve_mix(n_requests: int, load: float, seed: int = 0):
@@ -193,9 +241,30 @@ def serve_mix(n_requests: int, load: float, seed: int = 0):
     return res
 
 
+def _cpu_description():
+    """CPU model, and the logical CPUs and physical cores this process may run on."""
+    model, topo = None, {}
+    try:
+        cur = {}
+        with open("/proc/cpuinfo") as f:
+            for line in f.read().split("\n\n"):
+                d = dict(kv.split(":", 1) for kv in line.split("\n") if ":" in kv)
+                d = {k.strip(): v.strip() for k, v in d.items()}
+                if "processor" in d:
+                    topo[int(d["processor"])] = (d.get("physical id", "0"), d.get("core id", d["processor"]))
+                    model = model or d.get("model name")
+    except OSError:
+        pass
+    cpus = sorted(os.sched_getaffinity(0))
+    phys = len({topo[c] for c in cpus if c in topo}) or None
+    return {"cpu_model": model, "logical_cpus": len(cpus), "physical_cores": phys}
+
+
 def cpu_baseline(n, s):
-    """One oracle right-hand-side evaluation at the benchmark size (a quarter of an RK4
-    step; the integrating-factor update adds well under 5%), scaled to steps/s."""
+    """The FP64 oracle on this host: one right-hand-side evaluation at the benchmark size
+    (a quarter of an RK4 step; the integrating-factor update adds well under 5%), scaled
+    to steps/s; and, beside it, the small configurations in full: 32^3 (20 steps) and
+    256^3 (3 CFL steps)."""
     import oracle as ora
 
     prm = ora.Params(nu=NU, schmidt=SCHMIDT[:s], mean_grad=GRAD[:s], power=POWER, k_force=KF)
@@ -203,10 +272,44 @@ def cpu_baseline(n, s):
     t0 = time.perf_counter()
     ora.nonlinear(y, prm)
     dt = time.perf_counter() - t0
+    del y
     per_step = 4.0 * dt
-    return {"value": n ** 3 / per_step, "unit": "N^3*RK4-steps/s", "cores": ora.FFT_WORKERS, "kind": "oracle",
-            "sample": f"one FP64 oracle RHS evaluation at {n}^3 S={s} ({dt:.1f} s), x4 per RK4 step; "
-                      f"scipy.fft with {ora.FFT_WORKERS} workers, numpy elementwise single-threaded"}
+    others = {}
+    p1 = ora.Params(nu=0.01, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1, k_force=2.0)
+    y1 = ora.init_field(32, 1, 1, 4.0, 1.0)
+    t0 = time.perf_counter()
+    ora.step(y1, p1, 0.005, 20)
+    w1 = time.perf_counter() - t0
+    others["32^3 S=1 FP64, 20 steps dt 0.005"] = {"s_per_step": w1 / 20, "N3_steps_per_s": 32 ** 3 * 20 / w1}
+    p2 = ora.Params(nu=0.0015, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1, k_force=2.0)
+    y2 = ora.init_field(256, 1, 2, 6.0, 1.0)
+    t0 = time.perf_counter()
+    ora.step(y2, p2, None, 3, cfl=0.5)
+    w2 = time.perf_counter() - t0
+    others["256^3 S=1 FP64, 3 CFL steps"] = {"s_per_step": w2 / 3, "N3_steps_per_s": 256 ** 3 * 3 / w2}
+    del y1, y2
+    out = {"value": n ** 3 / per_step, "unit": "N^3*RK4-steps/s", "cores": ora.FFT_WORKERS, "kind": "oracle",
+           "sample": f"one FP64 oracle RHS evaluation at {n}^3 S={s} ({dt:.1f} s), x4 per RK4 step; "
+                     f"scipy.fft with {ora.FFT_WORKERS} workers, numpy elementwise single-threaded",
+           "other_configs": others}
+    out.update(_cpu_description())
+    return out
+
+
+def leg_summary(r, n, s, prec, steps):
+    """Throughput, step bandwidth under both byte models and the graph-replay median."""
+    ms = r["ms_total"] / steps
+    out = {"value": float(n) ** 3 / (ms * 1e-3), "ms_per_step": ms,
+           "graph_step_median_ms": r["graph_step_median_ms"], "graph_step_min_ms": r["graph_step_min_ms"],
+           "frac_survey_model": survey_step_bytes(n, s, prec) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "frac_design_bytes": step_bytes(n, s, prec) / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+           "finite": r["finite"], "schedule": r["schedule"]["chosen"] if r["schedule"] else 0}
+    kb = kernel_bytes(n, s, prec)
+    tim = r["timing"]
+    out["kernels"] = {k: {"launches": tim[k][0], "avg_ms": tim[k][1] / max(tim[k][0], 1),
+                          "alg_GBs": (kb[k] / (tim[k][1] / tim[k][0] * 1e-3) / 1e9) if k in kb and tim[k][0] else None}
+                      for k in tim if tim[k][0]}
+    return out
 
 
 def main():
@@ -218,6 +321,8 @@ def main():
     ap.add_argument("--scalars", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-1024", action="store_true", help="skip the 1024^3 S=1 leg")
+    ap.add_argument("--steps-1024", type=int, default=10)
     ap.add_argument("--copy-gb", type=float, default=1.0,
                     help="size of the copy-bandwidth reference (0 disables)")
     ap.add_argument("--serve-requests", type=int, default=40,
@@ -237,7 +342,6 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     n, s = args.n, args.scalars
-    n3 = float(n) ** 3
     copy = copy_reference(args.copy_gb) if args.copy_gb > 0 else None
     tr = 0 if args.no_tune else 3
     r32 = run_gpu(n, s, 32, args.steps, args.warmup, tune_reps=tr, schedule=args.schedule)
@@ -247,8 +351,8 @@ def main():
         r64 = run_gpu(n, s, 64, args.steps, args.warmup, tune_reps=tr, schedule=args.schedule)
         print(f"[bench] fp64 done: {r64['ms_total'] / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
 
-    ms32 = r32["ms_total"] / args.steps
-    value = n3 / (ms32 * 1e-3)
+    leg32 = leg_summary(r32, n, s, 32, args.steps)
+    ms32 = leg32["ms_per_step"]
     kb = kernel_bytes(n, s, 32)
     tim = r32["timing"]
     dom = max((k for k in kb), key=lambda k: tim.get(k, (0, 0.0))[1])
@@ -257,13 +361,14 @@ def main():
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
     chosen = r32["schedule"]["chosen"] if r32["schedule"] else 0
     traffic = measured_traffic(dom, n, s, 32, chosen)
-    per_kernel = {k: {"launches": tim[k][0], "avg_ms": tim[k][1] / max(tim[k][0], 1),
-                      "alg_GB_per_launch": kb[k] / 1e9 if k in kb else None,
-                      "alg_GBs": (kb[k] / (tim[k][1] / max(tim[k][0], 1) * 1e-3) / 1e9) if k in kb and tim[k][0] else None}
-                  for k in tim if tim[k][0]}
+    step_traffic = None
+    if all(measured_traffic(k, n, s, 32, chosen) is not None
+           for k in ("y_inverse", "x_pass", "y_forward", "z_forward_update_inverse")):
+        step_traffic = 4.0 * sum(measured_traffic(k, n, s, 32, chosen)
+                                 for k in ("y_inverse", "x_pass", "y_forward", "z_forward_update_inverse"))
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": leg32["value"],
         "unit": "N^3*RK4-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -276,32 +381,52 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{n}^3 pseudo-spectral DNS RK4 step, FP32 (FP64 beside), S={s} "
                                f"(Sc {SCHMIDT[:s]}, G=(0,1,0)), nu={NU}, P={POWER} on 0<|k|<={KF:g}, "
-                               f"Rogallo IC k_p={KP:g}, CFL 0.5", "n": n, "scalars": s, "batch": 1},
+                               f"Rogallo IC k_p={KP:g}, CFL 0.5; timed as graph replays", "n": n, "scalars": s,
+                   "batch": 1},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-scaled)",
                      "traffic_GBs": traffic / (avg_ms * 1e-3) / 1e9 if traffic else None,
-                     "alg_bytes_per_launch": kb[dom]},
+                     "alg_bytes_per_launch": kb[dom],
+                     "timing": "kernel durations from an eager pass of the same K steps with per-kernel events"},
         "step_roofline": {"alg_GB_per_step": step_bytes(n, s, 32) / 1e9,
                           "achieved_GBs": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9,
-                          "frac": step_bytes(n, s, 32) / (ms32 * 1e-3) / 1e9 / PEAK_HBM_GBS},
-        "kernels_fp32": per_kernel,
+                          "frac": leg32["frac_design_bytes"],
+                          "survey_model_GB_per_step": survey_step_bytes(n, s, 32) / 1e9,
+                          "frac_survey_model": leg32["frac_survey_model"],
+                          "counter_GB_per_step": step_traffic / 1e9 if step_traffic else None,
+                          "frac_counter_bytes": (step_traffic / (ms32 * 1e-3) / 1e9 / PEAK_HBM_GBS)
+                          if step_traffic else None},
+        "graph_step_median_ms": leg32["graph_step_median_ms"],
+        "graph_step_min_ms": leg32["graph_step_min_ms"],
+        "kernels_fp32": leg32["kernels"],
         "schedule_fp32": r32["schedule"],
         "copy_reference": copy,
         "finite": r32["finite"],
     }
     if r64 is not None:
-        ms64 = r64["ms_total"] / args.steps
-        out["fp64"] = {"value": n3 / (ms64 * 1e-3), "ms_per_step": ms64,
-                       "step_frac": step_bytes(n, s, 64) / (ms64 * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                       "finite": r64["finite"]}
-        out["fp32_over_fp64"] = ms64 / ms32
+        leg64 = leg_summary(r64, n, s, 64, args.steps)
+        out["fp64"] = {k: leg64[k] for k in ("value", "ms_per_step", "graph_step_median_ms", "frac_survey_model",
+                                              "frac_design_bytes", "finite")}
+        out["fp64"]["step_frac"] = leg64["frac_design_bytes"]
+        out["fp32_over_fp64"] = leg64["ms_per_step"] / ms32
         out["schedule_fp64"] = r64["schedule"]
-        kb64 = kernel_bytes(n, s, 64)
-        t64 = r64["timing"]
-        out["kernels_fp64"] = {k: {"launches": t64[k][0], "avg_ms": t64[k][1] / max(t64[k][0], 1),
-                                   "alg_GBs": (kb64[k] / (t64[k][1] / t64[k][0] * 1e-3) / 1e9)
-                                   if k in kb64 and t64[k][0] else None} for k in t64 if t64[k][0]}
+        out["kernels_fp64"] = leg64["kernels"]
+    if not args.no_1024:
+        # the 1024^3 configuration: one scalar (Sc 1, G = (0, 1, 0)), nu = 3e-4, CFL 0.5
+        big = {}
+        for prec in (32, 64):
+            r = run_gpu(1024, 1, prec, args.steps_1024, 2, seed=4, tune_reps=2 if tr else 0,
+                        schedule=args.schedule, nu=3e-4, schmidt=(1.0,))
+            leg = leg_summary(r, 1024, 1, prec, args.steps_1024)
+            big[f"fp{prec}"] = {k: leg[k] for k in ("value", "ms_per_step", "graph_step_median_ms",
+                                                    "frac_survey_model", "frac_design_bytes", "finite", "schedule",
+                                                    "kernels")}
+            print(f"[bench] 1024^3 fp{prec} done: {leg['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+        big["fp32_over_fp64"] = big["fp64"]["ms_per_step"] / big["fp32"]["ms_per_step"]
+        big["steps"] = args.steps_1024
+        big["workload"] = "1024^3 S=1 (Sc 1, G=(0,1,0)), nu=3e-4, P=0.1 on 0<|k|<=2, Rogallo IC k_p=8, CFL 0.5"
+        out["n1024"] = big
     if args.serve_requests > 0:
         out["serve"] = serve_mix(args.serve_requests, args.serve_load)
         print(f"[bench] serve done: p50 {out['serve']['p50_s']:.3f} s p99 {out['serve']['p99_s']:.3f} s",

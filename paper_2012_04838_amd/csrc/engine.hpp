@@ -99,8 +99,13 @@ struct ColCfg {
   static constexpr int EC = N < EC1 ? N : EC1;
   static constexpr int TC = N / EC;
   static constexpr int THREADS = W * TC;
+  // 64-byte row segments: the two halves of a 128-byte row go to consecutive blocks of
+  // one XCD (col_block), so that XCD's L2 serves the second half
+  static constexpr bool PAIR = W * (int)sizeof(cpx<T>) == 64;
   static_assert(THREADS <= 1024, "column block too large");
   static_assert((W * N + N) * sizeof(cpx<T>) <= 160 * 1024, "column pass LDS exceeds 160 KB");
+  // blocks along x of a grid covering ntile kx tiles
+  static constexpr int grid_x(int ntile) { return PAIR ? (ntile + 1) / 2 * 2 : ntile; }
 };
 
 // LDS of a column pass: the exchange buffer, doubled (one barrier per exchange)
@@ -191,6 +196,44 @@ struct Cfg {
   static constexpr int LP = LinePad<N>::value;
 };
 
+// Block placement of a column pass over (kx tile, row, slot).  Blocks are handed to the 8
+// XCDs round-robin in launch order (block L to XCD L mod 8), and each XCD has its own L2.
+// With PAIR (64-byte tiles) the launch order is permuted so that tiles 2q and 2q + 1 of a
+// row, the two halves of its 128-byte segments, are consecutive blocks on one XCD (launch
+// blocks 16 r' + x and 16 r' + 8 + x); the grid is 2 ceil(ntile / 2) blocks wide and a
+// block past the last tile has ok = false.  The tail of fewer than 16 blocks keeps the
+// launch order.
+struct ColBlock {
+  int tile, row, slot;
+  bool ok;
+};
+template <bool PAIR>
+__device__ __forceinline__ ColBlock col_block(int ntile, int nrow) {
+  ColBlock b;
+  if constexpr (PAIR) {
+    const long long L = blockIdx.x + (long long)gridDim.x * (blockIdx.y + (long long)gridDim.y * blockIdx.z);
+    const long long G = (long long)gridDim.x * gridDim.y * gridDim.z;
+    long long lam = L;
+    if (L < G / 16 * 16) {
+      const long long x = L % 8, r = L / 8;
+      lam = 16 * (r / 2) + 2 * x + (r % 2);
+    }
+    const int npairs = (ntile + 1) / 2;
+    const long long p = lam / 2;
+    b.tile = 2 * (int)(p % npairs) + (int)(lam % 2);
+    const long long rr = p / npairs;
+    b.row = (int)(rr % nrow);
+    b.slot = (int)(rr / nrow);
+    b.ok = b.tile < ntile;
+  } else {
+    b.tile = blockIdx.x;
+    b.row = blockIdx.y;
+    b.slot = blockIdx.z;
+    b.ok = true;
+  }
+  return b;
+}
+
 // position n of an N-point line -> compact index (or -1 if the wavenumber is truncated)
 __device__ __forceinline__ int compact_of(int n, int N, int K, int M) {
   return n <= K ? n : (n >= N - K ? n - N + M : -1);
@@ -221,14 +264,16 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   using L = ColLds<N, T, W>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
-  const int slot = blockIdx.z;
+  const ColBlock cb = col_block<C::Col::PAIR>((g.KX + W - 1) / W, M);
+  if (!cb.ok) return;
+  const int slot = cb.slot;
   if (!slots[slot].active) return;
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
-  const int kx = blockIdx.x * W + c;
-  const int kyc = blockIdx.y;
+  const int kx = cb.tile * W + c;
+  const int kyc = cb.row;
   const bool valid = kx < g.KX;
   const typename L::View lds{smem + c};
   const T scale = T(1) / (T(N) * T(N) * T(N));
@@ -309,14 +354,16 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
   using L = ColLds<N, T, W>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
-  const int slot = blockIdx.z;
+  const ColBlock cb = col_block<C::Col::PAIR>((g.KX + W - 1) / W, N);
+  if (!cb.ok) return;
+  const int slot = cb.slot;
   if (!slots[slot].active) return;
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
-  const int kx = blockIdx.x * W + c;
-  const int z = blockIdx.y;
+  const int kx = cb.tile * W + c;
+  const int z = cb.row;
   const bool valid = kx < g.KX;
   const typename L::View lds{smem + c};
   // A rows (z, ky_c) and B rows (z, y) are both PX entries apart at fixed z
@@ -779,14 +826,16 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   using L = ColLds<N, T, W, PSDNS_YF_DB>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
-  const int slot = blockIdx.z;
+  const ColBlock cb = col_block<C::Col::PAIR>((g.KX + W - 1) / W, N);
+  if (!cb.ok) return;
+  const int slot = cb.slot;
   if (!slots[slot].active) return;
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
-  const int kx = blockIdx.x * W + c;
-  const int z = blockIdx.y;
+  const int kx = cb.tile * W + c;
+  const int z = cb.row;
   const bool valid = kx < g.KX;
   const typename L::View lds{smem + c};
   const uint32_t rsb = (uint32_t)g.PX * CS;
@@ -843,32 +892,33 @@ struct StageArgs {
 // mode sits at byte offsets (vo, so) inside the field that starts foff entries
 // into each state array.  F is the right-hand side without the linear term
 // -lk2 y (lk2 = D |k|^2).  Integrating factor (expl = false): the stage formulas of
-// Lawson's RK4 with exp(-lk2 h/2) and exp(-lk2 h) (FP64, then cast).  Explicit: the
+// Lawson's RK4 with eh = exp(-lk2 h/2) and e1 = eh^2 (FP64, then cast).  Explicit: the
 // same formulas with both factors 1 and F completed by -lk2 times the stage input,
-// which is classical RK4 on the full right-hand side.
-template <typename T>
+// which is classical RK4 on the full right-hand side.  STG is the stage when known at
+// compile time (0..3, or -1 for dy/dt), else -2 and the stage comes from the arguments.
+template <int STG, typename T>
 __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so, cpx<T> F,
-                                            double lk2, double h, bool write_ys, bool expl) {
-  if (a.stage < 0) {
+                                            double lk2, double ehd, double h, bool write_ys, bool expl) {
+  const int stage = STG >= -1 ? STG : a.stage;
+  if (stage < 0) {
     const cpx<T> y = bload(make_buf<T>(a.sin + foff), vo, so);
     bstore(make_buf<T>(a.rhs + foff), vo, so, F - T(lk2) * y);
     return czero<T>();
   }
   const Buf<T> yn = make_buf<T>(a.yn + foff), acc = make_buf<T>(a.acc + foff);
-  const cpx<T> y = a.stage < 3 ? bload(yn, vo, so) : czero<T>();
+  const cpx<T> y = stage < 3 ? bload(yn, vo, so) : czero<T>();
   T eh, e1;
   if (expl) {
-    const cpx<T> yin = a.stage == 0 ? y : bload(make_buf<T>(a.sin + foff), vo, so);
+    const cpx<T> yin = stage == 0 ? y : bload(make_buf<T>(a.sin + foff), vo, so);
     F = F - T(lk2) * yin;
     eh = e1 = T(1);
   } else {
-    const double ehd = exp(-0.5 * lk2 * h);
     eh = T(ehd);
     e1 = T(ehd * ehd);
   }
   const T th = T(h);
   cpx<T> nxt;
-  switch (a.stage) {
+  switch (stage) {
     case 0: {
       bstore(acc, vo, so, e1 * (y + (th / T(6)) * F));
       nxt = eh * (y + (th / T(2)) * F);
@@ -905,7 +955,15 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long fof
 // Addressing: A rows (z, ky_c) and state rows (kz_c, ky_c) are both M PX entries
 // apart along z, so one per-thread byte offset (row j of the column) serves every
 // field of both; element m adds a uniform multiple of the row stride.
-template <int N, typename T, bool FUSE, int V>
+//
+// Integrating factor: exp(-D h |k|^2 / 2) = exp(-D h (kx^2 + ky^2) / 2) exp(-D h kz^2 / 2);
+// the block tabulates the kz part in LDS for each diffusivity (velocity, each scalar)
+// and each thread evaluates the first part once for its column, so that a mode costs one
+// product instead of an exponential.
+//
+// STG: the stage (0..3) when the launch fixes it, so that the update compiles to straight
+// code; -2 reads it from the arguments (the rarer unfused launches and dy/dt).
+template <int N, typename T, bool FUSE, int V, int STG>
 __global__ void PSDNS_FUSED_BOUNDS(Cfg<N, T, V>::Fused::THREADS)
 k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
                    const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
@@ -917,15 +975,29 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   using L = ColLds<N, T, W, PSDNS_FUSED_DB>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
-  const int slot = blockIdx.z;
+  __shared__ double ez[(1 + kMaxScalars) * (K + 1)];  // exp(-D h kz^2 / 2), |kz| <= K
+  const ColBlock cb = col_block<C::PAIR>((g.KX + W - 1) / W, g.M);
+  if (!cb.ok) return;
+  const int slot = cb.slot;
   const SlotDev& sp = slots[slot];
   if (!sp.active) return;
-  stage_twiddles<N>(stw, tw_g);
+  const double h = dyn[slot].dt;
+  const bool expl = sp.integrator == PSDNS_INTEGRATOR_EXPLICIT;
+  const int stage = STG >= -1 ? STG : sa.stage;
+  const bool factors = !expl && stage >= 0;
+  if (factors) {
+    // diffusivity of class cls: velocity (sp.diff[0]) or scalar cls - 1 (sp.diff[2 + cls])
+    for (int i = threadIdx.x; i < (1 + g.S) * (K + 1); i += blockDim.x) {
+      const int cls = i / (K + 1), kz = i % (K + 1);
+      ez[i] = exp(-0.5 * sp.diff[cls == 0 ? 0 : 2 + cls] * h * (double(kz) * kz));
+    }
+  }
+  stage_twiddles<N>(stw, tw_g);  // its barrier also covers ez
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
-  const int kx = blockIdx.x * W + c;
-  const int kyc = blockIdx.y;
+  const int kx = cb.tile * W + c;
+  const int kyc = cb.row;
   const bool valid = kx < g.KX;
   const typename L::View lds{smem + c};
   const uint32_t rsb = (uint32_t)M * g.PX * CS;                       // z row stride (bytes)
@@ -933,12 +1005,18 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   const cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
   const long long sslot = (long long)slot * g.F * g.st_field;
   const int ky = wave_of_compact(kyc, g.K, g.M);
-  const double h = dyn[slot].dt;
   const double A = dyn[slot].A;
-  const bool expl = sp.integrator == PSDNS_INTEGRATOR_EXPLICIT;
   const T scale = T(1) / (T(N) * T(N) * T(N));
 
   const int kxy2 = kx * kx + ky * ky;
+  // integrating factor of element m from its column's part exy (class cls)
+  auto exy_of = [&](int cls) {
+    return factors ? exp(-0.5 * sp.diff[cls == 0 ? 0 : 2 + cls] * h * double(kxy2)) : 1.0;
+  };
+  auto efac = [&](int cls, double exy, int m) {
+    const int kz = wave_of(j + TT * m, N);
+    return factors ? exy * ez[cls * (K + 1) + (kz < 0 ? -kz : kz)] : 1.0;
+  };
   auto k2m = [&](int m) {
     const int kz = wave_of(j + TT * m, N);
     return double(kxy2 + kz * kz);
@@ -981,6 +1059,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     fetch(3 + s, a);
     fft<N, E, false>(a, lds, j, tw);
     const double dif = sp.diff[3 + s];
+    const double exy = exy_of(1 + s);
     const long long foff = sslot + (long long)(3 + s) * g.st_field;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -989,7 +1068,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       if (state_at(m, vo, so)) {
         const double k2m_ = k2m(m);
         const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
-        nxt = rk_update(sa, foff, vo, so, F, dif * k2m_, h, !FUSE || expl, expl);
+        nxt = rk_update<STG>(sa, foff, vo, so, F, dif * k2m_, efac(1 + s, exy, m), h, !FUSE || expl, expl);
       }
       a[m] = nxt;
     }
@@ -1034,6 +1113,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       }
     }
     const double nu = sp.nu;
+    const double exy = exy_of(0);
     const long long f1 = sslot, f2 = sslot + g.st_field, f3 = sslot + 2 * g.st_field;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -1048,7 +1128,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
         if (k2m_ == 0.0) {
           F1 = F2 = F3 = czero<T>();
         } else {
-          const T ik2 = T(1.0 / k2m_);
+          const T ik2 = T(1) / T(k2m_);  // k2m_ is an integer below 2^24: exact in T
           const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
           F1 = c1[m] - (kxt * ik2) * kdc;
           F2 = c2[m] - (kyt * ik2) * kdc;
@@ -1063,9 +1143,10 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
         const double lk2 = nu * k2m_;
         // the next stage reads y_stage on the band (forcing) and, explicit, everywhere
         const bool wys = !FUSE || band || expl;
-        n1 = rk_update(sa, f1, vo, so, F1, lk2, h, wys, expl);
-        n2 = rk_update(sa, f2, vo, so, F2, lk2, h, wys, expl);
-        n3 = rk_update(sa, f3, vo, so, F3, lk2, h, wys, expl);
+        const double ef = efac(0, exy, m);
+        n1 = rk_update<STG>(sa, f1, vo, so, F1, lk2, ef, h, wys, expl);
+        n2 = rk_update<STG>(sa, f2, vo, so, F2, lk2, ef, h, wys, expl);
+        n3 = rk_update<STG>(sa, f3, vo, so, F3, lk2, ef, h, wys, expl);
       }
       c1[m] = n1;
       c2[m] = n2;
@@ -1969,7 +2050,7 @@ struct Step {
     const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
     cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
     cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
-    const int ntile = (g.KX + C::W - 1) / C::W;
+    const int ntile = C::Col::grid_x((g.KX + C::W - 1) / C::W);
     if (!(flags & kStagePrologue)) {
       TimedLaunch tl(x.timer, KID_FORCE, s);
       k_forcing_amplitude<T><<<g.batch, 256, 0, s>>>(sin, x.slots, x.dyn, g);
@@ -2005,15 +2086,20 @@ struct Step {
     sa.rhs = static_cast<cpx<T>*>(rhs_out);
     sa.fband = x.fband;
     sa.stage = stage;
-    const int ntile_u = (g.KX + C::Fused::W - 1) / C::Fused::W;
+    const dim3 grid_u(C::Fused::grid_x((g.KX + C::Fused::W - 1) / C::Fused::W), g.M, g.batch);
+    constexpr int TU = C::Fused::THREADS;
     if (flags & kStageFuse) {
+      // every stage of a multi-step call: the stage fixed at compile time
       TimedLaunch tl(x.timer, KID_ZFWDI, s);
-      k_z_forward_update<N, T, true, V>
-          <<<dim3(ntile_u, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+      switch (stage) {
+        case 0: k_z_forward_update<N, T, true, V, 0><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g); break;
+        case 1: k_z_forward_update<N, T, true, V, 1><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g); break;
+        case 2: k_z_forward_update<N, T, true, V, 2><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g); break;
+        default: k_z_forward_update<N, T, true, V, 3><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g); break;
+      }
     } else {
       TimedLaunch tl(x.timer, KID_ZFWD, s);
-      k_z_forward_update<N, T, false, V>
-          <<<dim3(ntile_u, g.M, g.batch), C::Fused::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
+      k_z_forward_update<N, T, false, V, -2><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     }
   }
 };
@@ -2078,13 +2164,14 @@ struct Engine {
     gp.S = 0;
     gp.nblk_x = N * N / C0::LX;
     const int ntile = (gp.KX + C0::W - 1) / C0::W;
+    const int gx = C0::Col::grid_x(ntile);  // the passes shared with the step place blocks by col_block
     TimedLaunch tl(x.timer, KID_AUX, s);
-    k_z_inverse<N, T, 0><<<dim3(ntile, gp.M, gp.batch), C0::COL_THREADS, 0, s>>>(st, A, tw, x.slots, gp);
-    k_y_inverse<N, T, 0><<<dim3(ntile, N, gp.batch), C0::COL_THREADS, 0, s>>>(A, B, tw, x.slots, gp);
+    k_z_inverse<N, T, 0><<<dim3(gx, gp.M, gp.batch), C0::COL_THREADS, 0, s>>>(st, A, tw, x.slots, gp);
+    k_y_inverse<N, T, 0><<<dim3(gx, N, gp.batch), C0::COL_THREADS, 0, s>>>(A, B, tw, x.slots, gp);
     k_x_pass<N, T, 0><<<dim3(gp.nblk_x, gp.batch), C0::X_THREADS, 0, s>>>(B, tw, x.slots, x.dyn, gp, kXPressure);
     Geom gy = gp;
     gy.F = 4;  // c1, c2, c3, |u|^2/2
-    k_y_forward<N, T, 0><<<dim3(ntile, N, gp.batch), C0::COL_THREADS, 0, s>>>(B, A, tw, x.slots, gy);
+    k_y_forward<N, T, 0><<<dim3(gx, N, gp.batch), C0::COL_THREADS, 0, s>>>(B, A, tw, x.slots, gy);
     k_z_forward_pressure<N, T><<<dim3(ntile, gp.M, gp.batch), C0::COL_THREADS, 0, s>>>(A, P, tw, x.slots, gp);
     const long long per = (long long)N * N * (N / 2 + 1);
     k_fill_zero<T><<<(unsigned)((per * gp.batch + 255) / 256), 256, 0, s>>>(static_cast<cpx<T>*>(canon),
