@@ -11,7 +11,8 @@
  *   dphi_hat/dt = -(u . grad phi)^   - g . u_hat       - (nu/Sc) |k|^2 phi_hat
  *
  * with P(k) = I - k k^T/|k|^2 the projection of Eq. (7), products formed in
- * physical space, 2/3-rule truncation |k_i| <= K = (N-1)/3, A = P/(2 E_f)
+ * physical space, 2/3-rule truncation |k_i| <= K = (N-1)/3 (or the paper's phase shift
+ * with spherical truncation, PSDNS_DEALIAS_PHASE_SPHERE), A = P/(2 E_f)
  * (constant power P injected into the band 0 < |k| <= k_force), and the
  * classical RK4 of Sec. 2.2 applied with the viscous/diffusive integrating
  * factor.
@@ -72,12 +73,28 @@ typedef enum {
   PSDNS_E_UNSUPPORTED = -4  /* valid request this build does not implement */
 } psdns_status;
 
-/* Plan geometry, fixed for the life of a plan. */
+/* Dealiasing of the quadratic products (Sec. 2.3).
+ * TWO_THIRDS:   the 2/3 rule: every product truncated to the cube |k_i| <= K = (N-1)/3.
+ * PHASE_SPHERE: the paper's scheme: every product is the mean of its values on the grid and
+ *               on the grid shifted by half a cell along each axis (inputs multiplied by
+ *               exp(i pi (kx+ky+kz)/N), products by its conjugate), truncated to the sphere
+ *               9 |k|^2 < 2 N^2 (|k| < sqrt(2) N / 3, Sec. 3.1); K is then the largest integer
+ *               with 9 K^2 < 2 N^2 and the state holds the sphere inside the cube |k_i| <= K.
+ *               Each right-hand side costs two evaluations of the products. */
+#define PSDNS_DEALIAS_TWO_THIRDS 0
+#define PSDNS_DEALIAS_PHASE_SPHERE 1
+
+/* Plan geometry, fixed for the life of a plan.  Grids that are powers of two with the 2/3
+ * rule run the tuned step kernels; any other even n whose prime factors are 2, 3, 5, 7, 11
+ * and 13 (the paper's n = 520 = 2^3 5 13, Sec. 3.1 and Table 2), and every plan with
+ * PHASE_SPHERE, run general kernels built on mixed-radix transforms (one schedule; no
+ * psdns_pressure, which returns PSDNS_E_UNSUPPORTED there). */
 typedef struct {
-  int32_t n;         /* points per axis: a power of two, 8 <= n <= 1024 */
+  int32_t n;         /* points per axis: even, 8 <= n <= 1024, prime factors in {2, 3, 5, 7, 11, 13} */
   int32_t n_scalars; /* S, 0 <= S <= PSDNS_MAX_SCALARS */
   int32_t precision; /* 32 or 64: storage, transforms and products; reductions are FP64 */
   int32_t batch;     /* number of independent realizations (slots), >= 1 */
+  int32_t dealias;   /* PSDNS_DEALIAS_TWO_THIRDS (0) or PSDNS_DEALIAS_PHASE_SPHERE */
 } psdns_plan_params;
 
 /* Forcing of the band 0 < |k| <= k_force (Eq. (1) term A U, Sec. 2.3).
@@ -165,6 +182,8 @@ typedef struct {
   int32_t n_schedules;        /* step schedules compiled for this size (psdns_set_schedule) */
   int32_t schedule;           /* schedule in use */
   int64_t plan_bytes;         /* device bytes of the plan's own tables (psdns_plan_device_bytes) */
+  int32_t dealias;            /* PSDNS_DEALIAS_* of the plan */
+  int32_t general;            /* 1 when the plan runs the general (mixed-radix) kernels */
 } psdns_plan_info;
 
 /* Bytes of the compact spectral state y for all slots (caller allocates). 0 on invalid params. */
@@ -341,15 +360,28 @@ psdns_status psdns_pressure(psdns_plan* plan, const void* state, void* ws, void*
 psdns_status psdns_spectra(psdns_plan* plan, const void* state, void* ws, double* out, int32_t flags,
                            void* hip_stream);
 
-/* Per-kernel timing with HIP events on the launch stream (off by default). */
+/* Per-kernel timing with HIP events on the launch stream (off by default).  Entries are the
+ * step kernels by name, "aux" (initial field, conversions, spectra, pressure) and "step":
+ * one whole RK4 step of psdns_step, around each graph replay or around the launches of an
+ * eager step (its kernels are timed inside it).  median_ms and min_ms are over the
+ * launches since the previous psdns_get_timing. */
 typedef struct {
   char name[32];
   int32_t launches;
   double total_ms;
+  double median_ms;
+  double min_ms;
 } psdns_kernel_timing;
 psdns_status psdns_set_timing(psdns_plan* plan, int32_t enable);
 /* Synchronises the recorded events, accumulates and clears them. Fills up to max entries. */
 psdns_status psdns_get_timing(psdns_plan* plan, psdns_kernel_timing* out, int32_t max, int32_t* count);
+
+/* Streaming device-to-device copy of `bytes` with `blocks` blocks of 256 threads, each
+ * thread keeping four 16-byte loads in flight (grid-stride).  Not part of the method: the
+ * achievable HBM bandwidth that the transform passes are compared with.  `bytes` and both
+ * pointers must be multiples of 16 and the buffers must not overlap (else PSDNS_E_INVAL).
+ * Asynchronous on the stream. */
+psdns_status psdns_stream_copy(void* dst, const void* src, size_t bytes, int32_t blocks, void* hip_stream);
 
 /* Thread-local description of the last error (never NULL). */
 const char* psdns_last_error(void);

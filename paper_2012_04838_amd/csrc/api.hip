@@ -1,6 +1,7 @@
 // C ABI of the pseudo-spectral DNS library (declarations and contracts in include/psdns.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,6 +20,7 @@ Ops ops_n128(int);
 Ops ops_n256(int);
 Ops ops_n512(int);
 Ops ops_n1024(int);
+Ops ops_general(int);
 }  // namespace psdns
 
 using namespace psdns;
@@ -44,14 +46,34 @@ psdns_status hip_fail(hipError_t e, const char* what) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+// largest retained |k_i|: (N-1)/3 for the 2/3 rule, else the largest k with 9 k^2 < 2 N^2
+int kmax_of(int n, int dealias) {
+  if (dealias != PSDNS_DEALIAS_PHASE_SPHERE) return (n - 1) / 3;
+  int k = 0;
+  while (9LL * (k + 1) * (k + 1) < 2LL * n * n) ++k;
+  return k;
+}
+
+// whether the plan runs the general kernels (mixed radix or phase-shift dealiasing)
+bool general_plan(const psdns_plan_params* p) { return !is_pow2(p->n) || p->dealias == PSDNS_DEALIAS_PHASE_SPHERE; }
+
 bool valid_params(const psdns_plan_params* p, std::string* why) {
   if (!p) {
     *why = "params is NULL";
     return false;
   }
   const int n = p->n;
-  if (n < 8 || n > 1024 || (n & (n - 1)) != 0) {
-    *why = "n must be a power of two in [8, 1024], got " + std::to_string(n);
+  int rest = n;
+  for (int f : {2, 3, 5, 7, 11, 13})
+    while (rest % f == 0) rest /= f;
+  if (n < 8 || n > 1024 || n % 2 != 0 || rest != 1) {
+    *why = "n must be even, in [8, 1024], with prime factors among 2, 3, 5, 7, 11, 13; got " + std::to_string(n);
+    return false;
+  }
+  if (p->dealias != PSDNS_DEALIAS_TWO_THIRDS && p->dealias != PSDNS_DEALIAS_PHASE_SPHERE) {
+    *why = "dealias must be PSDNS_DEALIAS_TWO_THIRDS or PSDNS_DEALIAS_PHASE_SPHERE, got " + std::to_string(p->dealias);
     return false;
   }
   if (p->n_scalars < 0 || p->n_scalars > PSDNS_MAX_SCALARS) {
@@ -65,7 +87,7 @@ bool valid_params(const psdns_plan_params* p, std::string* why) {
   {
     // the column passes address one field (one z plane for the y-pass arrays) with
     // 32-bit byte offsets from a per-field buffer base
-    const long long k = (n - 1) / 3, m = 2 * k + 1, px = (k + 1 + 15) / 16 * 16;
+    const long long k = kmax_of(n, p->dealias), m = 2 * k + 1, px = (k + 1 + 15) / 16 * 16;
     const double field_bytes = (double)n * m * px * (p->precision == 32 ? 8 : 16);
     if (field_bytes >= 4294967296.0) {
       *why = "one transposed field would exceed 4 GiB";
@@ -79,7 +101,9 @@ bool valid_params(const psdns_plan_params* p, std::string* why) {
   return true;
 }
 
-Ops ops_for(int n, int prec) {
+Ops ops_for(const psdns_plan_params* p) {
+  const int n = p->n, prec = p->precision;
+  if (general_plan(p)) return ops_general(prec);
   switch (n) {
     case 8: return ops_n8(prec);
     case 16: return ops_n16(prec);
@@ -107,7 +131,8 @@ int spectra_record(int ns, int S) { return ns * (1 + S) + 8 + 4 * S + 16 + 3 * S
 struct Layout {
   Geom g;
   size_t csize;  // bytes per complex
-  size_t off_dyn, off_fband, off_part, off_stat, off_ystage, off_acc, off_abuf, off_bbuf, ws_bytes, st_bytes;
+  size_t off_dyn, off_fband, off_part, off_stat, off_ystage, off_acc, off_abuf, off_bbuf, off_akeep, ws_bytes,
+      st_bytes;
   long long part_len, stat_len;
   int nbm, rec;
 };
@@ -116,7 +141,8 @@ Layout make_layout(const psdns_plan_params* p) {
   Layout L{};
   Geom& g = L.g;
   g.N = p->n;
-  g.K = (p->n - 1) / 3;
+  g.K = kmax_of(p->n, p->dealias);
+  g.sphere = p->dealias == PSDNS_DEALIAS_PHASE_SPHERE;
   g.M = 2 * g.K + 1;
   g.KX = g.K + 1;
   g.PX = (g.KX + 15) / 16 * 16;
@@ -157,6 +183,8 @@ Layout make_layout(const psdns_plan_params* p) {
   off = align_up(off + B * g.FA * (size_t)g.a_field * L.csize, 256);
   L.off_bbuf = off;
   off = align_up(off + B * g.FB * (size_t)g.b_field * L.csize, 256);
+  L.off_akeep = off;
+  if (g.sphere) off = align_up(off + B * g.F * (size_t)g.a_field * L.csize, 256);
   L.ws_bytes = off;
   L.st_bytes = B * g.F * (size_t)g.st_field * L.csize;
   return L;
@@ -164,12 +192,16 @@ Layout make_layout(const psdns_plan_params* p) {
 
 const char* kKernelNames[KID_COUNT] = {"forcing_amplitude", "z_inverse",        "y_inverse",
                                        "x_pass",            "step_dt",          "y_forward",
-                                       "z_forward_update",  "aux",              "z_forward_update_inverse"};
+                                       "z_forward_update",  "aux",              "z_forward_update_inverse",
+                                       "step"};
 
+// Event pairs around launches; records may nest (a step around its kernels), so end()
+// closes the innermost open record of its kind.
 struct EventTimer : Timer {
   struct Rec {
     int kid;
     hipEvent_t a, b;
+    bool closed;
   };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
@@ -186,12 +218,17 @@ struct EventTimer : Timer {
     return e;
   }
   void begin(int kid, hipStream_t s) override {
-    Rec r{kid, get(), get()};
+    Rec r{kid, get(), get(), false};
     if (r.a) hipEventRecord(r.a, s);
     recs.push_back(r);
   }
   void end(int kid, hipStream_t s) override {
-    if (!recs.empty() && recs.back().kid == kid && recs.back().b) hipEventRecord(recs.back().b, s);
+    for (auto it = recs.rbegin(); it != recs.rend(); ++it)
+      if (it->kid == kid && !it->closed) {
+        if (it->b) hipEventRecord(it->b, s);
+        it->closed = true;
+        return;
+      }
   }
   ~EventTimer() override {
     for (auto& r : recs) {
@@ -215,6 +252,7 @@ struct psdns_plan {
   EventTimer* timer = nullptr;
   double acc_ms[KID_COUNT] = {0};
   int acc_n[KID_COUNT] = {0};
+  std::vector<float> samples[KID_COUNT];  // per-launch milliseconds since the last psdns_get_timing
   // captured graph of one RK4 step (psdns_set_graph)
   bool use_graph = false;
   hipGraphExec_t graph_exec = nullptr;
@@ -244,6 +282,7 @@ Ctx make_ctx(psdns_plan* plan, void* ws) {
   c.acc = w + plan->L.off_acc;
   c.abuf = w + plan->L.off_abuf;
   c.bbuf = w + plan->L.off_bbuf;
+  c.akeep = plan->L.g.sphere ? w + plan->L.off_akeep : nullptr;
   c.timer = plan->timer;
   return c;
 }
@@ -282,7 +321,7 @@ psdns_status clear_slots(psdns_plan* plan, void* ws, int first, int count, hipSt
 // device bytes a plan allocates for itself (twiddle and slot tables)
 size_t plan_table_bytes(const psdns_plan_params* p) {
   const size_t cs = p->precision == 32 ? 8 : 16;
-  return align_up((size_t)p->n * cs, 256) + align_up(sizeof(SlotDev) * (size_t)p->batch, 256);
+  return align_up((size_t)root_table_entries(p->n) * cs, 256) + align_up(sizeof(SlotDev) * (size_t)p->batch, 256);
 }
 
 psdns_status check_plan(const psdns_plan* plan) {
@@ -346,16 +385,38 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
     // the captured step expects the z inverse of y_n: run it once, then replay
     plan->ops.sched[plan->sched].rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
     HIP_TRY(hipGetLastError());
-    for (int n = 0; n < nsteps; ++n) HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
+    for (int n = 0; n < nsteps; ++n) {
+      if (timer) timer->begin(KID_STEP, s);
+      HIP_TRY(hipGraphLaunch(plan->graph_exec, s));
+      if (timer) timer->end(KID_STEP, s);
+    }
     return PSDNS_OK;
   }
   for (int n = 0; n < nsteps; ++n) {
+    if (timer) timer->begin(KID_STEP, s);
     one_step(c, n == 0, n == nsteps - 1);
+    if (timer) timer->end(KID_STEP, s);
     HIP_TRY(hipGetLastError());
   }
   return PSDNS_OK;
 }
 
+
+// Streaming copy (psdns_stream_copy): 16-byte accesses, four loads in flight per thread,
+// grid-stride over the buffer.
+__global__ void __launch_bounds__(256)
+k_stream_copy(const uint4* __restrict__ src, uint4* __restrict__ dst, size_t n) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
 
 // Step records of every slot into a caller's device buffer (psdns_step_noalloc).
 __global__ void k_export_info(const DynDev* __restrict__ d, const SlotDev* __restrict__ slots,
@@ -431,26 +492,39 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
   psdns_plan* plan = new (std::nothrow) psdns_plan();
   if (!plan) return fail(PSDNS_E_NOMEM, "host allocation of the plan failed");
   plan->p = *p;
-  plan->ops = ops_for(p->n, p->precision);
+  plan->ops = ops_for(p);
   plan->L = make_layout(p);
   hipError_t e = hipGetDevice(&plan->device);
   if (e != hipSuccess) {
     delete plan;
     return hip_fail(e, "hipGetDevice");
   }
-  // twiddles w_N^m = exp(-2 pi i m / N), computed in double precision
+  // root table (layout in common.hpp), computed in double precision: twiddles
+  // w_N^m = exp(-2 pi i m / N), the roots of the odd radices, the half-cell shift phases
   const int n = p->n;
-  const size_t twb = (size_t)n * plan->L.csize;
-  std::vector<double> twd(2 * (size_t)n);
+  const size_t nent = (size_t)root_table_entries(n);
+  const size_t twb = nent * plan->L.csize;
+  std::vector<double> twd(2 * nent);
   for (int m = 0; m < n; ++m) {
     const double a = 2.0 * M_PI * (double)m / (double)n;
     twd[2 * m] = std::cos(a);
     twd[2 * m + 1] = -std::sin(a);
   }
+  for (int R : kOddRadices)
+    for (int m = 0; m < R; ++m) {
+      const size_t i = (size_t)n + kRootOff(R) + m;
+      twd[2 * i] = std::cos(2.0 * M_PI * m / R);
+      twd[2 * i + 1] = -std::sin(2.0 * M_PI * m / R);
+    }
+  for (int k = 0; k <= n / 2; ++k) {
+    const size_t i = (size_t)n + kShiftOff + k;
+    twd[2 * i] = std::cos(M_PI * k / n);
+    twd[2 * i + 1] = std::sin(M_PI * k / n);
+  }
   std::vector<char> host(twb);
   if (p->precision == 32) {
     float* f = reinterpret_cast<float*>(host.data());
-    for (size_t i = 0; i < 2 * (size_t)n; ++i) f[i] = (float)twd[i];
+    for (size_t i = 0; i < 2 * nent; ++i) f[i] = (float)twd[i];
   } else {
     std::memcpy(host.data(), twd.data(), twb);
   }
@@ -511,6 +585,8 @@ psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
   out->state_bytes = (int64_t)plan->L.st_bytes;
   out->workspace_bytes = (int64_t)plan->L.ws_bytes;
   out->plan_bytes = (int64_t)plan_table_bytes(&plan->p);
+  out->dealias = plan->p.dealias;
+  out->general = general_plan(&plan->p) ? 1 : 0;
   out->elems_col = plan->ops.sched[plan->sched].ec;
   out->elems_x = plan->ops.sched[plan->sched].ex;
   out->n_schedules = plan->ops.nsched;
@@ -764,6 +840,8 @@ psdns_status psdns_pressure(psdns_plan* plan, const void* state, void* ws, void*
   if (!state || !ws || !canonical_out) return fail(PSDNS_E_INVAL, "state, ws and canonical_out must be device pointers");
   if (state == canonical_out) return fail(PSDNS_E_INVAL, "canonical_out must not alias state");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  if (!plan->ops.pressure)
+    return fail(PSDNS_E_UNSUPPORTED, "psdns_pressure is not available for plans with the general kernels");
   Ctx c = make_ctx(plan, ws);
   std::vector<int> active(plan->p.batch);
   for (int i = 0; i < plan->p.batch; ++i) active[i] = plan->slots_host[i].active;
@@ -855,14 +933,16 @@ psdns_status psdns_get_timing(psdns_plan* plan, psdns_kernel_timing* out, int32_
   if (t) {
     if (t->err != hipSuccess) return hip_fail(t->err, "hipEventCreate");
     for (auto& r : t->recs) {
-      if (!r.a || !r.b) continue;
-      HIP_TRY(hipEventSynchronize(r.b));
-      float ms = 0.f;
-      HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
-      plan->acc_ms[r.kid] += ms;
-      plan->acc_n[r.kid] += 1;
-      t->pool.push_back(r.a);
-      t->pool.push_back(r.b);
+      if (r.a && r.b && r.closed) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        plan->acc_ms[r.kid] += ms;
+        plan->acc_n[r.kid] += 1;
+        plan->samples[r.kid].push_back(ms);
+      }
+      if (r.a) t->pool.push_back(r.a);
+      if (r.b) t->pool.push_back(r.b);
     }
     t->recs.clear();
   }
@@ -872,13 +952,38 @@ psdns_status psdns_get_timing(psdns_plan* plan, psdns_kernel_timing* out, int32_
     std::snprintf(out[k].name, sizeof(out[k].name), "%s", kKernelNames[i]);
     out[k].launches = plan->acc_n[i];
     out[k].total_ms = plan->acc_ms[i];
+    std::vector<float>& v = plan->samples[i];
+    out[k].median_ms = 0.0;
+    out[k].min_ms = 0.0;
+    if (!v.empty()) {
+      std::sort(v.begin(), v.end());
+      const size_t n = v.size();
+      out[k].median_ms = n % 2 ? v[n / 2] : 0.5 * ((double)v[n / 2 - 1] + v[n / 2]);
+      out[k].min_ms = v[0];
+    }
     ++k;
   }
   if (count) *count = k;
   for (int i = 0; i < KID_COUNT; ++i) {
     plan->acc_ms[i] = 0;
     plan->acc_n[i] = 0;
+    plan->samples[i].clear();
   }
+  return PSDNS_OK;
+}
+
+psdns_status psdns_stream_copy(void* dst, const void* src, size_t bytes, int32_t blocks, void* hip_stream) {
+  if (!dst || !src) return fail(PSDNS_E_INVAL, "dst and src must be device pointers");
+  if (bytes % 16 || (reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16)
+    return fail(PSDNS_E_INVAL, "bytes and both pointers must be multiples of 16");
+  if (blocks < 1 || blocks > (1 << 20)) return fail(PSDNS_E_INVAL, "blocks must be in [1, 2^20]");
+  const char* d = static_cast<const char*>(dst);
+  const char* q = static_cast<const char*>(src);
+  if (d < q + bytes && q < d + bytes) return fail(PSDNS_E_INVAL, "dst and src overlap");
+  if (bytes == 0) return PSDNS_OK;
+  k_stream_copy<<<blocks, 256, 0, static_cast<hipStream_t>(hip_stream)>>>(static_cast<const uint4*>(src),
+                                                                          static_cast<uint4*>(dst), bytes / 16);
+  HIP_TRY(hipGetLastError());
   return PSDNS_OK;
 }
 

@@ -26,7 +26,25 @@ struct Geom {
   long long b_field;      // per field after the y pass: N*N*PX   ([z][y][kx])
   int nblk_x;             // x-pass blocks per slot (partial maxima)
   int ns;                 // spectral shells 0 .. ns-1, ns = nint(sqrt(3) K) + 1
+  int sphere;             // retained set: 0 the cube |k_i| <= K (2/3 rule); 1 the sphere
+                          // 9 |k|^2 < 2 N^2 inside that cube (phase-shift dealiasing)
 };
+
+// Whether wavevector (kx, ky, kz), with |k_i| <= K, is retained.
+__host__ __device__ inline bool retained(const Geom& g, int kx, int ky, int kz) {
+  return !g.sphere || 9LL * ((long long)kx * kx + (long long)ky * ky + (long long)kz * kz) < 2LL * g.N * g.N;
+}
+
+// Layout of the plan's root table (plan precision, interleaved complex):
+//   [0, N)               w_N^m = exp(-2 pi i m / N)
+//   [N + kRootOff(R), +R) exp(-2 pi i m / R) for the odd radices R = 3, 5, 7, 11, 13
+//   [N + kShiftOff, +N/2+1) exp(i pi k / N), k = 0 .. N/2 (the half-cell grid shift)
+constexpr int kOddRadices[5] = {3, 5, 7, 11, 13};
+__host__ __device__ constexpr int kRootOff(int R) {
+  return R == 3 ? 0 : R == 5 ? 3 : R == 7 ? 8 : R == 11 ? 15 : 26;
+}
+constexpr int kShiftOff = 39;
+__host__ __device__ constexpr long long root_table_entries(int N) { return (long long)N + kShiftOff + N / 2 + 1; }
 
 // Row placement: row (kz_c, ky_c) of a state field and row (z, ky_c) of a field
 // after the z pass both sit at (z M + ky_c) PX, so the two share their strides.
@@ -84,6 +102,7 @@ enum KernelId {
   KID_ZFWD,
   KID_AUX,
   KID_ZFWDI,
+  KID_STEP,  // one whole RK4 step (a graph replay or the launches of an eager step)
   KID_COUNT
 };
 
@@ -106,6 +125,7 @@ struct Ctx {
   DynDev* dyn;             // device [batch]
   double* fband;           // device [batch][kStochCand][12] FP64 (stochastic forcing: b, P(k) b)
   void* abuf;              // [batch][FA][N][M][PX]
+  void* akeep;             // phase-shift dealiasing: forward product of the unshifted evaluation [batch][F][N][M][PX]
   void* bbuf;              // [batch][FB][N][N][PX]
   void* ystage;            // [batch][F][M][M][PX]
   void* acc;               // [batch][F][M][M][PX]

@@ -1584,10 +1584,11 @@ k_init_energy(Geom g, uint64_t seed, double kp, int kind, double* __restrict__ p
     const int kyc = (int)((i / g.KX) % g.M);
     const int kzc = (int)(i / ((long long)g.KX * g.M));
     double re[3], im[3];
-    init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, kind, re, im);
+    const int ky = wave_of_compact(kyc, g.K, g.M), kz = wave_of_compact(kzc, g.K, g.M);
+    init_coeff(kx, ky, kz, g.N, seed, kp, kind, re, im);
     double s = 0.0;
     for (int c = 0; c < 3; ++c) s += re[c] * re[c] + im[c] * im[c];
-    e = (kx == 0 ? 0.5 : 1.0) * s;
+    e = retained(g, kx, ky, kz) ? (kx == 0 ? 0.5 : 1.0) * s : 0.0;
   }
   red[threadIdx.x] = e;
   __syncthreads();
@@ -1627,8 +1628,9 @@ k_init_write(cpx<T>* __restrict__ st, Geom g, int slot, uint64_t seed, double kp
   const int kyc = (int)((i / g.KX) % g.M);
   const int kzc = (int)(i / ((long long)g.KX * g.M));
   double re[3], im[3];
-  init_coeff(kx, wave_of_compact(kyc, g.K, g.M), wave_of_compact(kzc, g.K, g.M), g.N, seed, kp, kind, re, im);
-  const double sc = d->scratch;
+  const int ky = wave_of_compact(kyc, g.K, g.M), kz = wave_of_compact(kzc, g.K, g.M);
+  init_coeff(kx, ky, kz, g.N, seed, kp, kind, re, im);
+  const double sc = retained(g, kx, ky, kz) ? d->scratch : 0.0;
   const long long o = st_row(kzc, kyc, g.M, g.PX) + kx;
   cpx<T>* base = st + (long long)slot * g.F * g.st_field;
   for (int c = 0; c < 3; ++c) base[o + c * g.st_field] = {T(sc * re[c]), T(sc * im[c])};
@@ -1656,15 +1658,18 @@ k_convert(cpx<T>* __restrict__ st, cpx<T>* __restrict__ canon, Geom g, int slot)
   const int kyc = (int)((r / g.KX) % g.M);
   const int kzc = (int)(r / ((long long)g.KX * g.M));
   const int N = g.N, NX = N / 2 + 1;
-  const int iy = (wave_of_compact(kyc, g.K, g.M) + N) % N;
-  const int iz = (wave_of_compact(kzc, g.K, g.M) + N) % N;
+  const int ky = wave_of_compact(kyc, g.K, g.M), kz = wave_of_compact(kzc, g.K, g.M);
+  const int iy = (ky + N) % N;
+  const int iz = (kz + N) % N;
   const long long oc = (((long long)f * N + iz) * N + iy) * NX + kx;
   const long long os = (long long)slot * g.F * g.st_field + (long long)f * g.st_field +
                        st_row(kzc, kyc, g.M, g.PX) + kx;
+  // modes of the bounding cube outside a spherical retained set are not part of the state
+  const bool in = retained(g, kx, ky, kz);
   if (TO_CANON)
-    canon[oc] = st[os];
+    canon[oc] = in ? st[os] : czero<T>();
   else
-    st[os] = canon[oc];
+    st[os] = in ? canon[oc] : czero<T>();
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,762 @@
+// General kernels of the right-hand side and its stage update for any even N whose prime
+// factors are 2, 3, 5, 7, 11 and 13 (the paper's N = 520 = 2^3 5 13, Sec. 3.1), and for the
+// paper's dealiasing: the mean of the products on the grid and on the grid shifted by half a
+// cell, truncated to the sphere |k| < sqrt(2) N / 3 (Sec. 2.3).
+//
+// The passes and the layouts are those of the tuned power-of-two kernels (z inverse,
+// y inverse, x pass with the products, y forward, z forward with projection, forcing and the
+// integrating-factor RK4 update), with N, K and the retained set known only at run time.
+// Transforms are Stockham stages of mixed radix that keep whole lines in LDS: W columns per
+// block (one row segment of the kx tile), TT threads per column, each stage a loop over the
+// N/R butterflies of radix R with a block barrier between stages.  These kernels favour
+// generality over speed: the tuned kernels stay the path for power-of-two grids.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.hpp"
+#include "fft.hpp"
+
+namespace psdns {
+namespace gen {
+
+constexpr int kMaxStages = 16;
+constexpr int kMaxOut = 3 * (6 + 3 * kMaxScalars);
+
+// Radices of the transform stages of an N-point line: eights, then one four or two for
+// the rest of the power of two, then the odd primes.
+struct Factors {
+  int n, nst;
+  int r[kMaxStages];
+};
+
+inline Factors factor(int N) {
+  Factors f{};
+  f.n = N;
+  int m = N;
+  while (m % 8 == 0) {
+    f.r[f.nst++] = 8;
+    m /= 8;
+  }
+  if (m % 4 == 0) {
+    f.r[f.nst++] = 4;
+    m /= 4;
+  }
+  if (m % 2 == 0) {
+    f.r[f.nst++] = 2;
+    m /= 2;
+  }
+  for (int p : kOddRadices)
+    while (m % p == 0) {
+      f.r[f.nst++] = p;
+      m /= p;
+    }
+  return f;
+}
+
+// In-register DFT of odd prime length R from the roots exp(-2 pi i m / R) (conjugated for
+// the inverse): y_k = sum_n a_n w^(k n), paired as a_n + a_{R-n} and a_n - a_{R-n}.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void dft_odd(cpx<T> (&a)[R], const cpx<T> (&w)[R]) {
+  cpx<T> s[R / 2 + 1], d[R / 2 + 1];
+#pragma unroll
+  for (int n = 1; n <= R / 2; ++n) {
+    s[n] = a[n] + a[R - n];
+    d[n] = a[n] - a[R - n];
+  }
+  cpx<T> y[R];
+  cpx<T> y0 = a[0];
+#pragma unroll
+  for (int n = 1; n <= R / 2; ++n) y0 = y0 + s[n];
+  y[0] = y0;
+#pragma unroll
+  for (int k = 1; k <= R / 2; ++k) {
+    // w^(k n) = c + i s with c = Re w_{kn}, s = Im w_{kn}; the pair (n, R - n) contributes
+    // c (a_n + a_{R-n}) + i s (a_n - a_{R-n}) to y_k and c (...) - i s (...) to y_{R-k}
+    cpx<T> cr = a[0], ci = {T(0), T(0)};
+#pragma unroll
+    for (int n = 1; n <= R / 2; ++n) {
+      const cpx<T> wk = w[(k * n) % R];
+      const T c = wk.x, sn = INV ? -wk.y : wk.y;
+      cr = cr + c * s[n];
+      ci = ci + sn * d[n];
+    }
+    y[k] = cr + mul_i(ci);
+    y[R - k] = cr - mul_i(ci);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) a[k] = y[k];
+}
+
+// One Stockham stage of radix R from src to dst (LDS; element p of column c at p W + c):
+// butterfly b < N/R takes positions b + r N/R, applies the twiddles w_N^(r kv N/(NS R)),
+// kv = b mod NS, and writes positions (b / NS) NS R + kv + r NS.
+template <int R, bool INV, typename T>
+__device__ __forceinline__ void stage(const cpx<T>* src, cpx<T>* dst, int W, int c, int j, int TT, int N, int NS,
+                                      const cpx<T>* __restrict__ tw) {
+  const int nb = N / R;
+  cpx<T> root[R];
+  if constexpr (R % 2 == 1) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) root[m] = tw[N + kRootOff(R) + m];
+  }
+  for (int b = j; b < nb; b += TT) {
+    const int kv = b % NS;
+    cpx<T> a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = src[(b + r * nb) * W + c];
+    if (NS > 1) {
+      const int step = N / (NS * R);
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        cpx<T> w = tw[r * kv * step];
+        if (INV) w.y = -w.y;
+        a[r] = cmul(a[r], w);
+      }
+    }
+    if constexpr (R % 2 == 1)
+      dft_odd<R, INV>(a, root);
+    else
+      dft<R, INV>(a);
+    const int base = (b / NS) * NS * R + kv;
+#pragma unroll
+    for (int r = 0; r < R; ++r) dst[(base + r * NS) * W + c] = a[r];
+  }
+}
+
+// Full N-point transform of the W columns held in b0 (all threads of the block call it).
+// Returns the buffer (b0 or b1) that holds the result in natural order.
+template <bool INV, typename T>
+__device__ cpx<T>* fft(cpx<T>* b0, cpx<T>* b1, const Factors& f, int W, int c, int j, int TT,
+                       const cpx<T>* __restrict__ tw) {
+  cpx<T>* src = b0;
+  cpx<T>* dst = b1;
+  int NS = 1;
+  for (int st = 0; st < f.nst; ++st) {
+    const int R = f.r[st];
+    switch (R) {
+      case 2: stage<2, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      case 3: stage<3, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      case 4: stage<4, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      case 5: stage<5, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      case 7: stage<7, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      case 8: stage<8, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      case 11: stage<11, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+      default: stage<13, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
+    }
+    __syncthreads();
+    NS *= R;
+    cpx<T>* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
+// exp(i pi k / N) for |k| <= N/2 (the half-cell shift along one axis), from the table
+template <typename T>
+__device__ __forceinline__ cpx<T> shift_of(const cpx<T>* __restrict__ tw, int N, int k) {
+  const cpx<T> v = tw[N + kShiftOff + (k < 0 ? -k : k)];
+  return k < 0 ? conj(v) : v;
+}
+
+// position n of a line -> signed wavenumber; compact index along ky/kz (-1 if |k| > K)
+__device__ __forceinline__ int wave(int n, int N) { return n <= N / 2 ? n : n - N; }
+__device__ __forceinline__ int compact(int k, int K, int M) { return k > K || k < -K ? -1 : (k >= 0 ? k : k + M); }
+
+// Output fields of a column pass: out_o = sum over its terms of sgn (i k_axis)^[axis > 0]
+// in_f, axis 0 none, 1 x, 2 y, 3 z (k of the column or of the line).
+struct Spec {
+  int nout;
+  int nterm[kMaxOut];
+  int f[kMaxOut][2];
+  int axis[kMaxOut][2];
+  float sgn[kMaxOut][2];
+};
+
+// Launch shape of the column passes: W columns (a row segment of the kx tile) and TT
+// threads per column, with two line buffers per column in dynamic LDS.
+struct Shape {
+  int W, TT;
+  size_t lds;
+};
+constexpr int kMaxPerThread = 16;  // positions n = j + TT m of a column held by one thread
+
+inline Shape col_shape(int N, int csize) {
+  Shape s{};
+  s.W = csize == 8 ? 16 : 8;
+  while (s.W > 1 && 2 * (size_t)s.W * N * csize > 150 * 1024) s.W /= 2;
+  // threads per column: up to 128 (and 1024 per block), at least N / kMaxPerThread
+  s.TT = 1024 / s.W < 128 ? 1024 / s.W : 128;
+  if (s.TT > N / 2) s.TT = N / 2;
+  s.lds = 2 * (size_t)s.W * N * csize;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// z inverse: state columns along kz (compact rows) -> A fields, all N positions of z.
+// shift: inputs carry exp(i pi kz / N) (the kx and ky parts are applied by the later passes).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw,
+            const SlotDev* __restrict__ slots, Geom g, Factors fz, Spec sp, int W, int TT, int shift, T scale) {
+  extern __shared__ char lds_raw[];
+  cpx<T>* b0 = reinterpret_cast<cpx<T>*>(lds_raw);
+  cpx<T>* b1 = b0 + (size_t)W * g.N;
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  const int c = threadIdx.x % W, j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c, kyc = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const int N = g.N, M = g.M;
+  const int ky = kyc <= g.K ? kyc : kyc - M;
+  const cpx<T>* sbase = st + (long long)slot * g.F * g.st_field;
+  cpx<T>* abase = abuf + (long long)slot * g.FA * g.a_field;
+  for (int o = 0; o < sp.nout; ++o) {
+    for (int n = j; n < N; n += TT) {
+      const int kz = wave(n, N), kc = compact(kz, g.K, M);
+      cpx<T> v = {T(0), T(0)};
+      // only retained modes are read: the stage inputs hold nothing defined outside a sphere
+      if (valid && kc >= 0 && retained(g, kx, ky, kz)) {
+        for (int t = 0; t < sp.nterm[o]; ++t) {
+          cpx<T> x = sbase[(long long)sp.f[o][t] * g.st_field + st_row(kc, kyc, M, g.PX) + kx];
+          const int ax = sp.axis[o][t];
+          if (ax) x = mul_is(x, T(ax == 1 ? kx : ax == 2 ? ky : kz));
+          v = v + T(sp.sgn[o][t]) * x;
+        }
+        v = scale * v;
+        if (shift) v = cmul(v, shift_of(tw, N, kz));
+      }
+      b0[n * W + c] = v;
+    }
+    __syncthreads();
+    const cpx<T>* res = fft<true>(b0, b1, fz, W, c, j, TT, tw);
+    if (valid)
+      for (int n = j; n < N; n += TT) abase[(long long)o * g.a_field + a_row(n, kyc, M, g.PX) + kx] = res[n * W + c];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y inverse: A columns along ky (compact rows) at fixed z -> B fields, all N positions of y.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw,
+            const SlotDev* __restrict__ slots, Geom g, Factors fy, Spec sp, int W, int TT, int shift) {
+  extern __shared__ char lds_raw[];
+  cpx<T>* b0 = reinterpret_cast<cpx<T>*>(lds_raw);
+  cpx<T>* b1 = b0 + (size_t)W * g.N;
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  const int c = threadIdx.x % W, j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c, z = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const int N = g.N, M = g.M;
+  const cpx<T>* abase = abuf + (long long)slot * g.FA * g.a_field;
+  cpx<T>* bbase = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX;
+  for (int o = 0; o < sp.nout; ++o) {
+    for (int n = j; n < N; n += TT) {
+      const int ky = wave(n, N), kc = compact(ky, g.K, M);
+      cpx<T> v = {T(0), T(0)};
+      if (valid && kc >= 0) {
+        for (int t = 0; t < sp.nterm[o]; ++t) {
+          cpx<T> x = abase[(long long)sp.f[o][t] * g.a_field + a_row(z, kc, M, g.PX) + kx];
+          const int ax = sp.axis[o][t];
+          if (ax) x = mul_is(x, T(ax == 1 ? kx : ky));
+          v = v + T(sp.sgn[o][t]) * x;
+        }
+        if (shift) v = cmul(v, shift_of(tw, N, ky));
+      }
+      b0[n * W + c] = v;
+    }
+    __syncthreads();
+    const cpx<T>* res = fft<true>(b0, b1, fy, W, c, j, TT, tw);
+    if (valid)
+      for (int n = j; n < N; n += TT) bbase[(long long)o * g.b_field + (long long)n * g.PX + kx] = res[n * W + c];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y forward: the first nf B fields along y (all N positions) at fixed z -> A (or the kept
+// unshifted product), rows |ky| <= K; shift multiplies by exp(-i pi ky / N).
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ aout, int a_fields, const cpx<T>* __restrict__ tw,
+            const SlotDev* __restrict__ slots, Geom g, Factors fy, int nf, int W, int TT, int shift) {
+  extern __shared__ char lds_raw[];
+  cpx<T>* b0 = reinterpret_cast<cpx<T>*>(lds_raw);
+  cpx<T>* b1 = b0 + (size_t)W * g.N;
+  const int slot = blockIdx.z;
+  if (!slots[slot].active) return;
+  const int c = threadIdx.x % W, j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c, z = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const int N = g.N, M = g.M;
+  const cpx<T>* bbase = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX;
+  cpx<T>* obase = aout + (long long)slot * a_fields * g.a_field;
+  for (int f = 0; f < nf; ++f) {
+    for (int n = j; n < N; n += TT)
+      b0[n * W + c] = valid ? bbase[(long long)f * g.b_field + (long long)n * g.PX + kx] : cpx<T>{T(0), T(0)};
+    __syncthreads();
+    const cpx<T>* res = fft<false>(b0, b1, fy, W, c, j, TT, tw);
+    if (valid)
+      for (int n = j; n < N; n += TT) {
+        const int ky = wave(n, N), kc = compact(ky, g.K, M);
+        if (kc < 0) continue;
+        cpx<T> v = res[n * W + c];
+        if (shift) v = cmul(v, conj(shift_of(tw, N, ky)));
+        obase[(long long)f * g.a_field + a_row(z, kc, M, g.PX) + kx] = v;
+      }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// x pass: one (z, y) line per block.  Pairs of real fields travel as one complex line
+// h = f + i g (half-spectrum entries kx <= K, their conjugates at N - kx); the physical
+// fields are kept in LDS, the products u x omega and u.grad phi_s + g_s.u formed pointwise
+// and transformed back, kx <= K written in place into the first F fields of B.  shift
+// multiplies the inputs by exp(i pi kx / N) and the outputs by its conjugate; with umax
+// the block's max |u1|+|u2|+|u3| joins the slot's maximum (Eq. (10)).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct XLds {
+  cpx<T>* b0;
+  cpx<T>* b1;
+  T* phys;  // [6 + S][N]: u1 u2 u3 c1 c2 c3 (omega while it is formed) a_0 .. a_{S-1}
+  double* red;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots,
+         DynDev* __restrict__ dyn, Geom g, Factors fx, int shift, int umax) {
+  extern __shared__ char lds_raw[];
+  const int N = g.N, S = g.S, K = g.K;
+  XLds<T> L;
+  L.b0 = reinterpret_cast<cpx<T>*>(lds_raw);
+  L.b1 = L.b0 + N;
+  L.phys = reinterpret_cast<T*>(L.b1 + N);
+  L.red = reinterpret_cast<double*>(L.phys + (size_t)(6 + S) * N + (N & 1));
+  const int slot = blockIdx.y;
+  if (!slots[slot].active) return;
+  const SlotDev& sp = slots[slot];
+  const long long line = blockIdx.x;  // z * N + y
+  const int TT = blockDim.x, j = threadIdx.x;
+  cpx<T>* lbase = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
+  // entry kx of the combination (field fa, optional i kx factor, sign)
+  auto entry = [&](int f, bool dx, T sg, int kx) {
+    cpx<T> v = lbase[(long long)f * g.b_field + kx];
+    if (dx) v = mul_is(v, T(kx));
+    v = sg * v;
+    if (shift) v = cmul(v, shift_of(tw, N, kx));
+    return v;
+  };
+  // a_e (sa x) + b_e: value of real field (fa1 (+ i kx) ... ) at kx, as a combination of up to
+  // two B fields: first (f1, dx1, s1), second (f2, dx2, s2) with f2 < 0 for none
+  struct Comb {
+    int f1;
+    bool dx1;
+    T s1;
+    int f2;
+    bool dx2;
+    T s2;
+  };
+  auto coeff = [&](const Comb& q, int kx) {
+    if (q.f1 < 0) return cpx<T>{T(0), T(0)};
+    cpx<T> v = entry(q.f1, q.dx1, q.s1, kx);
+    if (q.f2 >= 0) v = v + entry(q.f2, q.dx2, q.s2, kx);
+    if (kx == 0) v.y = T(0);
+    return v;
+  };
+  // inverse transform of the pair (qa, qb); the physical values are Re and Im of the result
+  auto inverse_pair = [&](const Comb& qa, const Comb& qb) -> const cpx<T>* {
+    for (int n = j; n < N; n += TT) {
+      cpx<T> h = {T(0), T(0)};
+      if (n <= K) {
+        h = coeff(qa, n) + mul_i(coeff(qb, n));
+      } else if (n >= N - K) {
+        h = conj(coeff(qa, N - n)) + mul_i(conj(coeff(qb, N - n)));
+      }
+      L.b0[n] = h;
+    }
+    __syncthreads();
+    return fft<true>(L.b0, L.b1, fx, 1, 0, j, TT, tw);
+  };
+  T* u1 = L.phys;
+  T* u2 = u1 + N;
+  T* u3 = u2 + N;
+  T* c1 = u3 + N;
+  T* c2 = c1 + N;
+  T* c3 = c2 + N;
+  T* as = c3 + N;
+  const Comb none = {-1, false, T(0), -1, false, T(0)};
+  // B fields: 0 u1, 1 u2, 2 u3, 3 omega1, 4 dz u1, 5 dy u1, 6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s
+  const cpx<T>* r = inverse_pair({0, false, T(1), -1, false, T(0)}, {1, false, T(1), -1, false, T(0)});
+  for (int n = j; n < N; n += TT) {
+    u1[n] = r[n].x;
+    u2[n] = r[n].y;
+  }
+  __syncthreads();
+  r = inverse_pair({2, false, T(1), -1, false, T(0)}, {3, false, T(1), -1, false, T(0)});
+  for (int n = j; n < N; n += TT) {
+    u3[n] = r[n].x;
+    c1[n] = r[n].y;  // omega1 until c is formed
+  }
+  __syncthreads();
+  // omega2 = dz u1 - dx u3, omega3 = dx u2 - dy u1
+  r = inverse_pair({4, false, T(1), 2, true, T(-1)}, {1, true, T(1), 5, false, T(-1)});
+  double mx = 0.0;
+  for (int n = j; n < N; n += TT) {
+    const T w1 = c1[n], w2 = r[n].x, w3 = r[n].y;
+    const T a = u1[n], b = u2[n], c = u3[n];
+    c1[n] = b * w3 - c * w2;
+    c2[n] = c * w1 - a * w3;
+    c3[n] = a * w2 - b * w1;
+    const double sm = fabs((double)a) + fabs((double)b) + fabs((double)c);
+    mx = (sm > mx || sm != sm) ? sm : mx;
+  }
+  __syncthreads();
+  for (int s = 0; s < S; ++s) {
+    const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
+    r = inverse_pair({6 + 3 * s, true, T(1), -1, false, T(0)}, {7 + 3 * s, false, T(1), -1, false, T(0)});
+    for (int n = j; n < N; n += TT)
+      as[s * N + n] = u1[n] * r[n].x + u2[n] * r[n].y + (g0 * u1[n] + g1 * u2[n] + g2 * u3[n]);
+    __syncthreads();
+    r = inverse_pair({8 + 3 * s, false, T(1), -1, false, T(0)}, none);
+    for (int n = j; n < N; n += TT) as[s * N + n] += u3[n] * r[n].x;
+    __syncthreads();
+  }
+  // forward: pairs of the F output fields c1 c2 c3 a_0 .. a_{S-1}
+  const int F = 3 + S;
+  auto out_field = [&](int f) -> const T* { return f < 3 ? c1 + (size_t)f * N : as + (size_t)(f - 3) * N; };
+  for (int fp = 0; fp < F; fp += 2) {
+    const int fq = fp + 1 < F ? fp + 1 : -1;
+    const T* p = out_field(fp);
+    const T* q = fq >= 0 ? out_field(fq) : nullptr;
+    for (int n = j; n < N; n += TT) L.b0[n] = {p[n], q ? q[n] : T(0)};
+    __syncthreads();
+    const cpx<T>* Z = fft<false>(L.b0, L.b1, fx, 1, 0, j, TT, tw);
+    for (int k = j; k <= K; k += TT) {
+      const cpx<T> zk = Z[k], zc = conj(Z[(N - k) % N]);
+      cpx<T> P = T(0.5) * (zk + zc);
+      cpx<T> Q = mul_mi(T(0.5) * (zk - zc));
+      if (shift) {
+        const cpx<T> e = conj(shift_of(tw, N, k));
+        P = cmul(P, e);
+        Q = cmul(Q, e);
+      }
+      lbase[(long long)fp * g.b_field + k] = P;
+      if (fq >= 0) lbase[(long long)fq * g.b_field + k] = Q;
+    }
+    __syncthreads();
+  }
+  if (umax) {
+    L.red[j] = mx;
+    __syncthreads();
+    for (int o = TT / 2; o > 0; o >>= 1) {
+      if (j < o) {
+        const double a = L.red[j], b = L.red[j + o];
+        L.red[j] = (b > a || b != b) ? b : a;
+      }
+      __syncthreads();
+    }
+    if (j == 0) atomicMax(&dyn[slot].umax, (unsigned long long)__double_as_longlong(L.red[0]));
+  }
+}
+
+inline size_t x_lds_bytes(int N, int S, int csize, int threads) {
+  const size_t real = csize / 2;
+  return 2 * (size_t)N * csize + (size_t)(6 + S) * N * real + (N & 1) * real + (size_t)threads * sizeof(double);
+}
+
+// ---------------------------------------------------------------------------
+// z forward + assembly + stage update.  Each field is transformed along z; with the phase
+// shift the kept unshifted product (akeep) is transformed too and the mean
+// (P0 + P1 exp(-i pi kz / N)) / 2 taken.  Modes outside the retained set are dropped; then
+// F_u = P(k) c_hat + A 1_band u_hat (+ the stochastic band term), F_phi = -a_hat, and the
+// update of the stage (dy/dt for stage < 0) exactly as the tuned kernels do it.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct GStage {
+  cpx<T>* yn;
+  cpx<T>* acc;
+  cpx<T>* ys;
+  const cpx<T>* sin;
+  cpx<T>* rhs;
+  const double* fband;
+  int stage;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> update(const GStage<T>& a, long long o, cpx<T> F, double lk2, double h, bool expl) {
+  if (a.stage < 0) {
+    a.rhs[o] = F - T(lk2) * a.sin[o];
+    return {T(0), T(0)};
+  }
+  const cpx<T> y = a.stage < 3 ? a.yn[o] : cpx<T>{T(0), T(0)};
+  T eh, e1;
+  if (expl) {
+    F = F - T(lk2) * (a.stage == 0 ? y : a.sin[o]);
+    eh = e1 = T(1);
+  } else {
+    const double e = exp(-0.5 * lk2 * h);
+    eh = T(e);
+    e1 = T(e * e);
+  }
+  const T th = T(h);
+  cpx<T> nxt;
+  switch (a.stage) {
+    case 0:
+      a.acc[o] = e1 * (y + (th / T(6)) * F);
+      nxt = eh * (y + (th / T(2)) * F);
+      break;
+    case 1:
+      a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
+      nxt = eh * y + (th / T(2)) * F;
+      break;
+    case 2:
+      a.acc[o] = a.acc[o] + ((th / T(3)) * eh) * F;
+      nxt = e1 * y + (th * eh) * F;
+      break;
+    default:
+      nxt = a.acc[o] + (th / T(6)) * F;
+      a.yn[o] = nxt;
+      return nxt;
+  }
+  a.ys[o] = nxt;
+  return nxt;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(1024)
+k_z_forward_update(const cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ akeep, GStage<T> sa,
+                   const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn,
+                   Geom g, Factors fz, int W, int TT) {
+  extern __shared__ char lds_raw[];
+  cpx<T>* b0 = reinterpret_cast<cpx<T>*>(lds_raw);
+  cpx<T>* b1 = b0 + (size_t)W * g.N;
+  const int slot = blockIdx.z;
+  const SlotDev& sp = slots[slot];
+  if (!sp.active) return;
+  const int c = threadIdx.x % W, j = threadIdx.x / W;
+  const int kx = blockIdx.x * W + c, kyc = blockIdx.y;
+  const bool valid = kx < g.KX;
+  const int N = g.N, M = g.M, K = g.K;
+  const int ky = kyc <= K ? kyc : kyc - M;
+  const double h = dyn[slot].dt, A = dyn[slot].A;
+  const bool expl = sp.integrator == PSDNS_INTEGRATOR_EXPLICIT;
+  const cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
+  const cpx<T>* kslot = akeep ? akeep + (long long)slot * g.F * g.a_field : nullptr;
+  const long long sslot = (long long)slot * g.F * g.st_field;
+  const int np = (N - j + TT - 1) / TT;  // positions n = j + TT m of this thread
+  // transformed (and, with the shift, averaged) field f at this thread's positions
+  auto forward = [&](int f, cpx<T> (&v)[kMaxPerThread]) {
+    for (int n = j; n < N; n += TT)
+      b0[n * W + c] = valid ? aslot[(long long)f * g.a_field + a_row(n, kyc, M, g.PX) + kx] : cpx<T>{T(0), T(0)};
+    __syncthreads();
+    const cpx<T>* r = fft<false>(b0, b1, fz, W, c, j, TT, tw);
+#pragma unroll
+    for (int m = 0; m < kMaxPerThread; ++m)
+      if (m < np) v[m] = r[(j + TT * m) * W + c];
+    __syncthreads();
+    if (kslot) {
+      for (int n = j; n < N; n += TT)
+        b0[n * W + c] = valid ? kslot[(long long)f * g.a_field + a_row(n, kyc, M, g.PX) + kx] : cpx<T>{T(0), T(0)};
+      __syncthreads();
+      r = fft<false>(b0, b1, fz, W, c, j, TT, tw);
+#pragma unroll
+      for (int m = 0; m < kMaxPerThread; ++m)
+        if (m < np) {
+          const int kz = wave(j + TT * m, N);
+          // akeep holds the unshifted product, abuf the shifted one
+          v[m] = T(0.5) * (r[(j + TT * m) * W + c] + cmul(v[m], conj(shift_of(tw, N, kz))));
+        }
+      __syncthreads();
+    }
+  };
+  auto mode_of = [&](int m, long long& o, double& k2) {
+    if (!valid || m >= np) return false;
+    const int kz = wave(j + TT * m, N), kc = compact(kz, K, M);
+    if (kc < 0 || !retained(g, kx, ky, kz)) return false;
+    o = st_row(kc, kyc, M, g.PX) + kx;
+    k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
+    return true;
+  };
+  for (int s = 0; s < g.S; ++s) {
+    cpx<T> a[kMaxPerThread];
+    forward(3 + s, a);
+    const double dif = sp.diff[3 + s];
+    GStage<T> q = sa;
+    const long long foff = sslot + (long long)(3 + s) * g.st_field;
+    q.yn += foff;
+    q.acc += foff;
+    q.ys += foff;
+    q.sin += foff;
+    q.rhs += sa.stage < 0 ? foff : 0;
+#pragma unroll
+    for (int m = 0; m < kMaxPerThread; ++m) {
+      long long o;
+      double k2;
+      if (m < np && mode_of(m, o, k2)) {
+        const cpx<T> F = k2 == 0.0 ? cpx<T>{T(0), T(0)} : cpx<T>{-a[m].x, -a[m].y};
+        update(q, o, F, dif * k2, h, expl);
+      }
+    }
+  }
+  cpx<T> c1[kMaxPerThread], c2[kMaxPerThread], c3[kMaxPerThread];
+  forward(0, c1);
+  forward(1, c2);
+  forward(2, c3);
+  int kfs = 0;
+  while ((double)(kfs + 1) * (kfs + 1) <= sp.kf2) ++kfs;
+  if (kfs > K) kfs = K;
+  const bool stoch = sp.forcing == PSDNS_FORCING_STOCHASTIC || sp.forcing == PSDNS_FORCING_ALVELIUS;
+  GStage<T> q[3];
+  for (int f = 0; f < 3; ++f) {
+    q[f] = sa;
+    const long long foff = sslot + (long long)f * g.st_field;
+    q[f].yn += foff;
+    q[f].acc += foff;
+    q[f].ys += foff;
+    q[f].sin += foff;
+    q[f].rhs += sa.stage < 0 ? foff : 0;
+  }
+#pragma unroll
+  for (int m = 0; m < kMaxPerThread; ++m) {
+    long long o;
+    double k2;
+    if (!(m < np && mode_of(m, o, k2))) continue;
+    const int kz = wave(j + TT * m, N);
+    cpx<T> F1 = {T(0), T(0)}, F2 = F1, F3 = F1;
+    const bool band = k2 > 0.0 && k2 <= sp.kf2;
+    if (k2 > 0.0) {
+      cpx<T> p1 = c1[m], p2 = c2[m], p3 = c3[m];
+      if (stoch && band) {
+        const double* e = sa.fband + ((long long)slot * kStochCand + kx + (kfs + 1) * ((ky + kfs) + (2 * kfs + 1) * (kz + kfs))) * 12 + 6;
+        p1 = p1 + cpx<T>{T(e[0]), T(e[1])};
+        p2 = p2 + cpx<T>{T(e[2]), T(e[3])};
+        p3 = p3 + cpx<T>{T(e[4]), T(e[5])};
+      }
+      const T ik2 = T(1.0 / k2);
+      const T kxt = T(kx), kyt = T(ky), kzt = T(kz);
+      const cpx<T> kdc = kxt * p1 + kyt * p2 + kzt * p3;
+      F1 = p1 - (kxt * ik2) * kdc;
+      F2 = p2 - (kyt * ik2) * kdc;
+      F3 = p3 - (kzt * ik2) * kdc;
+      if (A != 0.0 && band) {
+        const T At = T(A);
+        F1 = F1 + At * q[0].sin[o];
+        F2 = F2 + At * q[1].sin[o];
+        F3 = F3 + At * q[2].sin[o];
+      }
+    }
+    const double lk2 = sp.nu * k2;
+    update(q[0], o, F1, lk2, h, expl);
+    update(q[1], o, F2, lk2, h, expl);
+    update(q[2], o, F3, lk2, h, expl);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// moments of nf B fields along x lines (statistics): FP64 sums of f^2, f^3, f^4 of the
+// fields [mom0, nf) and max |u1|+|u2|+|u3| when fields 0..2 are the velocity (with_max).
+// A fixed grid of blocks walks the lines in a fixed order; one partial record per block:
+// [3 (nf - mom0)] moments then the max, 3 6 + 1 doubles apart.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_x_moments(const cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, Geom g, Factors fx, int nf, int mom0,
+            int with_max, double* __restrict__ part) {
+  extern __shared__ char lds_raw[];
+  const int N = g.N, K = g.K;
+  cpx<T>* b0 = reinterpret_cast<cpx<T>*>(lds_raw);
+  cpx<T>* b1 = b0 + N;
+  T* uabs = reinterpret_cast<T*>(b1 + N);       // running |u1| + |u2| + |u3| per position
+  double* red = reinterpret_cast<double*>(uabs + N + (N & 1));
+  const int slot = blockIdx.y;
+  const int TT = blockDim.x, j = threadIdx.x;
+  double mom[6][3];
+  for (int f = 0; f < 6; ++f) mom[f][0] = mom[f][1] = mom[f][2] = 0.0;
+  double mx = 0.0;
+  const long long nlines = (long long)N * N;
+  for (long long line = blockIdx.x; line < nlines; line += gridDim.x) {
+    const cpx<T>* lbase = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
+    for (int f = 0; f < nf; f += 2) {
+      const int fb = f + 1 < nf ? f + 1 : -1;
+      for (int n = j; n < N; n += TT) {
+        cpx<T> h = {T(0), T(0)};
+        const int kx = n <= K ? n : (n >= N - K ? N - n : -1);
+        if (kx >= 0) {
+          cpx<T> a = lbase[(long long)f * g.b_field + kx];
+          cpx<T> b = fb >= 0 ? lbase[(long long)fb * g.b_field + kx] : cpx<T>{T(0), T(0)};
+          if (kx == 0) {
+            a.y = T(0);
+            b.y = T(0);
+          }
+          h = n <= K ? a + mul_i(b) : conj(a) + mul_i(conj(b));
+        }
+        b0[n] = h;
+      }
+      __syncthreads();
+      const cpx<T>* r = fft<true>(b0, b1, fx, 1, 0, j, TT, tw);
+      for (int n = j; n < N; n += TT) {
+        const double vx = r[n].x, vy = r[n].y;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+          if (q == f && f >= mom0) {
+            const double v2 = vx * vx;
+            mom[q][0] += v2;
+            mom[q][1] += v2 * vx;
+            mom[q][2] += v2 * v2;
+          }
+          if (q == fb && fb >= mom0) {
+            const double v2 = vy * vy;
+            mom[q][0] += v2;
+            mom[q][1] += v2 * vy;
+            mom[q][2] += v2 * v2;
+          }
+        }
+        if (with_max && f == 0) uabs[n] = T(fabs(vx) + fabs(vy));
+        if (with_max && f == 2) {
+          const double sm = (double)fabs(r[n].x) + (double)uabs[n];
+          mx = (sm > mx || sm != sm) ? sm : mx;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  const int nm = nf - mom0;
+  double* out = part + ((long long)slot * gridDim.x + blockIdx.x) * (3 * 6 + 1);
+  for (int q = 0; q < 3 * nm + 1; ++q) {
+    double v = 0.0;
+    if (q < 3 * nm) {
+#pragma unroll
+      for (int f = 0; f < 6; ++f)
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+          if (f == mom0 + q / 3 && r == q % 3) v = mom[f][r];
+    } else {
+      v = mx;
+    }
+    red[j] = v;
+    __syncthreads();
+    for (int o = TT / 2; o > 0; o >>= 1) {
+      if (j < o) {
+        const double a = red[j], b = red[j + o];
+        red[j] = q < 3 * nm ? a + b : ((b > a || b != b) ? b : a);
+      }
+      __syncthreads();
+    }
+    if (j == 0) out[q] = red[0];
+    __syncthreads();
+  }
+}
+
+}  // namespace gen
+}  // namespace psdns

@@ -27,7 +27,12 @@ _c_void_p = ctypes.c_void_p
 
 
 class PlanParams(ctypes.Structure):
-    _fields_ = [("n", _c_int32), ("n_scalars", _c_int32), ("precision", _c_int32), ("batch", _c_int32)]
+    _fields_ = [("n", _c_int32), ("n_scalars", _c_int32), ("precision", _c_int32), ("batch", _c_int32),
+                ("dealias", _c_int32)]
+
+
+DEALIAS_TWO_THIRDS = 0
+DEALIAS_PHASE_SPHERE = 1
 
 
 FORCING_POWER = 0
@@ -58,7 +63,8 @@ class PlanInfo(ctypes.Structure):
                                              "precision", "batch", "n_shells", "spectra_doubles")] + \
                [("state_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("elems_col", _c_int32), ("elems_x", _c_int32), ("n_schedules", _c_int32),
-                ("schedule", _c_int32), ("plan_bytes", ctypes.c_int64)]
+                ("schedule", _c_int32), ("plan_bytes", ctypes.c_int64), ("dealias", _c_int32),
+                ("general", _c_int32)]
 
 
 class ScheduleInfo(ctypes.Structure):
@@ -67,7 +73,8 @@ class ScheduleInfo(ctypes.Structure):
 
 
 class KernelTiming(ctypes.Structure):
-    _fields_ = [("name", ctypes.c_char * 32), ("launches", _c_int32), ("total_ms", ctypes.c_double)]
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", _c_int32), ("total_ms", ctypes.c_double),
+                ("median_ms", ctypes.c_double), ("min_ms", ctypes.c_double)]
 
 
 class PsdnsError(RuntimeError):
@@ -109,6 +116,7 @@ _SIGS = {
     "psdns_set_timing": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_get_timing": (ctypes.c_int, [_c_void_p, ctypes.POINTER(KernelTiming), _c_int32,
                                         ctypes.POINTER(_c_int32)]),
+    "psdns_stream_copy": (ctypes.c_int, [_c_void_p, _c_void_p, ctypes.c_size_t, _c_int32, _c_void_p]),
     "psdns_last_error": (ctypes.c_char_p, []),
 }
 
@@ -148,22 +156,22 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
-def plan_params(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> PlanParams:
-    return PlanParams(n, n_scalars, precision, batch)
+def plan_params(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1, dealias: int = 0) -> PlanParams:
+    return PlanParams(n, n_scalars, precision, batch, dealias)
 
 
-def state_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> int:
-    p = plan_params(n, n_scalars, precision, batch)
+def state_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1, dealias: int = 0) -> int:
+    p = plan_params(n, n_scalars, precision, batch, dealias)
     return int(lib().psdns_state_bytes(ctypes.byref(p)))
 
 
-def workspace_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> int:
-    p = plan_params(n, n_scalars, precision, batch)
+def workspace_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1, dealias: int = 0) -> int:
+    p = plan_params(n, n_scalars, precision, batch, dealias)
     return int(lib().psdns_workspace_bytes(ctypes.byref(p)))
 
 
-def plan_device_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1) -> int:
-    p = plan_params(n, n_scalars, precision, batch)
+def plan_device_bytes(n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1, dealias: int = 0) -> int:
+    p = plan_params(n, n_scalars, precision, batch, dealias)
     return int(lib().psdns_plan_device_bytes(ctypes.byref(p)))
 
 
@@ -174,9 +182,10 @@ class Plan:
     `new_workspace()` allocate them with the sizes the library reports.
     """
 
-    def __init__(self, n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1):
+    def __init__(self, n: int, n_scalars: int = 0, precision: int = 64, batch: int = 1, dealias: int = 0):
         self.n, self.n_scalars, self.precision, self.batch = n, n_scalars, precision, batch
-        self._p = plan_params(n, n_scalars, precision, batch)
+        self.dealias = dealias
+        self._p = plan_params(n, n_scalars, precision, batch, dealias)
         h = ctypes.c_void_p()
         _check(lib().psdns_plan_create(ctypes.byref(self._p), ctypes.byref(h)))
         self._h = h
@@ -369,10 +378,16 @@ class Plan:
     def set_timing(self, enable: bool) -> None:
         _check(lib().psdns_set_timing(self._h, 1 if enable else 0))
 
-    def get_timing(self):
+    def get_timing(self, detail: bool = False):
+        """{name: (launches, total ms)} since the last call; with detail, {name: dict of
+        launches, total_ms, median_ms, min_ms}."""
         arr = (KernelTiming * 16)()
         cnt = _c_int32()
         _check(lib().psdns_get_timing(self._h, arr, 16, ctypes.byref(cnt)))
+        if detail:
+            return {arr[i].name.decode(): dict(launches=arr[i].launches, total_ms=arr[i].total_ms,
+                                               median_ms=arr[i].median_ms, min_ms=arr[i].min_ms)
+                    for i in range(cnt.value)}
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(cnt.value)}
 
 
@@ -380,6 +395,14 @@ def step_info_from_bytes(raw: bytes, batch: int):
     """Records written by psdns_step_noalloc (psdns_step_info[batch]) as dicts."""
     arr = (StepInfo * batch).from_buffer_copy(raw)
     return [dict(t=a.t, dt=a.dt, max_u=a.max_u, steps=a.steps, flags=a.flags, active=a.active) for a in arr]
+
+
+def stream_copy(dst, src, blocks: int) -> None:
+    """The library's streaming copy of src into dst (device uint8 tensors of equal size)."""
+    n = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != n:
+        raise ValueError("dst and src sizes differ")
+    _check(lib().psdns_stream_copy(_ptr(dst), _ptr(src), n, blocks, _stream()))
 
 
 def parse_spectra(r, ns: int, S: int) -> dict:

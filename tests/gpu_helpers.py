@@ -24,9 +24,9 @@ def torch_mod():
     return torch
 
 
-def make_plan(N, S, prec, batch=1):
+def make_plan(N, S, prec, batch=1, dealias=0):
     from paper_2012_04838_amd import psdns
-    return psdns.Plan(N, S, prec, batch)
+    return psdns.Plan(N, S, prec, batch, dealias)
 
 
 def set_params(plan, slot, prm: "ora.Params", active=True):
@@ -45,6 +45,15 @@ def set_params(plan, slot, prm: "ora.Params", active=True):
                   stoch_seed=prm.stoch_seed if (stoch or alv) else 0)
 
 
+def poisoned_workspace(plan):
+    """A workspace whose every byte is 0xFF (NaN in both precisions) before its records are
+    cleared: a pass that reads workspace entries nobody wrote turns the result into NaN."""
+    ws = plan.new_workspace()
+    ws.fill_(255)
+    plan.clear_step_info(ws)
+    return ws
+
+
 def to_numpy(t):
     return t.detach().cpu().numpy().astype(np.complex128)
 
@@ -53,10 +62,10 @@ def gpu_rhs(state_np, prm, prec=64):
     torch = torch_mod()
     N = state_np.shape[-3]
     S = state_np.shape[0] - 3
-    plan = make_plan(N, S, prec)
+    plan = make_plan(N, S, prec, dealias=1 if prm.dealias == "phase" else 0)
     set_params(plan, 0, prm)
     st = plan.new_state()
-    ws = plan.new_workspace()
+    ws = poisoned_workspace(plan)
     out = plan.new_state()
     plan.set_state(st, state_np, 0)
     plan.rhs(st, out, ws)

@@ -28,11 +28,28 @@ def test_library_exports_every_declared_function():
 
 
 def test_sizes_reject_invalid_params():
-    assert psdns.state_bytes(100, 0, 64) == 0
+    assert psdns.state_bytes(34, 0, 64) == 0      # prime factor 17
+    assert psdns.state_bytes(105, 0, 64) == 0     # odd
+    assert psdns.state_bytes(6, 0, 64) == 0       # below 8
     assert psdns.state_bytes(512, 5, 64) == 0
     assert psdns.state_bytes(512, 2, 16) == 0
     assert psdns.workspace_bytes(2048, 0, 32) == 0
-    assert psdns.plan_device_bytes(100, 0, 64) == 0
+    assert psdns.plan_device_bytes(34, 0, 64) == 0
+    assert psdns.state_bytes(64, 0, 64, dealias=2) == 0
+
+
+def test_mixed_radix_and_phase_shift_plans_size_their_retained_sets():
+    # N = 520 = 2^3 5 13 (the paper's grid) with the 2/3 rule: K = 173
+    K = 173
+    M, PX = 2 * K + 1, ((K + 1 + 15) // 16) * 16
+    assert psdns.state_bytes(520, 1, 32) == 4 * M * M * PX * 8
+    # phase shift with the sphere 9 |k|^2 < 2 N^2: bounding cube K = 30 at N = 64, and one
+    # more buffer of the unshifted products (3 + S fields after the y forward pass)
+    K = 30
+    M, PX = 2 * K + 1, ((K + 1 + 15) // 16) * 16
+    assert psdns.state_bytes(64, 2, 64, dealias=psdns.DEALIAS_PHASE_SPHERE) == 5 * M * M * PX * 16
+    ws = psdns.workspace_bytes(64, 2, 64, dealias=psdns.DEALIAS_PHASE_SPHERE)
+    assert ws >= ((9 + 5) * 64 * M * PX + 12 * 64 * 64 * PX + 2 * 5 * M * M * PX) * 16
 
 
 def test_plan_device_bytes_cover_the_plan_tables():
@@ -58,9 +75,12 @@ def test_sizes_follow_the_compact_layout():
 def test_plan_create_validates_before_touching_the_device():
     L = psdns.lib()
     h = ctypes.c_void_p()
-    p = psdns.plan_params(96, 0, 64, 1)
+    p = psdns.plan_params(34, 0, 64, 1)
     assert L.psdns_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
-    assert b"power of two" in L.psdns_last_error()
+    assert b"prime factors" in L.psdns_last_error()
+    p = psdns.plan_params(64, 0, 64, 1, 5)
+    assert L.psdns_plan_create(ctypes.byref(p), ctypes.byref(h)) == -1
+    assert b"dealias" in L.psdns_last_error()
     assert L.psdns_plan_create(None, ctypes.byref(h)) == -1
     assert L.psdns_plan_destroy(None) == 0
     assert L.psdns_step(None, None, None, 0.1, 1, None) == -1

@@ -1,0 +1,193 @@
+"""The general kernels on the GPU against the oracle: grids whose N is not a power of two
+(mixed-radix transforms with radices 2..13, the paper's N = 520 = 2^3 5 13 of Sec. 3.1),
+and the paper's dealiasing (phase shift with spherical truncation, Sec. 2.3) at any N.
+
+FP64 bar 1e-12 relative L2, FP32 1e-5.  Workspaces start filled with NaN bytes, so a pass
+that reads an entry nobody wrote (e.g. modes of the bounding cube outside the sphere) fails.
+Sizes: N = 24 (2^3 3), 40 (2^3 5), 52 (2^2 13),
+56 (2^3 7), 44 (2^2 11) with the 2/3 rule; N = 16, 32, 64 and 48 with the phase shift;
+N = 520 for one right-hand side and one step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as ora
+from paper_2012_04838_amd import inputs, psdns
+from tests.gpu_helpers import (gpu_rhs, make_plan, poisoned_workspace, progress, rel_l2, set_params, to_numpy,
+                               torch_mod)
+
+pytestmark = pytest.mark.gpu
+
+
+def _prm(S, dealias="cube", **kw):
+    sc = (1.0, 0.7, 2.0)[:S]
+    g = ((0.0, 1.0, 0.0), (0.2, 1.0, -0.3), (1.0, 0.0, 0.0))[:S]
+    return ora.Params(nu=kw.pop("nu", 0.01), schmidt=sc, mean_grad=g, power=0.1, k_force=2.0, dealias=dealias, **kw)
+
+
+def _state(N, S, seed, dealias="cube", kp=4.0):
+    y = ora.init_field(N, S, seed, kp, 1.0, dealias=dealias)
+    if S:
+        K = ora.kmax_retained(N, dealias)
+        y[3:] = inputs.random_spectral_state(N, S, seed + 5, K, 4.0, 0.3) * ora.retained_mask(N, dealias)
+    return y
+
+
+def _run(N, S, prec, prm, y0, dt, nsteps, dealias):
+    torch = torch_mod()
+    plan = make_plan(N, S, prec, dealias=1 if dealias == "phase" else 0)
+    assert plan.info.general == 1
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), poisoned_workspace(plan)
+    plan.set_state(st, y0, 0)
+    plan.step(st, ws, dt, nsteps)
+    got = to_numpy(plan.get_state(st, 0))
+    info = plan.read_step_info(ws)[0]
+    torch.cuda.synchronize()
+    return got, info
+
+
+@pytest.mark.parametrize("N,S", [(24, 1), (40, 2), (52, 0), (56, 1), (44, 1)])
+def test_mixed_radix_rhs_matches_oracle(N, S):
+    x = inputs.random_spectral_state(N, 3 + S, 60 + N, ora.kmax_retained(N), 5.0)
+    prm = _prm(S)
+    ref = ora.rhs(x, prm)
+    got = gpu_rhs(x, prm, 64)
+    err = rel_l2(got, ref)
+    progress(f"[general] N={N} S={S} 2/3 rule rhs FP64 rel L2 {err:.2e}")
+    assert err < 1e-12
+    got32 = gpu_rhs(x, prm, 32)
+    assert rel_l2(got32, ref) < 1e-5, rel_l2(got32, ref)
+
+
+@pytest.mark.parametrize("N,S,prec", [(40, 1, 64), (52, 2, 64), (24, 1, 32)])
+def test_mixed_radix_cfl_steps_match_oracle(N, S, prec):
+    prm = _prm(S, nu=0.005)
+    y0 = _state(N, S, 7)
+    got, info = _run(N, S, prec, prm, y0, -0.5, 6, "cube")
+    ref, dts = ora.step(y0, prm, nsteps=6, cfl=0.5, return_dts=True)
+    err = rel_l2(got, ref)
+    progress(f"[general] N={N} S={S} FP{prec} 6 CFL steps rel L2 {err:.2e}")
+    assert err < (1e-12 if prec == 64 else 1e-5)
+    assert abs(info["t"] - sum(dts)) < (1e-12 if prec == 64 else 1e-6) * sum(dts)
+
+
+@pytest.mark.parametrize("N,S,prec", [(16, 1, 64), (32, 2, 64), (64, 1, 64), (48, 1, 64), (32, 1, 32)])
+def test_phase_shift_rhs_matches_oracle(N, S, prec):
+    K = ora.kmax_retained(N, "phase")
+    x = inputs.random_spectral_state(N, 3 + S, 80 + N, K, 5.0) * ora.retained_mask(N, "phase")
+    prm = _prm(S, "phase")
+    ref = ora.rhs(x, prm)
+    # the shifted evaluation matters at this size: the single-grid product differs
+    single = ora.rhs(x, ora.Params(**{**prm.__dict__, "dealias": "cube"}))
+    got = gpu_rhs(x, prm, prec)
+    err = rel_l2(got, ref)
+    progress(f"[general] N={N} S={S} phase shift rhs FP{prec} rel L2 {err:.2e} "
+             f"(2/3-rule rhs differs by {rel_l2(single, ref):.2e})")
+    assert err < (1e-12 if prec == 64 else 1e-5)
+
+
+@pytest.mark.parametrize("N,S,integrator", [(32, 1, "if"), (48, 2, "if"), (32, 1, "explicit")])
+def test_phase_shift_steps_match_oracle(N, S, integrator):
+    prm = _prm(S, "phase", nu=0.01, integrator=integrator)
+    y0 = _state(N, S, 9, "phase")
+    cfl = 0.5 if integrator == "if" else 0.2
+    got, info = _run(N, S, 64, prm, y0, -cfl, 5, "phase")
+    ref, dts = ora.step(y0, prm, nsteps=5, cfl=cfl, return_dts=True)
+    err = rel_l2(got, ref)
+    progress(f"[general] N={N} S={S} phase shift {integrator} 5 CFL steps rel L2 {err:.2e}")
+    assert err < 1e-12
+    assert abs(info["dt"] - dts[-1]) < 1e-12 * dts[-1]
+
+
+def test_phase_shift_initial_field_and_spectra_match_oracle():
+    torch = torch_mod()
+    N, S = 48, 1
+    prm = _prm(S, "phase")
+    plan = make_plan(N, S, 64, dealias=psdns.DEALIAS_PHASE_SPHERE)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), poisoned_workspace(plan)
+    plan.init_field(st, ws, 0, seed=4, k_peak=5.0, kinetic_energy=1.0)
+    got = to_numpy(plan.get_state(st, 0))
+    ref = ora.init_field(N, S, 4, 5.0, 1.0, dealias="phase")
+    assert rel_l2(got, ref) < 1e-14
+    # modes of the sphere outside the 2/3 cube are populated, none outside the sphere
+    assert np.any(got[:, ora.retained_mask(N, "phase") & ~ora.retained_mask(N)] != 0)
+    assert np.all(got[:, ~ora.retained_mask(N, "phase")] == 0)
+    y = _state(N, S, 11, "phase")
+    plan.set_state(st, y, 0)
+    sp = plan.spectra(st, ws)[0]
+    torch.cuda.synchronize()
+    rs = ora.spectra(y, prm)
+    ph = ora.physical_stats(y)
+    assert len(sp["E"]) == len(rs["E"]) == ora.n_shells(N, "phase")
+    np.testing.assert_allclose(sp["E"], rs["E"], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(sp["E_phi"], rs["E_phi"], rtol=1e-12, atol=1e-15)
+    assert abs(sp["eps"] - rs["eps"]) <= 1e-12 * rs["eps"]
+    np.testing.assert_allclose(sp["vgt_skew"], ph["vgt_skew"], rtol=1e-9)
+    np.testing.assert_allclose(sp["phi2_skew"], ph["phi2_skew"], rtol=1e-9)
+    assert abs(sp["max_abs_u_sum"] - ph["max_abs_u_sum"]) <= 1e-13 * ph["max_abs_u_sum"]
+
+
+def test_general_plans_step_by_graph_replay_and_report_pressure_unsupported():
+    torch = torch_mod()
+    N, S, dt = 40, 1, 0.004
+    prm = _prm(S, "phase")
+    y0 = _state(N, S, 13, "phase")
+    plan = make_plan(N, S, 64, dealias=psdns.DEALIAS_PHASE_SPHERE)
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), poisoned_workspace(plan)
+    plan.set_state(st, y0, 0)
+    stream = torch.cuda.Stream()
+    plan.set_graph(True)
+    with torch.cuda.stream(stream):
+        plan.step(st, ws, dt, 2)
+        plan.step(st, ws, dt, 2)
+    stream.synchronize()
+    plan.set_graph(False)
+    got = to_numpy(plan.get_state(st, 0))
+    assert rel_l2(got, ora.step(y0, prm, dt, 4)) < 1e-12
+    with pytest.raises(psdns.PsdnsError, match="general kernels"):
+        plan.pressure(st, ws)
+    torch.cuda.synchronize()
+
+
+def test_alvelius_forcing_with_phase_shift_matches_oracle():
+    N, S = 32, 1
+    prm = _prm(S, "phase", forcing_mode="alvelius", stoch_seed=5)
+    prm.power = 0.3
+    y0 = _state(N, S, 15, "phase", kp=3.0)
+    got, _ = _run(N, S, 64, prm, y0, -0.5, 4, "phase")
+    ref = ora.step(y0, prm, None, 4, cfl=0.5, stoch_state={"b": {}, "n": 0})
+    assert rel_l2(got, ref) < 1e-12, rel_l2(got, ref)
+
+
+@pytest.mark.timeout(900)
+def test_paper_grid_520_rhs_and_step_match_oracle():
+    """N = 520 = 2^3 5 13 (Table 2 of the paper), one scalar: the right-hand side in FP64
+    against the oracle, and one fixed step in FP32 against the oracle's FP64 step."""
+    torch = torch_mod()
+    N, S = 520, 1
+    prm = _prm(S, nu=8e-4)
+    progress("[general] 520^3 oracle initial field")
+    y0 = ora.init_field(N, S, 2, 8.0, 1.0)
+    y0[3:] = inputs.random_spectral_state(N, S, 3, ora.kmax_retained(N), 8.0, 0.3)
+    progress("[general] 520^3 GPU right-hand side (FP64)")
+    got = gpu_rhs(y0, prm, 64)
+    torch.cuda.empty_cache()
+    progress("[general] 520^3 oracle right-hand side")
+    ref = ora.rhs(y0, prm)
+    err = rel_l2(got, ref)
+    del got, ref
+    progress(f"[general] 520^3 rhs FP64 rel L2 {err:.2e}")
+    assert err < 1e-12
+    dt = ora.cfl_dt(y0, 0.5)
+    got, info = _run(N, S, 32, prm, y0, dt, 1, "cube")
+    torch.cuda.empty_cache()
+    progress("[general] 520^3 oracle step")
+    ref = ora.step(y0, prm, dt, 1)
+    err = rel_l2(got, ref)
+    progress(f"[general] 520^3 one step FP32 vs oracle rel L2 {err:.2e}")
+    assert err < 1e-5 and info["flags"] == 0
