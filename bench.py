@@ -37,14 +37,16 @@ GRAD = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
 
 # HBM bytes per launch of the 512^3 S=2 FP32 kernels from rocprofv3 --pmc FETCH_SIZE and
 # WRITE_SIZE runs, each counter scaled by what it reads for a plain 1e9-byte device copy in
-# the same process (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  `src` is the digest of the kernel
+# the same process (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0; the library's own streaming copy and
+# the runtime's copy kernel read the same).  `src` is the digest of the kernel
 # sources and build flags they were taken with; a different digest reports null.
 MEASURED_TRAFFIC = {
-    "src": "7f5d7b0919364429",
+    "src": "68abc67de7c4929f",
     "workload": (512, 2, 32),
-    "schedules": (0, 5, 6),  # measured separately; every pass moved the same bytes in each
-    "bytes": {"x_pass": 6233.6e6, "y_inverse": 6542.0e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
-              "z_forward_update_inverse": 5502.6e6},
+    "schedules": (6,),
+    # z_forward_update_inverse: mean over the four stage instances of the fused pass
+    "bytes": {"x_pass": 6233.0e6, "y_inverse": 6542.0e6, "y_forward": 3047.5e6, "z_inverse": 2981.5e6,
+              "z_forward_update": 2848.8e6, "z_forward_update_inverse": 5420.3e6},
 }
 
 
