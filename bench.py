@@ -200,7 +200,7 @@ def copy_reference(gbytes: float, reps: int = 5):
     ms = timed(lambda: b.copy_(a))
     out = {"bytes_read": n, "bytes_written": n, "ms": ms, "GBs": 2 * n / (ms * 1e-3) / 1e9}
     kern = {}
-    for blocks in (1024, 2048, 4096, 8192, 16384):
+    for blocks in (1024, 4096, 16384, 65536, 262144):
         kms = timed(lambda: psdns.stream_copy(b.view(torch.uint8), a.view(torch.uint8), blocks))
         kern[str(blocks)] = 2 * n / (kms * 1e-3) / 1e9
     assert torch.equal(a, b)

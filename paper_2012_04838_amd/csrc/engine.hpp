@@ -378,7 +378,8 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       uint32_t vo, so;
-      v[m] = (valid && compact_at<N, TT>(m, j, voff, rsb, vo, so)) ? bload(b, vo, so) : czero<T>();
+      v[m] = (valid && compact_at<N, TT>(m, j, voff, rsb, vo, so)) ? bload<T, kPolicyStream>(b, vo, so)
+                                                                     : czero<T>();
     }
   };
   auto store = [&](int f, const cpx<T> (&v)[E]) {
@@ -845,7 +846,7 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   auto load = [&](int f, cpx<T> (&v)[E]) {
     const Buf<T> b = make_buf<T>(bplane + (long long)f * g.b_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
+    for (int m = 0; m < E; ++m) v[m] = valid ? bload<T, kPolicyStream>(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
   };
   cpx<T> a[E], nx[E];
   constexpr bool PF = col_prefetch<T, E, C::COL_THREADS>();

@@ -19,6 +19,13 @@ namespace psdns {
 // Word 3 of a gfx9 buffer descriptor for raw dword access (data format 32, no swizzle).
 constexpr int kBufWord3 = 0x00020000;
 
+// Cache policy of the buffer accesses (the instructions' nt bit).  Every pass writes each
+// output element once and the next pass reads it from HBM, so stores are streamed
+// (non-temporal); loads are streamed in the passes where that measured faster (the y
+// passes), and left cached where it did not (the x pass, the z passes).
+constexpr int kPolicyCached = 0;
+constexpr int kPolicyStream = 2;
+
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -37,13 +44,15 @@ __device__ __forceinline__ Buf<T> make_buf(const cpx<T>* base) {
 
 // Loads go through a two-lane vector of T: taking the lanes of the raw dword vector
 // one by one lets the optimiser split the access into single-dword loads.
-template <typename T>
+template <typename T, int POLICY = kPolicyCached>
 __device__ __forceinline__ cpx<T> bload(const Buf<T>& b, uint32_t voff, uint32_t soff) {
   if constexpr (sizeof(T) == 4) {
-    const f32x2_t v = __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+    const f32x2_t v =
+        __builtin_bit_cast(f32x2_t, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, POLICY));
     return {v.x, v.y};
   } else {
-    const f64x2_t v = __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)soff, 0));
+    const f64x2_t v =
+        __builtin_bit_cast(f64x2_t, __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)soff, POLICY));
     return {v.x, v.y};
   }
 }
@@ -57,10 +66,11 @@ template <typename T>
 __device__ __forceinline__ void bstore(const Buf<T>& b, uint32_t voff, uint32_t soff, cpx<T> v) {
   if constexpr (sizeof(T) == 4) {
     const f32x2_t w = {v.x, v.y};
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, w), b.r, (int)voff, (int)soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, w), b.r, (int)voff, (int)soff, kPolicyStream);
   } else {
     const f64x2_t w = {v.x, v.y};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)(voff + soff), 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)(voff + soff), 0,
+                                           kPolicyStream);
   }
 }
 
