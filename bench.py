@@ -65,12 +65,17 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, n: int, s: int, prec: int, schedule: int):
+# pass of each timed kernel (the schedule index that applies to it)
+KERNEL_PASS = {"z_inverse": 0, "y_inverse": 1, "x_pass": 2, "y_forward": 3, "z_forward_update": 4,
+               "z_forward_update_inverse": 4}
+
+
+def measured_traffic(kernel: str, n: int, s: int, prec: int, pass_schedules):
     """Counter bytes per launch of a kernel, if they were taken on these sources, this
-    workload and this schedule (spills and tile shapes change the traffic)."""
+    workload and the schedule its pass runs in (spills and tile shapes change the traffic)."""
     t = MEASURED_TRAFFIC
-    if (t["workload"] != (n, s, prec) or schedule not in t["schedules"] or kernel not in t["bytes"]
-            or t["src"] != kernel_source_digest()):
+    if (t["workload"] != (n, s, prec) or kernel not in t["bytes"] or kernel not in KERNEL_PASS
+            or pass_schedules[KERNEL_PASS[kernel]] not in t["schedules"] or t["src"] != kernel_source_digest()):
         return None
     return t["bytes"][kernel]
 
@@ -131,11 +136,16 @@ def run_gpu(n, s, prec, steps, warmup, seed=3, tune_reps=3, schedule=-1, nu=None
     sched = None
     if schedule >= 0:
         plan.set_schedule(schedule)
-        sched = {"chosen": schedule, "ms_per_stage": None, "chosen_desc": plan.schedule_info(schedule)}
+        sched = {"chosen": [schedule] * psdns.NUM_PASSES, "ms_per_stage": None}
     elif tune_reps > 0:
-        # autotuner (outside the timed region): every compiled schedule on this state
+        # autotuner (outside the timed region): every compiled schedule as a whole on this
+        # state, then the fastest schedule of each pass (the one the timed steps run)
         best, ms_each = plan.tune(st, ws, tune_reps)
-        sched = {"chosen": best, "ms_per_stage": ms_each, "chosen_desc": plan.schedule_info(best)}
+        chosen, table = plan.tune_passes(st, ws, tune_reps)
+        sched = {"chosen": chosen, "best_whole_schedule": best, "ms_per_stage": ms_each,
+                 "ms_per_pass": {psdns.PASS_NAMES[p]: [row[p] for row in table] for p in range(psdns.NUM_PASSES)}}
+    if sched is not None:
+        sched["chosen_desc"] = {psdns.PASS_NAMES[p]: plan.schedule_info(v) for p, v in enumerate(plan.pass_schedules)}
     stream = torch.cuda.Stream()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -361,7 +371,7 @@ def main():
     launches, tot = tim[dom]
     avg_ms = tot / max(launches, 1)
     achieved = kb[dom] / (avg_ms * 1e-3) / 1e9
-    chosen = r32["schedule"]["chosen"] if r32["schedule"] else 0
+    chosen = r32["schedule"]["chosen"] if r32["schedule"] else [0] * 5
     traffic = measured_traffic(dom, n, s, 32, chosen)
     step_traffic = None
     if all(measured_traffic(k, n, s, 32, chosen) is not None

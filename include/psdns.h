@@ -180,10 +180,11 @@ typedef struct {
   int64_t state_bytes, workspace_bytes;
   int32_t elems_col, elems_x; /* FFT elements per thread of the column and x passes (schedule in use) */
   int32_t n_schedules;        /* step schedules compiled for this size (psdns_set_schedule) */
-  int32_t schedule;           /* schedule in use */
+  int32_t schedule;           /* schedule in use, or -1 when the passes run in different ones */
   int64_t plan_bytes;         /* device bytes of the plan's own tables (psdns_plan_device_bytes) */
   int32_t dealias;            /* PSDNS_DEALIAS_* of the plan */
   int32_t general;            /* 1 when the plan runs the general (mixed-radix) kernels */
+  int32_t pass_schedules[5];  /* schedule of each pass, PSDNS_PASS_* order */
 } psdns_plan_info;
 
 /* Bytes of the compact spectral state y for all slots (caller allocates). 0 on invalid params. */
@@ -299,6 +300,29 @@ psdns_status psdns_set_schedule(psdns_plan* plan, int32_t index);
  * records untouched.  Synchronises the stream. */
 psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
                         int32_t* best, void* hip_stream);
+
+/* The passes of one right-hand-side evaluation (Sec. 2.2: the inverse transforms of Eq. (5)
+ * axis by axis, the products, the forward transforms and the update).  Every schedule reads
+ * and writes the same buffers in the same layouts, so each pass may run in its own. */
+#define PSDNS_PASS_Z_INVERSE 0 /* z inverse of the stage input (first stage of a call)          */
+#define PSDNS_PASS_Y_INVERSE 1
+#define PSDNS_PASS_X 2         /* x inverse, the products and the CFL maximum, x forward        */
+#define PSDNS_PASS_Y_FORWARD 3
+#define PSDNS_PASS_Z_FORWARD 4 /* z forward, projection, forcing, stage update, next z inverse */
+#define PSDNS_NUM_PASSES 5
+/* Select the schedule of each pass: sched[PSDNS_NUM_PASSES] (host array), each in
+ * [0, n_schedules), else PSDNS_E_INVAL.  psdns_set_schedule(i) sets every pass to i.  The
+ * results are those of any schedule (the same transforms; only the association order of the
+ * butterflies differs).  A captured step graph is dropped and re-captured. */
+psdns_status psdns_set_pass_schedules(psdns_plan* plan, const int32_t* sched);
+/* Autotuner per pass: times the passes of `reps` RK stages with each schedule (the trial of
+ * psdns_tune, and the standalone z inverse) with an event pair around every kernel, selects
+ * the fastest schedule of each pass and returns the mean milliseconds of every pass and
+ * schedule in host array ms_out[n_schedules * PSDNS_NUM_PASSES] (schedule-major; may be
+ * NULL) and the selection in best[PSDNS_NUM_PASSES] (may be NULL).  Leaves `state` and the
+ * step records untouched.  Synchronises the stream. */
+psdns_status psdns_tune_passes(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
+                               int32_t* best, void* hip_stream);
 
 /* Copy the per-slot stepping records to host memory `out[batch]` (synchronises the stream). */
 psdns_status psdns_read_step_info(psdns_plan* plan, const void* ws, psdns_step_info* out, void* hip_stream);

@@ -260,7 +260,8 @@ struct psdns_plan {
   const void* graph_ws = nullptr;
   double graph_dt = 0.0;
   bool graph_hold = false;  // captured with the hold forcing's step structure
-  int sched = 0;  // step schedule in use (psdns_set_schedule / psdns_tune)
+  bool graph_expl = false;  // captured with the unfused stages of an explicit-integrator slot
+  int psched[kNumPasses] = {0, 0, 0, 0, 0};  // schedule of each pass (psdns_set_pass_schedules)
 };
 
 namespace {
@@ -268,6 +269,7 @@ namespace {
 Ctx make_ctx(psdns_plan* plan, void* ws) {
   Ctx c{};
   c.g = plan->L.g;
+  for (int p = 0; p < kNumPasses; ++p) c.psched[p] = plan->psched[p];
   c.tw = plan->tw;
   c.slots = plan->slots_dev;
   char* w = static_cast<char*>(ws);
@@ -329,6 +331,19 @@ psdns_status check_plan(const psdns_plan* plan) {
   return PSDNS_OK;
 }
 
+// The stage launcher: each pass in the schedule Ctx::psched names (plans with one
+// schedule only: that one).
+RhsStageFn stage_fn(const psdns_plan* plan) {
+  return plan->ops.rhs_mixed ? plan->ops.rhs_mixed : plan->ops.sched[0].rhs_stage;
+}
+
+// Whether an active slot uses the explicit integrator (the fused passes do not run it).
+bool any_explicit(const psdns_plan* plan) {
+  for (int i = 0; i < plan->p.batch; ++i)
+    if (plan->slots_host[i].active && plan->slots_host[i].integrator == PSDNS_INTEGRATOR_EXPLICIT) return true;
+  return false;
+}
+
 // The steps of psdns_step on workspace ws (graph replay when allowed and enabled).
 psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int nsteps, hipStream_t s,
                        bool allow_graph, Timer* timer) {
@@ -342,19 +357,23 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
   bool hold = false;
   for (int i = 0; i < plan->p.batch; ++i)
     hold = hold || (plan->slots_host[i].active && plan->slots_host[i].forcing == PSDNS_FORCING_HOLD);
+  // The fused passes update integrating-factor slots only; a batch with an explicit-
+  // integrator slot runs every stage unfused (its own z inverse, then the update).
+  const bool expl = any_explicit(plan);
   auto one_step = [&](const Ctx& cx, bool first, bool last) {
     for (int stage = 0; stage < 4; ++stage) {
       const void* sin = stage == 0 ? state : cx.ystage;
       int fl = kStageFuse;
       if ((first || hold) && stage == 0) fl |= kStageZinv;
       if ((last || hold) && stage == 3) fl &= ~kStageFuse;
-      plan->ops.sched[plan->sched].rhs_stage(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
+      if (expl) fl = kStageZinv;
+      stage_fn(plan)(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
     }
     if (hold) plan->ops.band_hold(cx, state, s);
   };
   if (allow_graph && s != nullptr && nsteps > 0) {
     if (!plan->graph_exec || plan->graph_state != state || plan->graph_ws != ws || plan->graph_dt != dt ||
-        plan->graph_hold != hold) {
+        plan->graph_hold != hold || plan->graph_expl != expl) {
       if (plan->graph_exec) {
         HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
         plan->graph_exec = nullptr;
@@ -380,10 +399,11 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
       plan->graph_state = state;
       plan->graph_ws = ws;
       plan->graph_hold = hold;
+      plan->graph_expl = expl;
       plan->graph_dt = dt;
     }
     // the captured step expects the z inverse of y_n: run it once, then replay
-    plan->ops.sched[plan->sched].rhs_stage(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
+    stage_fn(plan)(c, state, state, 0, nullptr, 0, dt, kStageZinv | kStagePrologue, s);
     HIP_TRY(hipGetLastError());
     for (int n = 0; n < nsteps; ++n) {
       if (timer) timer->begin(KID_STEP, s);
@@ -587,10 +607,14 @@ psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
   out->plan_bytes = (int64_t)plan_table_bytes(&plan->p);
   out->dealias = plan->p.dealias;
   out->general = general_plan(&plan->p) ? 1 : 0;
-  out->elems_col = plan->ops.sched[plan->sched].ec;
-  out->elems_x = plan->ops.sched[plan->sched].ex;
+  out->elems_col = plan->ops.sched[plan->psched[kPassYInverse]].ec;
+  out->elems_x = plan->ops.sched[plan->psched[kPassX]].ex;
   out->n_schedules = plan->ops.nsched;
-  out->schedule = plan->sched;
+  out->schedule = plan->psched[0];
+  for (int p = 0; p < kNumPasses; ++p) {
+    out->pass_schedules[p] = plan->psched[p];
+    if (plan->psched[p] != plan->psched[0]) out->schedule = -1;
+  }
   return PSDNS_OK;
 }
 
@@ -610,17 +634,30 @@ psdns_status psdns_get_schedule_info(const psdns_plan* plan, int32_t index, psdn
   return PSDNS_OK;
 }
 
+psdns_status psdns_set_pass_schedules(psdns_plan* plan, const int32_t* sched) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!sched) return fail(PSDNS_E_INVAL, "sched is NULL");
+  bool same = true;
+  for (int p = 0; p < kNumPasses; ++p) {
+    if (sched[p] < 0 || sched[p] >= plan->ops.nsched)
+      return fail(PSDNS_E_INVAL, "schedule index out of range [0, " + std::to_string(plan->ops.nsched) + ")");
+    same = same && sched[p] == plan->psched[p];
+  }
+  if (!same && plan->graph_exec) {
+    // a captured step holds the kernels of the old schedules
+    HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
+    plan->graph_exec = nullptr;
+  }
+  for (int p = 0; p < kNumPasses; ++p) plan->psched[p] = sched[p];
+  return PSDNS_OK;
+}
+
 psdns_status psdns_set_schedule(psdns_plan* plan, int32_t index) {
   if (psdns_status s = check_plan(plan)) return s;
   if (index < 0 || index >= plan->ops.nsched)
     return fail(PSDNS_E_INVAL, "schedule index out of range [0, " + std::to_string(plan->ops.nsched) + ")");
-  if (index != plan->sched && plan->graph_exec) {
-    // a captured step holds the kernels of the old schedule
-    HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
-    plan->graph_exec = nullptr;
-  }
-  plan->sched = index;
-  return PSDNS_OK;
+  const int32_t all[kNumPasses] = {index, index, index, index, index};
+  return psdns_set_pass_schedules(plan, all);
 }
 
 psdns_status psdns_set_slot(psdns_plan* plan, int32_t slot, const psdns_slot_params* prm, int32_t active) {
@@ -717,7 +754,7 @@ psdns_status psdns_rhs(psdns_plan* plan, const void* state, void* out, void* ws,
   if (state == out) return fail(PSDNS_E_INVAL, "out must not alias state");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   Ctx c = make_ctx(plan, ws);
-  plan->ops.sched[plan->sched].rhs_stage(c, const_cast<void*>(state), state, -1, out, 0, 0.0, kStageZinv, s);
+  stage_fn(plan)(c, const_cast<void*>(state), state, -1, out, 0, 0.0, kStageZinv, s);
   HIP_TRY(hipGetLastError());
   return PSDNS_OK;
 }
@@ -746,9 +783,10 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
     // fused z pass); it reads the state and writes only workspace buffers (accumulator,
     // stage input on the band, transform buffers), all of which a step rebuilds.
     void* st = const_cast<void*>(state);
-    f(c, st, c.ystage, 1, nullptr, 0, 0.0, kStageFuse, s);
+    const int fl = any_explicit(plan) ? kStageZinv : kStageFuse;  // the stage a step would run
+    f(c, st, c.ystage, 1, nullptr, 0, 0.0, fl, s);
     err = hipEventRecord(e0, s);
-    for (int r = 0; r < reps && err == hipSuccess; ++r) f(c, st, c.ystage, 1, nullptr, 0, 0.0, kStageFuse, s);
+    for (int r = 0; r < reps && err == hipSuccess; ++r) f(c, st, c.ystage, 1, nullptr, 0, 0.0, fl, s);
     if (err == hipSuccess) err = hipEventRecord(e1, s);
     if (err == hipSuccess) err = hipEventSynchronize(e1);
     float t = 0.f;
@@ -764,6 +802,61 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
     for (int i = 0; i < plan->ops.nsched; ++i) ms_out[i] = ms[i];
   if (best) *best = b;
   return psdns_set_schedule(plan, b);
+}
+
+psdns_status psdns_tune_passes(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
+                               int32_t* best, void* hip_stream) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (!state || !ws) return fail(PSDNS_E_INVAL, "state and ws must be device pointers");
+  if (reps < 1 || reps > 1000) return fail(PSDNS_E_INVAL, "reps must be in [1, 1000]");
+  hipStream_t s = static_cast<hipStream_t>(hip_stream);
+  const int ns = plan->ops.nsched;
+  const bool expl = any_explicit(plan);
+  // kernel record of each pass in the stage a step runs
+  const int kid[kNumPasses] = {KID_ZINV, KID_YINV, KID_XPASS, KID_YFWD, expl ? KID_ZFWD : KID_ZFWDI};
+  std::vector<double> ms((size_t)ns * kNumPasses, 0.0);
+  for (int i = 0; i < ns; ++i) {
+    Ctx c = make_ctx(plan, ws);
+    for (int p = 0; p < kNumPasses; ++p) c.psched[p] = i;
+    EventTimer t;
+    void* st = const_cast<void*>(state);
+    const int fl = expl ? kStageZinv : kStageFuse;
+    // untimed trial, then reps timed ones of the standalone z inverse (of the state) and
+    // of the steady stage (the trial of psdns_tune); workspace buffers only
+    c.timer = nullptr;
+    stage_fn(plan)(c, st, st, 0, nullptr, 0, 0.0, kStageZinv | kStagePrologue, s);
+    stage_fn(plan)(c, st, c.ystage, 1, nullptr, 0, 0.0, fl, s);
+    c.timer = &t;
+    for (int r = 0; r < reps; ++r) {
+      stage_fn(plan)(c, st, st, 0, nullptr, 0, 0.0, kStageZinv | kStagePrologue, s);
+      stage_fn(plan)(c, st, c.ystage, 1, nullptr, 0, 0.0, fl, s);
+    }
+    HIP_TRY(hipGetLastError());
+    if (t.err != hipSuccess) return hip_fail(t.err, "hipEventCreate");
+    double sum[KID_COUNT] = {0};
+    int cnt[KID_COUNT] = {0};
+    for (auto& r : t.recs) {
+      if (!(r.a && r.b && r.closed)) continue;
+      HIP_TRY(hipEventSynchronize(r.b));
+      float e = 0.f;
+      HIP_TRY(hipEventElapsedTime(&e, r.a, r.b));
+      sum[r.kid] += e;
+      cnt[r.kid] += 1;
+    }
+    for (int p = 0; p < kNumPasses; ++p)
+      ms[(size_t)i * kNumPasses + p] = cnt[kid[p]] ? sum[kid[p]] / cnt[kid[p]] : 0.0;
+  }
+  int32_t pick[kNumPasses];
+  for (int p = 0; p < kNumPasses; ++p) {
+    pick[p] = 0;
+    for (int i = 1; i < ns; ++i)
+      if (ms[(size_t)i * kNumPasses + p] < ms[(size_t)pick[p] * kNumPasses + p]) pick[p] = i;
+  }
+  if (ms_out)
+    for (size_t k = 0; k < ms.size(); ++k) ms_out[k] = ms[k];
+  if (best)
+    for (int p = 0; p < kNumPasses; ++p) best[p] = pick[p];
+  return psdns_set_pass_schedules(plan, pick);
 }
 
 psdns_status psdns_step(psdns_plan* plan, void* state, void* ws, double dt, int32_t nsteps, void* hip_stream) {

@@ -118,6 +118,15 @@ struct Timer {
   virtual ~Timer() {}
 };
 
+// The passes of a right-hand-side evaluation, each of which may run in its own schedule
+// (index order of psdns_set_pass_schedules).
+constexpr int kPassZInverse = 0;  // z inverse of the stage input (first stage of a call)
+constexpr int kPassYInverse = 1;
+constexpr int kPassX = 2;         // x inverse, products, x forward
+constexpr int kPassYForward = 3;
+constexpr int kPassZForward = 4;  // z forward, projection, forcing, stage update (and next z inverse)
+constexpr int kNumPasses = 5;
+
 struct Ctx {
   Geom g;
   const void* tw;          // w_N^m = exp(-2 pi i m/N), m = 0..N-1, in the plan precision
@@ -135,6 +144,7 @@ struct Ctx {
   int nbm;                 // blocks of the moments kernels per slot
   int spectra_rec;         // doubles per slot of the spectra record
   Timer* timer;            // may be null
+  int psched[kNumPasses];  // schedule of each pass (Ops::rhs_mixed)
 };
 
 // One evaluation of the nonlinear right-hand side at stage_in followed by the stage
@@ -157,6 +167,8 @@ struct StepSched {
 struct Ops {
   int nsched;
   StepSched sched[kMaxSched];
+  // the stage with each pass in the schedule Ctx::psched names (null: sched[0] only)
+  RhsStageFn rhs_mixed;
   void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, int spectrum, double energy,
                      hipStream_t);
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);

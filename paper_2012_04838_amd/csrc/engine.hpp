@@ -945,6 +945,48 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long fof
   return nxt;
 }
 
+// The integrating-factor update split into its loads and its arithmetic and stores, so
+// that a column issues the state loads of all its elements before any of its stores.
+// Loads and stores share one completion counter, so a load waited for after a store
+// also waits for that store; loading first keeps the stores out of those waits.
+template <typename T>
+struct RkIn {
+  cpx<T> y, accv;  // y_n (stages 0-2) and the accumulator (stages 1-3)
+};
+template <int STG, typename T>
+__device__ __forceinline__ RkIn<T> rk_load(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so) {
+  static_assert(STG >= 0 && STG <= 3, "integrating-factor stages only");
+  RkIn<T> r{czero<T>(), czero<T>()};
+  if constexpr (STG < 3) r.y = bload(make_buf<T>(a.yn + foff), vo, so);
+  if constexpr (STG > 0) r.accv = bload(make_buf<T>(a.acc + foff), vo, so);
+  return r;
+}
+// The stage formulas of rk_update (integrating factor) on values from rk_load.
+template <int STG, typename T>
+__device__ __forceinline__ cpx<T> rk_apply(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so,
+                                           const RkIn<T>& in, cpx<T> F, double ehd, double h, bool write_ys) {
+  const Buf<T> yn = make_buf<T>(a.yn + foff), acc = make_buf<T>(a.acc + foff);
+  const T eh = T(ehd), e1 = T(ehd * ehd), th = T(h);
+  const cpx<T> y = in.y;
+  cpx<T> nxt;
+  if constexpr (STG == 0) {
+    bstore(acc, vo, so, e1 * (y + (th / T(6)) * F));
+    nxt = eh * (y + (th / T(2)) * F);
+  } else if constexpr (STG == 1) {
+    bstore(acc, vo, so, in.accv + ((th / T(3)) * eh) * F);
+    nxt = eh * y + (th / T(2)) * F;
+  } else if constexpr (STG == 2) {
+    bstore(acc, vo, so, in.accv + ((th / T(3)) * eh) * F);
+    nxt = e1 * y + (th * eh) * F;
+  } else {
+    nxt = in.accv + (th / T(6)) * F;
+    bstore(yn, vo, so, nxt);
+    return nxt;
+  }
+  if (write_ys) bstore(make_buf<T>(a.ys + foff), vo, so, nxt);
+  return nxt;
+}
+
 // FUSE: after the update, the next stage input (held in registers, in the same
 // strided kz ownership the inverse transform starts from) is transformed back
 // along z and written as the A fields of the next evaluation (the work of
@@ -986,6 +1028,12 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   const bool expl = sp.integrator == PSDNS_INTEGRATOR_EXPLICIT;
   const int stage = STG >= -1 ? STG : sa.stage;
   const bool factors = !expl && stage >= 0;
+  // The fused instances update integrating-factor slots only: the host runs a batch with
+  // an explicit-integrator slot through the unfused pass.  Should such a slot reach a
+  // fused instance, its stage input becomes non-finite, which its step record flags.
+  auto guard = [&](cpx<T> v) {
+    return (FUSE && expl) ? cpx<T>{T(__builtin_nan("")), T(__builtin_nan(""))} : v;
+  };
   if (factors) {
     // diffusivity of class cls: velocity (sp.diff[0]) or scalar cls - 1 (sp.diff[2 + cls])
     for (int i = threadIdx.x; i < (1 + g.S) * (K + 1); i += blockDim.x) {
@@ -1062,16 +1110,42 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     const double dif = sp.diff[3 + s];
     const double exy = exy_of(1 + s);
     const long long foff = sslot + (long long)(3 + s) * g.st_field;
+    if constexpr (FUSE) {
+      // two batches of E/2 elements: their loads, then their arithmetic and stores
+      constexpr int HB = E / 2;
+      static_for<0, 2>([&](auto hc) {
+        constexpr int h0 = decltype(hc)::value * HB;
+        RkIn<T> in[HB];
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      uint32_t vo, so;
-      cpx<T> nxt = czero<T>();
-      if (state_at(m, vo, so)) {
-        const double k2m_ = k2m(m);
-        const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
-        nxt = rk_update<STG>(sa, foff, vo, so, F, dif * k2m_, efac(1 + s, exy, m), h, !FUSE || expl, expl);
+        for (int q = 0; q < HB; ++q) {
+          uint32_t vo, so;
+          if (state_at(h0 + q, vo, so)) in[q] = rk_load<STG>(sa, foff, vo, so);
+        }
+#pragma unroll
+        for (int q = 0; q < HB; ++q) {
+          const int m = h0 + q;
+          uint32_t vo, so;
+          cpx<T> nxt = czero<T>();
+          if (state_at(m, vo, so)) {
+            const cpx<T> F = k2m(m) == 0.0 ? czero<T>() : czero<T>() - a[m];
+            nxt = rk_apply<STG>(sa, foff, vo, so, in[q], F, efac(1 + s, exy, m), h, false);
+          }
+          a[m] = guard(nxt);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      });
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        uint32_t vo, so;
+        cpx<T> nxt = czero<T>();
+        if (state_at(m, vo, so)) {
+          const double k2m_ = k2m(m);
+          const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
+          nxt = rk_update<STG>(sa, foff, vo, so, F, dif * k2m_, efac(1 + s, exy, m), h, true, expl);
+        }
+        a[m] = nxt;
       }
-      a[m] = nxt;
     }
     if constexpr (FUSE) inverse_out(a, 5 + 2 * s, 6 + 2 * s);
   }
@@ -1116,42 +1190,99 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     const double nu = sp.nu;
     const double exy = exy_of(0);
     const long long f1 = sslot, f2 = sslot + g.st_field, f3 = sslot + 2 * g.st_field;
+    if constexpr (FUSE) {
+      // P(k) c_hat + A 1_band u_hat in place of c1..c3 (before any store of the velocity
+      // update), then the update one component at a time, each in two batches of E/2
+      // elements (their loads, then their arithmetic and stores)
 #pragma unroll
-    for (int m = 0; m < E; ++m) {
-      uint32_t vo, so;
-      cpx<T> n1 = czero<T>(), n2 = czero<T>(), n3 = czero<T>();
-      if (state_at(m, vo, so)) {
+      for (int m = 0; m < E; ++m) {
+        uint32_t vo, so;
+        if (!state_at(m, vo, so)) continue;
         const double k2m_ = k2m(m);
-        const int n = j + TT * m;
-        const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
-        cpx<T> F1, F2, F3;
-        const bool band = k2m_ > 0.0 && k2m_ <= sp.kf2;
         if (k2m_ == 0.0) {
-          F1 = F2 = F3 = czero<T>();
-        } else {
-          const T ik2 = T(1) / T(k2m_);  // k2m_ is an integer below 2^24: exact in T
-          const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
-          F1 = c1[m] - (kxt * ik2) * kdc;
-          F2 = c2[m] - (kyt * ik2) * kdc;
-          F3 = c3[m] - (kzt * ik2) * kdc;
-          if (A != 0.0 && band) {
-            const T At = T(A);
-            F1 = F1 + At * bload(make_buf<T>(sa.sin + f1), vo, so);
-            F2 = F2 + At * bload(make_buf<T>(sa.sin + f2), vo, so);
-            F3 = F3 + At * bload(make_buf<T>(sa.sin + f3), vo, so);
-          }
+          c1[m] = c2[m] = c3[m] = czero<T>();
+          continue;
         }
-        const double lk2 = nu * k2m_;
-        // the next stage reads y_stage on the band (forcing) and, explicit, everywhere
-        const bool wys = !FUSE || band || expl;
-        const double ef = efac(0, exy, m);
-        n1 = rk_update<STG>(sa, f1, vo, so, F1, lk2, ef, h, wys, expl);
-        n2 = rk_update<STG>(sa, f2, vo, so, F2, lk2, ef, h, wys, expl);
-        n3 = rk_update<STG>(sa, f3, vo, so, F3, lk2, ef, h, wys, expl);
+        const T kzt = T(wave_of(j + TT * m, N)), kyt = T(ky), kxt = T(kx);
+        const T ik2 = T(1) / T(k2m_);  // k2m_ is an integer below 2^24: exact in T
+        const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
+        c1[m] = c1[m] - (kxt * ik2) * kdc;
+        c2[m] = c2[m] - (kyt * ik2) * kdc;
+        c3[m] = c3[m] - (kzt * ik2) * kdc;
+        if (A != 0.0 && k2m_ <= sp.kf2) {
+          const T At = T(A);
+          c1[m] = c1[m] + At * bload(make_buf<T>(sa.sin + f1), vo, so);
+          c2[m] = c2[m] + At * bload(make_buf<T>(sa.sin + f2), vo, so);
+          c3[m] = c3[m] + At * bload(make_buf<T>(sa.sin + f3), vo, so);
+        }
       }
-      c1[m] = n1;
-      c2[m] = n2;
-      c3[m] = n3;
+      auto component = [&](cpx<T> (&cv)[E], long long fo) {
+        constexpr int HB = E / 2;
+        static_for<0, 2>([&](auto hc) {
+          constexpr int h0 = decltype(hc)::value * HB;
+          RkIn<T> in[HB];
+#pragma unroll
+          for (int q = 0; q < HB; ++q) {
+            uint32_t vo, so;
+            if (state_at(h0 + q, vo, so)) in[q] = rk_load<STG>(sa, fo, vo, so);
+          }
+#pragma unroll
+          for (int q = 0; q < HB; ++q) {
+            const int m = h0 + q;
+            uint32_t vo, so;
+            cpx<T> nxt = czero<T>();
+            if (state_at(m, vo, so)) {
+              const double k2m_ = k2m(m);
+              // the next stage reads y_stage on the band (forcing amplitude and term)
+              const bool band = k2m_ > 0.0 && k2m_ <= sp.kf2;
+              nxt = rk_apply<STG>(sa, fo, vo, so, in[q], cv[m], efac(0, exy, m), h, band);
+            }
+            cv[m] = guard(nxt);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+        });
+      };
+      component(c1, f1);
+      __builtin_amdgcn_sched_barrier(0);
+      component(c2, f2);
+      __builtin_amdgcn_sched_barrier(0);
+      component(c3, f3);
+    } else {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        uint32_t vo, so;
+        cpx<T> n1 = czero<T>(), n2 = czero<T>(), n3 = czero<T>();
+        if (state_at(m, vo, so)) {
+          const double k2m_ = k2m(m);
+          const int n = j + TT * m;
+          const T kzt = T(wave_of(n, N)), kyt = T(ky), kxt = T(kx);
+          cpx<T> F1, F2, F3;
+          const bool band = k2m_ > 0.0 && k2m_ <= sp.kf2;
+          if (k2m_ == 0.0) {
+            F1 = F2 = F3 = czero<T>();
+          } else {
+            const T ik2 = T(1) / T(k2m_);  // k2m_ is an integer below 2^24: exact in T
+            const cpx<T> kdc = kxt * c1[m] + kyt * c2[m] + kzt * c3[m];
+            F1 = c1[m] - (kxt * ik2) * kdc;
+            F2 = c2[m] - (kyt * ik2) * kdc;
+            F3 = c3[m] - (kzt * ik2) * kdc;
+            if (A != 0.0 && band) {
+              const T At = T(A);
+              F1 = F1 + At * bload(make_buf<T>(sa.sin + f1), vo, so);
+              F2 = F2 + At * bload(make_buf<T>(sa.sin + f2), vo, so);
+              F3 = F3 + At * bload(make_buf<T>(sa.sin + f3), vo, so);
+            }
+          }
+          const double lk2 = nu * k2m_;
+          const double ef = efac(0, exy, m);
+          n1 = rk_update<STG>(sa, f1, vo, so, F1, lk2, ef, h, true, expl);
+          n2 = rk_update<STG>(sa, f2, vo, so, F2, lk2, ef, h, true, expl);
+          n3 = rk_update<STG>(sa, f3, vo, so, F3, lk2, ef, h, true, expl);
+        }
+        c1[m] = n1;
+        c2[m] = n2;
+        c3[m] = n3;
+      }
     }
     if constexpr (FUSE) {
       inverse_out(c1, 0, 3);
@@ -2040,62 +2171,47 @@ struct TimedLaunch {
   }
 };
 
-// One right-hand-side evaluation and stage update with schedule V.
+// The passes of one right-hand-side evaluation and stage update with schedule V.  Every
+// schedule reads and writes the same buffers in the same layouts, so a stage may take
+// each pass from a different schedule (Stage below).
 template <int N, typename T, int V>
 struct Step {
   using C = Cfg<N, T, V>;
+  // x-pass blocks per slot, which is also the count of partial maxima k_step_dt reads
+  static constexpr int kXBlocks = N * N / C::LX;
+  static int ntile(const Geom& g) { return C::Col::grid_x((g.KX + C::W - 1) / C::W); }
 
-  // flags: kStageZinv launches the standalone z inverse of stage_in first; kStageFuse makes
-  // the last pass also produce the z-inverse of the next stage input.
-  static void rhs_stage(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
-                        double dt_arg, int flags, hipStream_t s) {
-    // the x-pass block count (and so the partial-maximum count) follows the schedule
-    Geom g = x.g;
-    g.nblk_x = N * N / C::LX;
-    const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
-    const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
+  static void z_inverse(const Ctx& x, const cpx<T>* sin, hipStream_t s) {
+    TimedLaunch tl(x.timer, KID_ZINV, s);
+    k_z_inverse<N, T, V><<<dim3(ntile(x.g), x.g.M, x.g.batch), C::COL_THREADS, 0, s>>>(
+        sin, static_cast<cpx<T>*>(x.abuf), static_cast<const cpx<T>*>(x.tw), x.slots, x.g);
+  }
+  static void y_inverse(const Ctx& x, hipStream_t s) {
+    TimedLaunch tl(x.timer, KID_YINV, s);
+    k_y_inverse<N, T, V><<<dim3(ntile(x.g), N, x.g.batch), C::COL_THREADS, 0, s>>>(
+        static_cast<const cpx<T>*>(x.abuf), static_cast<cpx<T>*>(x.bbuf), static_cast<const cpx<T>*>(x.tw), x.slots,
+        x.g);
+  }
+  // g carries nblk_x = kXBlocks
+  static void x_pass(const Ctx& x, const Geom& g, int mode, hipStream_t s) {
+    TimedLaunch tl(x.timer, KID_XPASS, s);
+    k_x_pass<N, T, V><<<dim3(kXBlocks, g.batch), C::X_THREADS, 0, s>>>(
+        static_cast<cpx<T>*>(x.bbuf), static_cast<const cpx<T>*>(x.tw), x.slots, x.dyn, g, mode);
+  }
+  static void y_forward(const Ctx& x, hipStream_t s) {
+    TimedLaunch tl(x.timer, KID_YFWD, s);
+    k_y_forward<N, T, V><<<dim3(ntile(x.g), N, x.g.batch), C::COL_THREADS, 0, s>>>(
+        static_cast<const cpx<T>*>(x.bbuf), static_cast<cpx<T>*>(x.abuf), static_cast<const cpx<T>*>(x.tw), x.slots,
+        x.g);
+  }
+  // fuse: every stage of a multi-step call, the stage fixed at compile time
+  static void z_forward(const Ctx& x, const StageArgs<T>& sa, int stage, bool fuse, hipStream_t s) {
+    const Geom& g = x.g;
     cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
-    cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
-    const int ntile = C::Col::grid_x((g.KX + C::W - 1) / C::W);
-    if (!(flags & kStagePrologue)) {
-      TimedLaunch tl(x.timer, KID_FORCE, s);
-      k_forcing_amplitude<T><<<g.batch, 256, 0, s>>>(sin, x.slots, x.dyn, g);
-    }
-    if (flags & kStageZinv) {
-      TimedLaunch tl(x.timer, KID_ZINV, s);
-      k_z_inverse<N, T, V><<<dim3(ntile, g.M, g.batch), C::COL_THREADS, 0, s>>>(sin, A, tw, x.slots, g);
-    }
-    if (flags & kStagePrologue) return;
-    {
-      TimedLaunch tl(x.timer, KID_YINV, s);
-      k_y_inverse<N, T, V><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, x.slots, g);
-    }
-    {
-      TimedLaunch tl(x.timer, KID_XPASS, s);
-      k_x_pass<N, T, V><<<dim3(g.nblk_x, g.batch), C::X_THREADS, 0, s>>>(B, tw, x.slots, x.dyn, g, want_max ? kXMax : 0);
-    }
-    if (stage == 0) {
-      TimedLaunch tl(x.timer, KID_DT, s);
-      k_step_dt<<<g.batch, 64, 0, s>>>(x.slots, x.dyn, g, dt_arg);
-      // returns at once for slots without the stochastic forcing
-      k_stochastic_update<T><<<g.batch, 256, 0, s>>>(static_cast<const cpx<T>*>(state), x.slots, x.dyn, x.fband, g);
-    }
-    {
-      TimedLaunch tl(x.timer, KID_YFWD, s);
-      k_y_forward<N, T, V><<<dim3(ntile, N, g.batch), C::COL_THREADS, 0, s>>>(B, A, tw, x.slots, g);
-    }
-    StageArgs<T> sa;
-    sa.yn = static_cast<cpx<T>*>(state);
-    sa.acc = static_cast<cpx<T>*>(x.acc);
-    sa.ys = static_cast<cpx<T>*>(x.ystage);
-    sa.sin = sin;
-    sa.rhs = static_cast<cpx<T>*>(rhs_out);
-    sa.fband = x.fband;
-    sa.stage = stage;
+    const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
     const dim3 grid_u(C::Fused::grid_x((g.KX + C::Fused::W - 1) / C::Fused::W), g.M, g.batch);
     constexpr int TU = C::Fused::THREADS;
-    if (flags & kStageFuse) {
-      // every stage of a multi-step call: the stage fixed at compile time
+    if (fuse) {
       TimedLaunch tl(x.timer, KID_ZFWDI, s);
       switch (stage) {
         case 0: k_z_forward_update<N, T, true, V, 0><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g); break;
@@ -2107,6 +2223,69 @@ struct Step {
       TimedLaunch tl(x.timer, KID_ZFWD, s);
       k_z_forward_update<N, T, false, V, -2><<<grid_u, TU, 0, s>>>(A, sa, tw, x.slots, x.dyn, g);
     }
+  }
+};
+
+// Calls fn(std::integral_constant<int, v>) for a schedule index v known only at run time.
+template <int N, int I = 0, class Fn>
+void with_sched(int v, Fn&& fn) {
+  if constexpr (I < sched_count<N>()) {
+    if (v == I)
+      fn(std::integral_constant<int, I>{});
+    else
+      with_sched<N, I + 1>(v, fn);
+  }
+}
+
+// One right-hand-side evaluation and stage update, each pass with the schedule that
+// x.psched names for it.
+template <int N, typename T>
+struct Stage {
+  // flags: kStageZinv launches the standalone z inverse of stage_in first; kStageFuse makes
+  // the last pass also produce the z-inverse of the next stage input.
+  static void rhs_stage(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
+                        double dt_arg, int flags, hipStream_t s) {
+    // the x-pass block count (and so the partial-maximum count) follows its schedule
+    Geom g = x.g;
+    with_sched<N>(x.psched[kPassX], [&](auto v) { g.nblk_x = Step<N, T, decltype(v)::value>::kXBlocks; });
+    const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
+    if (!(flags & kStagePrologue)) {
+      TimedLaunch tl(x.timer, KID_FORCE, s);
+      k_forcing_amplitude<T><<<g.batch, 256, 0, s>>>(sin, x.slots, x.dyn, g);
+    }
+    if (flags & kStageZinv)
+      with_sched<N>(x.psched[kPassZInverse], [&](auto v) { Step<N, T, decltype(v)::value>::z_inverse(x, sin, s); });
+    if (flags & kStagePrologue) return;
+    with_sched<N>(x.psched[kPassYInverse], [&](auto v) { Step<N, T, decltype(v)::value>::y_inverse(x, s); });
+    with_sched<N>(x.psched[kPassX],
+                  [&](auto v) { Step<N, T, decltype(v)::value>::x_pass(x, g, want_max ? kXMax : 0, s); });
+    if (stage == 0) {
+      TimedLaunch tl(x.timer, KID_DT, s);
+      k_step_dt<<<g.batch, 64, 0, s>>>(x.slots, x.dyn, g, dt_arg);
+      // returns at once for slots without the stochastic forcing
+      k_stochastic_update<T><<<g.batch, 256, 0, s>>>(static_cast<const cpx<T>*>(state), x.slots, x.dyn, x.fband, g);
+    }
+    with_sched<N>(x.psched[kPassYForward], [&](auto v) { Step<N, T, decltype(v)::value>::y_forward(x, s); });
+    StageArgs<T> sa;
+    sa.yn = static_cast<cpx<T>*>(state);
+    sa.acc = static_cast<cpx<T>*>(x.acc);
+    sa.ys = static_cast<cpx<T>*>(x.ystage);
+    sa.sin = sin;
+    sa.rhs = static_cast<cpx<T>*>(rhs_out);
+    sa.fband = x.fband;
+    sa.stage = stage;
+    const bool fuse = (flags & kStageFuse) != 0;
+    with_sched<N>(x.psched[kPassZForward],
+                  [&](auto v) { Step<N, T, decltype(v)::value>::z_forward(x, sa, stage, fuse, s); });
+  }
+
+  // the stage with every pass in schedule V
+  template <int V>
+  static void rhs_stage_of(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
+                           double dt_arg, int flags, hipStream_t s) {
+    Ctx y = x;
+    for (int p = 0; p < kNumPasses; ++p) y.psched[p] = V;
+    rhs_stage(y, state, stage_in, stage, rhs_out, want_max, dt_arg, flags, s);
   }
 };
 
@@ -2242,7 +2421,7 @@ struct Engine {
     d.fused_ec = CV::Fused::EC;
     d.fused_w = CV::Fused::W;
     d.x_lines = CV::LX;
-    d.rhs_stage = &Step<N, T, V>::rhs_stage;
+    d.rhs_stage = &Stage<N, T>::template rhs_stage_of<V>;
   }
 
   template <int V, int NV>
@@ -2257,6 +2436,7 @@ struct Engine {
     Ops o{};
     o.nsched = sched_count<N>();
     add_scheds<0, sched_count<N>()>(o);
+    o.rhs_mixed = &Stage<N, T>::rhs_stage;
     o.init_field = &init_field;
     o.get_state = &get_state;
     o.set_state = &set_state;

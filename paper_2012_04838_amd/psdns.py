@@ -39,6 +39,10 @@ FORCING_POWER = 0
 FORCING_HOLD = 1
 FORCING_STOCHASTIC = 2
 FORCING_ALVELIUS = 3
+# passes of a right-hand-side evaluation (psdns_set_pass_schedules order)
+PASS_Z_INVERSE, PASS_Y_INVERSE, PASS_X, PASS_Y_FORWARD, PASS_Z_FORWARD = range(5)
+NUM_PASSES = 5
+PASS_NAMES = ("z_inverse", "y_inverse", "x_pass", "y_forward", "z_forward")
 INTEGRATOR_IF = 0
 INTEGRATOR_EXPLICIT = 1
 SPECTRUM_CONFIG = 0
@@ -64,7 +68,7 @@ class PlanInfo(ctypes.Structure):
                [("state_bytes", ctypes.c_int64), ("workspace_bytes", ctypes.c_int64),
                 ("elems_col", _c_int32), ("elems_x", _c_int32), ("n_schedules", _c_int32),
                 ("schedule", _c_int32), ("plan_bytes", ctypes.c_int64), ("dealias", _c_int32),
-                ("general", _c_int32)]
+                ("general", _c_int32), ("pass_schedules", _c_int32 * 5)]
 
 
 class ScheduleInfo(ctypes.Structure):
@@ -111,6 +115,9 @@ _SIGS = {
                                  _c_int32, _c_void_p]),
     "psdns_get_schedule_info": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(ScheduleInfo)]),
     "psdns_set_schedule": (ctypes.c_int, [_c_void_p, _c_int32]),
+    "psdns_set_pass_schedules": (ctypes.c_int, [_c_void_p, ctypes.POINTER(_c_int32)]),
+    "psdns_tune_passes": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(_c_int32), _c_void_p]),
     "psdns_tune": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(_c_int32), _c_void_p]),
     "psdns_set_timing": (ctypes.c_int, [_c_void_p, _c_int32]),
@@ -355,7 +362,13 @@ class Plan:
 
     @property
     def schedule(self) -> int:
+        """Schedule of every pass, or -1 when the passes run in different schedules."""
         return int(self.info.schedule)
+
+    @property
+    def pass_schedules(self) -> list:
+        """Schedule of each pass (PASS_* order)."""
+        return [int(v) for v in self.info.pass_schedules]
 
     def schedule_info(self, index: int) -> dict:
         si = ScheduleInfo()
@@ -365,6 +378,24 @@ class Plan:
     def set_schedule(self, index: int) -> None:
         _check(lib().psdns_set_schedule(self._h, index))
         self._refresh_info()
+
+    def set_pass_schedules(self, sched) -> None:
+        """Schedule of each pass, PASS_* order (five indices in [0, n_schedules))."""
+        if len(sched) != NUM_PASSES:
+            raise ValueError(f"{NUM_PASSES} schedule indices expected")
+        arr = (_c_int32 * NUM_PASSES)(*[int(v) for v in sched])
+        _check(lib().psdns_set_pass_schedules(self._h, arr))
+        self._refresh_info()
+
+    def tune_passes(self, state, ws, reps: int = 3):
+        """Time every pass in every schedule on `state` and select the fastest schedule of
+        each pass; returns (selection [NUM_PASSES], ms [n_schedules][NUM_PASSES])."""
+        ms = (ctypes.c_double * (self.n_schedules * NUM_PASSES))()
+        best = (_c_int32 * NUM_PASSES)()
+        _check(lib().psdns_tune_passes(self._h, _ptr(state), _ptr(ws), reps, ms, best, _stream()))
+        self._refresh_info()
+        table = [[float(ms[i * NUM_PASSES + p]) for p in range(NUM_PASSES)] for i in range(self.n_schedules)]
+        return [int(v) for v in best], table
 
     def tune(self, state, ws, reps: int = 3):
         """Time every schedule on `state` (steady-state RK stages), select the fastest;

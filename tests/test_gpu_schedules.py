@@ -132,6 +132,81 @@ def test_graph_recaptures_after_schedule_change():
     assert rel_l2(got, ref) < 1e-12
 
 
+@pytest.mark.parametrize("N,S,prec", [(64, 2, 64), (128, 1, 64), (64, 2, 32)])
+def test_passes_in_different_schedules_match_oracle(N, S, prec):
+    """Each pass in its own schedule (the layouts are shared): the right-hand side and CFL
+    steps, eager and by graph replay, meet the same bars as a single schedule."""
+    torch = torch_mod()
+    from paper_2012_04838_amd import psdns
+
+    prm = _prm(S)
+    plan = make_plan(N, S, prec)
+    set_params(plan, 0, prm)
+    ns = plan.n_schedules
+    mix = [3 % ns, 1 % ns, 5 % ns, 2 % ns, 6 % ns]
+    plan.set_pass_schedules(mix)
+    assert plan.pass_schedules == mix and plan.schedule == -1
+    tol = 1e-12 if prec == 64 else 1e-5
+    x = inputs.random_spectral_state(N, 3 + S, 60 + N + S, ora.kmax_retained(N), 5.0)
+    st, ws, out = plan.new_state(), plan.new_workspace(), plan.new_state()
+    plan.set_state(st, x, 0)
+    plan.rhs(st, out, ws)
+    err = rel_l2(to_numpy(plan.get_state(out, 0)), ora.rhs(x, prm))
+    assert err < tol, err
+    y = ora.init_field(N, S, 13, 4.0, 1.0)
+    ref = ora.step(y, prm, nsteps=3, cfl=0.5)
+    for graph in (False, True):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            plan.set_graph(graph)
+            plan.set_state(st, y, 0)
+            plan.clear_step_info(ws)
+            plan.step(st, ws, -0.5, 3)
+            got = to_numpy(plan.get_state(st, 0))
+        stream.synchronize()
+        err = rel_l2(got, ref)
+        print(f"N={N} S={S} fp{prec} passes {mix} graph={graph}: 3 CFL steps rel L2 {err:.2e}", flush=True)
+        assert err < (1e-12 if prec == 64 else 1e-5), (graph, err)
+    with pytest.raises(psdns.PsdnsError):
+        plan.set_pass_schedules([0, 0, ns, 0, 0])
+    assert plan.pass_schedules == mix
+
+
+def test_tune_passes_selects_the_fastest_of_each_pass_and_leaves_the_state_alone():
+    torch = torch_mod()
+    N, S = 64, 2
+    plan = make_plan(N, S, 32, batch=2)
+    prm = _prm(S)
+    for slot in range(2):
+        set_params(plan, slot, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    plan.init_field(st, ws, 0, seed=3, k_peak=4.0)
+    plan.init_field(st, ws, 1, seed=4, k_peak=4.0)
+    plan.step(st, ws, -0.5, 2)
+    before = st.clone()
+    info0 = plan.read_step_info(ws)
+    sel, table = plan.tune_passes(st, ws, reps=2)
+    torch.cuda.synchronize()
+    assert len(table) == plan.n_schedules and all(len(r) == 5 for r in table)
+    assert all(m > 0 for r in table for m in r)
+    assert sel == [int(np.argmin([r[p] for r in table])) for p in range(5)]
+    assert plan.pass_schedules == sel
+    assert torch.equal(st, before)
+    info1 = plan.read_step_info(ws)
+    for a, b in zip(info0, info1):
+        assert a["steps"] == b["steps"] and a["t"] == b["t"] and a["flags"] == b["flags"]
+    ref = before.clone()
+    plan.step(st, ws, -0.5, 2)
+    plan2 = make_plan(N, S, 32, batch=2)
+    for slot in range(2):
+        set_params(plan2, slot, prm)
+    plan2.set_pass_schedules(sel)
+    ws2 = plan2.new_workspace()
+    plan2.step(ref, ws2, -0.5, 2)
+    torch.cuda.synchronize()
+    assert torch.equal(st, ref)
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_every_schedule_repeats_bitwise(prec):
     """Identical input gives bitwise identical steps, every schedule, run after run.
