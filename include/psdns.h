@@ -316,11 +316,13 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
  * butterflies differs).  A captured step graph is dropped and re-captured. */
 psdns_status psdns_set_pass_schedules(psdns_plan* plan, const int32_t* sched);
 /* Autotuner per pass: times the passes of `reps` RK stages with each schedule (the trial of
- * psdns_tune, and the standalone z inverse) with an event pair around every kernel, selects
- * the fastest schedule of each pass and returns the mean milliseconds of every pass and
- * schedule in host array ms_out[n_schedules * PSDNS_NUM_PASSES] (schedule-major; may be
- * NULL) and the selection in best[PSDNS_NUM_PASSES] (may be NULL).  Leaves `state` and the
- * step records untouched.  Synchronises the stream. */
+ * psdns_tune, and the standalone z inverse) with an event pair around every kernel and
+ * selects for each pass the lowest-index schedule within 1% of its fastest (schedules that
+ * coincide at a size then resolve to the same choice on every run).  Returns the mean
+ * milliseconds of every pass and schedule in host array ms_out[n_schedules *
+ * PSDNS_NUM_PASSES] (schedule-major; may be NULL) and the selection in
+ * best[PSDNS_NUM_PASSES] (may be NULL).  Leaves `state` and the step records untouched.
+ * Synchronises the stream. */
 psdns_status psdns_tune_passes(psdns_plan* plan, const void* state, void* ws, int32_t reps, double* ms_out,
                                int32_t* best, void* hip_stream);
 

@@ -846,11 +846,14 @@ psdns_status psdns_tune_passes(psdns_plan* plan, const void* state, void* ws, in
     for (int p = 0; p < kNumPasses; ++p)
       ms[(size_t)i * kNumPasses + p] = cnt[kid[p]] ? sum[kid[p]] / cnt[kid[p]] : 0.0;
   }
+  // the lowest-index schedule within 1% of the fastest: schedules whose kernels coincide at
+  // this size (or differ within the timing noise) resolve to the same choice on every run
   int32_t pick[kNumPasses];
   for (int p = 0; p < kNumPasses; ++p) {
+    double lo = ms[p];
+    for (int i = 1; i < ns; ++i) lo = std::min(lo, ms[(size_t)i * kNumPasses + p]);
     pick[p] = 0;
-    for (int i = 1; i < ns; ++i)
-      if (ms[(size_t)i * kNumPasses + p] < ms[(size_t)pick[p] * kNumPasses + p]) pick[p] = i;
+    while (pick[p] < ns - 1 && ms[(size_t)pick[p] * kNumPasses + p] > 1.01 * lo) ++pick[p];
   }
   if (ms_out)
     for (size_t k = 0; k < ms.size(); ++k) ms_out[k] = ms[k];

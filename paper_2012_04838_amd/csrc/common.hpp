@@ -61,17 +61,18 @@ struct SlotDev {
   double diff[3 + kMaxScalars];     // diffusivity of each spectral field
   double g[kMaxScalars][3];         // mean scalar gradients
   int active;
-  int forcing;                      // PSDNS_FORCING_POWER, _HOLD or _STOCHASTIC
+  int forcing;                      // PSDNS_FORCING_POWER, _HOLD, _STOCHASTIC or _ALVELIUS
   double hold;                      // target band energy of PSDNS_FORCING_HOLD
   int integrator;                   // PSDNS_INTEGRATOR_IF or PSDNS_INTEGRATOR_EXPLICIT
   int pad_;
   double sigma;                     // PSDNS_FORCING_STOCHASTIC: stationary deviation per part
   double tl;                        // PSDNS_FORCING_STOCHASTIC: correlation time
-  unsigned long long seed;          // PSDNS_FORCING_STOCHASTIC: SplitMix64 seed
+  unsigned long long seed;          // PSDNS_FORCING_STOCHASTIC and _ALVELIUS: SplitMix64 seed
 };
 
-// Band table of the stochastic forcing: per slot, kStochCand candidates of 12 FP64 (the
-// vector b and the forcing term N^3 P(k) b, 3 complex each), candidate
+// Band table of the stochastic forcings: per slot, kStochCand candidates of 12 FP64 (the
+// Ornstein-Uhlenbeck vector b, or unused for Alvelius' force, then the forcing term, 3
+// complex each), candidate
 // i = kx + (kf+1)((ky+kf) + (2kf+1)(kz+kf)) for the slot's kf.
 constexpr int kStochKfMax = PSDNS_STOCHASTIC_KF_MAX;
 constexpr int kStochCand = (kStochKfMax + 1) * (2 * kStochKfMax + 1) * (2 * kStochKfMax + 1);

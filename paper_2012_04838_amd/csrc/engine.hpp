@@ -617,6 +617,9 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   // registers for the line data.
   constexpr bool kLong = E > 8;
   constexpr bool kRegTw = sizeof(T) == 4 && !kLong && C::D.xreg;
+  // FP32 short lines load every input up front; FP64 and 16-element lines load u3/omega1
+  // and u1/u2 only when their transform comes (registers)
+  constexpr bool kLate = kLong || sizeof(T) == 8;
   using TwT = std::conditional_t<kRegTw, TwReg<N, E, T>, const cpx<T>*>;
   TwT tw;
   if constexpr (kRegTw)
@@ -642,7 +645,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   load(2, r2);
   load(4, r4);
   load(5, r5);
-  if constexpr (!kLong) {
+  if constexpr (!kLate) {
     load(3, r3);
     load(0, r0);
   }
@@ -662,7 +665,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     w3p[m] = h[m].y;
   }
   // u3, omega1
-  if constexpr (kLong) load(3, r3);
+  if constexpr (kLate) load(3, r3);
   build(r2, r3, h);
   fft<N, E, true, XS>(h, lds, j, tw);
   T u3p[E], w1p[E];
@@ -672,7 +675,7 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     w1p[m] = h[m].y;
   }
   // u1, u2
-  if constexpr (kLong) load(0, r0);
+  if constexpr (kLate) load(0, r0);
   build(r0, r1, h);
   const int S = g.S;
   // first scalar pair's entries go in flight before the next transforms
@@ -747,7 +750,13 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
     // scalars in pairs (s, s+1): a_s = u.grad phi_s + g_s.u
     for (int s = 0; s < S; s += 2) {
       const bool two = s + 1 < S;
-      if (s > 0 || !kPrefetchScalars) load_scalar_pair(s);
+      // FP64: each transform's inputs are loaded just before it (registers)
+      if constexpr (kLate) {
+        load(6 + 3 * s, s0);
+        load(7 + 3 * s, s1);
+      } else if (s > 0 || !kPrefetchScalars) {
+        load_scalar_pair(s);
+      }
       {
         const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
 #pragma unroll
@@ -760,6 +769,10 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       }
       if (two) {
         const T g0 = T(sp.g[s + 1][0]), g1 = T(sp.g[s + 1][1]), g2 = T(sp.g[s + 1][2]);
+        if constexpr (kLate) {
+          load(9 + 3 * s, s3);
+          load(10 + 3 * s, s4);
+        }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) va[q] = mul_is(s3[q], kxq(q));
         build(va, s4, h);
@@ -769,6 +782,10 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
           as1[m] = u1p[m] * h[m].x + u2p[m] * h[m].y + (g0 * u1p[m] + g1 * u2p[m] + g2 * u3p[m]);
       }
       // z-derivatives of both scalars share one transform
+      if constexpr (kLate) {
+        load(8 + 3 * s, s2);
+        if (two) load(11 + 3 * s, s5);
+      }
       if (!two) {
 #pragma unroll
         for (int q = 0; q < NQ; ++q) s5[q] = czero<T>();

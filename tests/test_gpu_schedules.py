@@ -189,7 +189,10 @@ def test_tune_passes_selects_the_fastest_of_each_pass_and_leaves_the_state_alone
     torch.cuda.synchronize()
     assert len(table) == plan.n_schedules and all(len(r) == 5 for r in table)
     assert all(m > 0 for r in table for m in r)
-    assert sel == [int(np.argmin([r[p] for r in table])) for p in range(5)]
+    for p in range(5):
+        col = [r[p] for r in table]
+        # the lowest index within 1% of the fastest
+        assert sel[p] == min(i for i, v in enumerate(col) if v <= 1.01 * min(col)), (p, col)
     assert plan.pass_schedules == sel
     assert torch.equal(st, before)
     info1 = plan.read_step_info(ws)
