@@ -316,6 +316,47 @@ def cpu_baseline(n, s):
     return out
 
 
+def batched_small(steps: int = 20, tune_reps: int = 2):
+    """Saturated throughput of small grids in one batch: B independent realizations of N^3,
+    S = 2, FP32, with B N^3 = 2^24 at every size (the work of an eighth of a 512^3 step),
+    stepped together by graph replay with the per-pass tuned schedules.  Reports the
+    batch's N^3*steps/s and its step bandwidth on this design's bytes."""
+    import torch
+
+    from paper_2012_04838_amd import psdns
+    from paper_2012_04838_amd.serve import viscosity_for
+
+    out = {}
+    for n, b in ((64, 64), (128, 8), (256, 1)):
+        plan = psdns.Plan(n, 2, 32, b)
+        for i in range(b):
+            plan.set_slot(i, nu=viscosity_for(n), power=POWER, k_force=KF, schmidt=SCHMIDT[:2], mean_grad=GRAD[:2])
+        st, ws = plan.new_state(), plan.new_workspace()
+        for i in range(b):
+            plan.init_field(st, ws, i, seed=100 + i, k_peak=4.0, kinetic_energy=1.0)
+        chosen = plan.tune_passes(st, ws, tune_reps)[0] if tune_reps > 0 else [0] * psdns.NUM_PASSES
+        stream = torch.cuda.Stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            plan.set_graph(True)
+            plan.step(st, ws, -0.5, 2)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            plan.step(st, ws, -0.5, steps)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        info = plan.read_step_info(ws)
+        gbs = b * step_bytes(n, 2, 32) / (ms * 1e-3) / 1e9
+        out[str(n)] = {"batch": b, "ms_per_step": ms, "N3_steps_per_s": b * float(n) ** 3 / (ms * 1e-3),
+                       "alg_GBs": gbs, "frac": gbs / PEAK_HBM_GBS, "schedule": chosen,
+                       "finite": all(r["flags"] == 0 for r in info)}
+        del st, ws
+        plan.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def leg_summary(r, n, s, prec, steps):
     """Throughput, step bandwidth under both byte models and the graph-replay median."""
     ms = r["ms_total"] / steps
@@ -343,6 +384,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-1024", action="store_true", help="skip the 1024^3 S=1 leg")
     ap.add_argument("--steps-1024", type=int, default=10)
+    ap.add_argument("--no-small", action="store_true", help="skip the batched small-grid leg")
     ap.add_argument("--copy-gb", type=float, default=1.0,
                     help="size of the copy-bandwidth reference (0 disables)")
     ap.add_argument("--serve-requests", type=int, default=40,
@@ -447,6 +489,11 @@ def main():
         big["steps"] = args.steps_1024
         big["workload"] = "1024^3 S=1 (Sc 1, G=(0,1,0)), nu=3e-4, P=0.1 on 0<|k|<=2, Rogallo IC k_p=8, CFL 0.5"
         out["n1024"] = big
+    if not args.no_small:
+        out["batched_small"] = batched_small(tune_reps=2 if tr else 0)
+        print("[bench] batched small grids done: " + ", ".join(
+            f"{k}^3 x{v['batch']} {v['ms_per_step']:.2f} ms" for k, v in out["batched_small"].items()),
+            file=sys.stderr, flush=True)
     if args.serve_requests > 0:
         out["serve"] = serve_mix(args.serve_requests, args.serve_load)
         print(f"[bench] serve done: p50 {out['serve']['p50_s']:.3f} s p99 {out['serve']['p99_s']:.3f} s",

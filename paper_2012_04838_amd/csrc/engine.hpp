@@ -102,6 +102,7 @@ struct ColCfg {
   // 64-byte row segments: the two halves of a 128-byte row go to consecutive blocks of
   // one XCD (col_block), so that XCD's L2 serves the second half
   static constexpr bool PAIR = W * (int)sizeof(cpx<T>) == 64;
+  static constexpr int STORE = store_policy(W * (int)sizeof(cpx<T>));  // cache policy of its stores
   static_assert(THREADS <= 1024, "column block too large");
   static_assert((W * N + N) * sizeof(cpx<T>) <= 160 * 1024, "column pass LDS exceeds 160 KB");
   // blocks along x of a grid covering ntile kx tiles
@@ -295,7 +296,7 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
     if (!valid) return;
     const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
+    for (int m = 0; m < E; ++m) bstore<C::Col::STORE>(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
   cpx<T> a[E], d[E], nx[E];
   // transform the field held in a (and its z derivative into fd when fd >= 0)
@@ -386,7 +387,7 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
     if (!valid) return;
     const Buf<T> b = make_buf<T>(bplane + (long long)f * g.b_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
+    for (int m = 0; m < E; ++m) bstore<C::Col::STORE>(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
   cpx<T> a[E], d[E], nx[E];
   // field cur into a (from the prefetch when enabled), then prefetch field nxt
@@ -884,7 +885,7 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         uint32_t vo, so;
-        if (compact_at<N, TT>(m, j, voff, rsb, vo, so)) bstore(b, vo, so, a[m]);
+        if (compact_at<N, TT>(m, j, voff, rsb, vo, so)) bstore<C::Col::STORE>(b, vo, so, a[m]);
       }
     }
   }
@@ -914,13 +915,13 @@ struct StageArgs {
 // same formulas with both factors 1 and F completed by -lk2 times the stage input,
 // which is classical RK4 on the full right-hand side.  STG is the stage when known at
 // compile time (0..3, or -1 for dy/dt), else -2 and the stage comes from the arguments.
-template <int STG, typename T>
+template <int STG, int SP = kPolicyStream, typename T>
 __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so, cpx<T> F,
                                             double lk2, double ehd, double h, bool write_ys, bool expl) {
   const int stage = STG >= -1 ? STG : a.stage;
   if (stage < 0) {
     const cpx<T> y = bload(make_buf<T>(a.sin + foff), vo, so);
-    bstore(make_buf<T>(a.rhs + foff), vo, so, F - T(lk2) * y);
+    bstore<SP>(make_buf<T>(a.rhs + foff), vo, so, F - T(lk2) * y);
     return czero<T>();
   }
   const Buf<T> yn = make_buf<T>(a.yn + foff), acc = make_buf<T>(a.acc + foff);
@@ -938,27 +939,27 @@ __device__ __forceinline__ cpx<T> rk_update(const StageArgs<T>& a, long long fof
   cpx<T> nxt;
   switch (stage) {
     case 0: {
-      bstore(acc, vo, so, e1 * (y + (th / T(6)) * F));
+      bstore<SP>(acc, vo, so, e1 * (y + (th / T(6)) * F));
       nxt = eh * (y + (th / T(2)) * F);
       break;
     }
     case 1: {
-      bstore(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
+      bstore<SP>(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
       nxt = eh * y + (th / T(2)) * F;
       break;
     }
     case 2: {
-      bstore(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
+      bstore<SP>(acc, vo, so, bload(acc, vo, so) + ((th / T(3)) * eh) * F);
       nxt = e1 * y + (th * eh) * F;
       break;
     }
     default: {
       nxt = bload(acc, vo, so) + (th / T(6)) * F;
-      bstore(yn, vo, so, nxt);
+      bstore<SP>(yn, vo, so, nxt);
       return nxt;
     }
   }
-  if (write_ys) bstore(make_buf<T>(a.ys + foff), vo, so, nxt);
+  if (write_ys) bstore<SP>(make_buf<T>(a.ys + foff), vo, so, nxt);
   return nxt;
 }
 
@@ -978,8 +979,9 @@ __device__ __forceinline__ RkIn<T> rk_load(const StageArgs<T>& a, long long foff
   if constexpr (STG > 0) r.accv = bload(make_buf<T>(a.acc + foff), vo, so);
   return r;
 }
-// The stage formulas of rk_update (integrating factor) on values from rk_load.
-template <int STG, typename T>
+// The stage formulas of rk_update (integrating factor) on values from rk_load; SP is the
+// cache policy of the stores.
+template <int STG, int SP = kPolicyStream, typename T>
 __device__ __forceinline__ cpx<T> rk_apply(const StageArgs<T>& a, long long foff, uint32_t vo, uint32_t so,
                                            const RkIn<T>& in, cpx<T> F, double ehd, double h, bool write_ys) {
   const Buf<T> yn = make_buf<T>(a.yn + foff), acc = make_buf<T>(a.acc + foff);
@@ -987,20 +989,20 @@ __device__ __forceinline__ cpx<T> rk_apply(const StageArgs<T>& a, long long foff
   const cpx<T> y = in.y;
   cpx<T> nxt;
   if constexpr (STG == 0) {
-    bstore(acc, vo, so, e1 * (y + (th / T(6)) * F));
+    bstore<SP>(acc, vo, so, e1 * (y + (th / T(6)) * F));
     nxt = eh * (y + (th / T(2)) * F);
   } else if constexpr (STG == 1) {
-    bstore(acc, vo, so, in.accv + ((th / T(3)) * eh) * F);
+    bstore<SP>(acc, vo, so, in.accv + ((th / T(3)) * eh) * F);
     nxt = eh * y + (th / T(2)) * F;
   } else if constexpr (STG == 2) {
-    bstore(acc, vo, so, in.accv + ((th / T(3)) * eh) * F);
+    bstore<SP>(acc, vo, so, in.accv + ((th / T(3)) * eh) * F);
     nxt = e1 * y + (th * eh) * F;
   } else {
     nxt = in.accv + (th / T(6)) * F;
-    bstore(yn, vo, so, nxt);
+    bstore<SP>(yn, vo, so, nxt);
     return nxt;
   }
-  if (write_ys) bstore(make_buf<T>(a.ys + foff), vo, so, nxt);
+  if (write_ys) bstore<SP>(make_buf<T>(a.ys + foff), vo, so, nxt);
   return nxt;
 }
 
@@ -1097,7 +1099,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     if (!valid) return;
     const Buf<T> b = make_buf<T>(aslot + (long long)f * g.a_field);
 #pragma unroll
-    for (int m = 0; m < E; ++m) bstore(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
+    for (int m = 0; m < E; ++m) bstore<C::STORE>(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
   // inverse z of the next stage input (scaled by 1/N^3) into A field f, and of i kz * it into fd
   auto inverse_out = [&](cpx<T> (&v)[E], int f, int fd) {
@@ -1145,7 +1147,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
           cpx<T> nxt = czero<T>();
           if (state_at(m, vo, so)) {
             const cpx<T> F = k2m(m) == 0.0 ? czero<T>() : czero<T>() - a[m];
-            nxt = rk_apply<STG>(sa, foff, vo, so, in[q], F, efac(1 + s, exy, m), h, false);
+            nxt = rk_apply<STG, C::STORE>(sa, foff, vo, so, in[q], F, efac(1 + s, exy, m), h, false);
           }
           a[m] = guard(nxt);
         }
@@ -1159,7 +1161,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
         if (state_at(m, vo, so)) {
           const double k2m_ = k2m(m);
           const cpx<T> F = k2m_ == 0.0 ? czero<T>() : czero<T>() - a[m];
-          nxt = rk_update<STG>(sa, foff, vo, so, F, dif * k2m_, efac(1 + s, exy, m), h, true, expl);
+          nxt = rk_update<STG, C::STORE>(sa, foff, vo, so, F, dif * k2m_, efac(1 + s, exy, m), h, true, expl);
         }
         a[m] = nxt;
       }
@@ -1252,7 +1254,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
               const double k2m_ = k2m(m);
               // the next stage reads y_stage on the band (forcing amplitude and term)
               const bool band = k2m_ > 0.0 && k2m_ <= sp.kf2;
-              nxt = rk_apply<STG>(sa, fo, vo, so, in[q], cv[m], efac(0, exy, m), h, band);
+              nxt = rk_apply<STG, C::STORE>(sa, fo, vo, so, in[q], cv[m], efac(0, exy, m), h, band);
             }
             cv[m] = guard(nxt);
           }
@@ -1292,9 +1294,9 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
           }
           const double lk2 = nu * k2m_;
           const double ef = efac(0, exy, m);
-          n1 = rk_update<STG>(sa, f1, vo, so, F1, lk2, ef, h, true, expl);
-          n2 = rk_update<STG>(sa, f2, vo, so, F2, lk2, ef, h, true, expl);
-          n3 = rk_update<STG>(sa, f3, vo, so, F3, lk2, ef, h, true, expl);
+          n1 = rk_update<STG, C::STORE>(sa, f1, vo, so, F1, lk2, ef, h, true, expl);
+          n2 = rk_update<STG, C::STORE>(sa, f2, vo, so, F2, lk2, ef, h, true, expl);
+          n3 = rk_update<STG, C::STORE>(sa, f3, vo, so, F3, lk2, ef, h, true, expl);
         }
         c1[m] = n1;
         c2[m] = n2;
@@ -1370,7 +1372,7 @@ k_z_forward_pressure(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ pout,
     const double k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
     cpx<T> p = czero<T>();
     if (k2 > 0.0) p = czero<T>() - v[m] - mul_is(kdc[m], T(1.0 / k2));
-    bstore(out, vo, so, p);
+    bstore<C::Col::STORE>(out, vo, so, p);
   }
 }
 

@@ -20,11 +20,16 @@ namespace psdns {
 constexpr int kBufWord3 = 0x00020000;
 
 // Cache policy of the buffer accesses (the instructions' nt bit).  Every pass writes each
-// output element once and the next pass reads it from HBM, so stores are streamed
-// (non-temporal); loads are streamed in the passes where that measured faster (the y
-// passes), and left cached where it did not (the x pass, the z passes).
+// output element once and the next pass reads it from HBM, so stores of whole 128-byte
+// lines are streamed (non-temporal).  A column pass with 64-byte row segments writes the
+// two halves of each 128-byte line from two blocks of one XCD; those stores stay cached,
+// so that the L2 joins the halves before the line goes to HBM (streamed, each half went
+// out alone and the passes moved 8-36% more bytes).  Loads are streamed in the passes
+// where that measured faster (the y passes), and left cached where it did not.
 constexpr int kPolicyCached = 0;
 constexpr int kPolicyStream = 2;
+// store policy of a pass whose row segments are ROW_BYTES long
+constexpr int store_policy(int row_bytes) { return row_bytes >= 128 ? kPolicyStream : kPolicyCached; }
 
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
@@ -62,15 +67,14 @@ __device__ __forceinline__ cpx<T> bload(const Buf<T>& b, uint32_t voff, uint32_t
 // whose SGPR offset is the constant 0, so the 128-bit (FP64) stores carry their whole
 // offset in the VGPR; with the offset in an SGPR the overwrite was observed to corrupt
 // stored values now and then.  64-bit (FP32) stores are not affected.
-template <typename T>
+template <int POLICY = kPolicyStream, typename T>
 __device__ __forceinline__ void bstore(const Buf<T>& b, uint32_t voff, uint32_t soff, cpx<T> v) {
   if constexpr (sizeof(T) == 4) {
     const f32x2_t w = {v.x, v.y};
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, w), b.r, (int)voff, (int)soff, kPolicyStream);
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, w), b.r, (int)voff, (int)soff, POLICY);
   } else {
     const f64x2_t w = {v.x, v.y};
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)(voff + soff), 0,
-                                           kPolicyStream);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, w), b.r, (int)(voff + soff), 0, POLICY);
   }
 }
 
