@@ -357,6 +357,68 @@ def batched_small(steps: int = 20, tune_reps: int = 2):
     return out
 
 
+def options_leg(steps: int = 5):
+    """The paper's options on the 512^3 S=2 FP32 workload (CFL 0.5): milliseconds per step
+    of each by graph replay, beside the default path (integrating factor, constant power,
+    2/3 rule) timed the same way, and the general kernels on the paper's own grid N = 520;
+    then the cost of one pressure call and of one spectra-and-statistics call."""
+    import torch
+
+    from paper_2012_04838_amd import psdns
+
+    cases = [
+        ("default", 512, {}, {}),
+        ("explicit_rk4", 512, {}, {"integrator": psdns.INTEGRATOR_EXPLICIT}),
+        ("band_energy_hold", 512, {}, {"forcing": psdns.FORCING_HOLD, "hold_energy": 0.01}),
+        ("stochastic_eswaran_pope", 512, {},
+         {"forcing": psdns.FORCING_STOCHASTIC, "stoch_sigma": 0.05, "stoch_tl": 0.5, "stoch_seed": 7}),
+        ("stochastic_alvelius", 512, {}, {"forcing": psdns.FORCING_ALVELIUS, "stoch_seed": 7}),
+        ("phase_shift_sphere", 512, {"dealias": psdns.DEALIAS_PHASE_SPHERE}, {}),
+        ("mixed_radix_520", 520, {}, {}),
+    ]
+    out = {}
+    for name, n, pkw, skw in cases:
+        plan = psdns.Plan(n, 2, 32, 1, **pkw)
+        plan.set_slot(0, nu=NU, power=POWER, k_force=KF, schmidt=SCHMIDT[:2], mean_grad=GRAD[:2], **skw)
+        st, ws = plan.new_state(), plan.new_workspace()
+        plan.init_field(st, ws, 0, seed=3, k_peak=KP, kinetic_energy=1.0)
+        plan.tune_passes(st, ws, 1)
+        stream = torch.cuda.Stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            plan.set_graph(True)
+            plan.step(st, ws, -0.5, 1)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            plan.step(st, ws, -0.5, steps)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        rec = {"n": n, "ms_per_step": ms, "N3_steps_per_s": float(n) ** 3 / (ms * 1e-3),
+               "general_kernels": bool(plan.info.general), "finite": plan.read_step_info(ws)[0]["flags"] == 0}
+        if name == "default":
+            # one call each of the pressure and of the spectra and statistics
+            for what, fn in (("pressure_ms", lambda: plan.pressure(st, ws)),
+                             ("spectra_ms", lambda: plan.spectra_raw(st, ws))):
+                fn()
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(3):
+                    fn()
+                e1.record()
+                torch.cuda.synchronize()
+                rec[what] = e0.elapsed_time(e1) / 3
+        out[name] = rec
+        del st, ws
+        plan.close()
+        torch.cuda.empty_cache()
+    base = out["default"]["ms_per_step"]
+    for name, rec in out.items():
+        if rec["n"] == 512:
+            rec["vs_default"] = rec["ms_per_step"] / base
+    return out
+
+
 def leg_summary(r, n, s, prec, steps):
     """Throughput, step bandwidth under both byte models and the graph-replay median."""
     ms = r["ms_total"] / steps
@@ -385,6 +447,7 @@ def main():
     ap.add_argument("--no-1024", action="store_true", help="skip the 1024^3 S=1 leg")
     ap.add_argument("--steps-1024", type=int, default=10)
     ap.add_argument("--no-small", action="store_true", help="skip the batched small-grid leg")
+    ap.add_argument("--no-options", action="store_true", help="skip the leg of the paper's options")
     ap.add_argument("--copy-gb", type=float, default=1.0,
                     help="size of the copy-bandwidth reference (0 disables)")
     ap.add_argument("--serve-requests", type=int, default=40,
@@ -489,6 +552,10 @@ def main():
         big["steps"] = args.steps_1024
         big["workload"] = "1024^3 S=1 (Sc 1, G=(0,1,0)), nu=3e-4, P=0.1 on 0<|k|<=2, Rogallo IC k_p=8, CFL 0.5"
         out["n1024"] = big
+    if not args.no_options:
+        out["options"] = options_leg()
+        print("[bench] options done: " + ", ".join(f"{k} {v['ms_per_step']:.1f} ms" for k, v in out["options"].items()),
+              file=sys.stderr, flush=True)
     if not args.no_small:
         out["batched_small"] = batched_small(tune_reps=2 if tr else 0)
         print("[bench] batched small grids done: " + ", ".join(

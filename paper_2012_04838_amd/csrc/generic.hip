@@ -78,7 +78,9 @@ Spec plain_spec(int nf) {
 template <typename T>
 struct GEngine {
   static Shape shape(const Geom& g) { return gen::col_shape(g.N, (int)sizeof(cpx<T>)); }
-  static int x_threads(const Geom& g) {
+  static int x_threads(const Geom&) { return gen::kXLineThreads; }
+  // the line-moment kernel of the statistics: up to 256 threads per line
+  static int moment_threads(const Geom& g) {
     int t = 64;
     while (t < 256 && t < g.N / 2) t *= 2;
     return t;
@@ -225,8 +227,8 @@ struct GEngine {
     const cpx<T>* st = static_cast<const cpx<T>*>(state);
     if (flags & 1) k_shell_sums<T><<<dim3(ns, g.batch), 256, 0, s>>>(st, x.slots, g, shells, ns);
     if (flags & 2) {
-      const int t = x_threads(g);
-      const size_t xl = gen::x_lds_bytes(g.N, 0, (int)sizeof(cpx<T>), t);
+      const int t = moment_threads(g);
+      const size_t xl = gen::moment_lds_bytes(g.N, (int)sizeof(cpx<T>), t);
       // round 1: u1 u2 u3, du1/dx1, du2/dx2 (moments of the last two) and the max
       Spec z1{};
       const int f1[5] = {0, 1, 2, 0, 1}, a1[5] = {0, 0, 0, 1, 2};

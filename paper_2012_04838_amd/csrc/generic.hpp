@@ -332,8 +332,13 @@ struct XLds {
   double* red;
 };
 
+// x pass: one wavefront per (z, y) line (its stage barriers are those of a single wave), so
+// a lane holds at most kXLineEntries half-spectrum entries k = j + 64 q <= K of a field.
+constexpr int kXLineThreads = 64;
+constexpr int kXLineEntries = 8;  // K + 1 <= 512 for every accepted N and dealiasing
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kXLineThreads)
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots,
          DynDev* __restrict__ dyn, Geom g, Factors fx, int shift, int umax) {
   extern __shared__ char lds_raw[];
@@ -374,16 +379,25 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     if (kx == 0) v.y = T(0);
     return v;
   };
-  // inverse transform of the pair (qa, qb); the physical values are Re and Im of the result
+  // inverse transform of the pair (qa, qb); the physical values are Re and Im of the result.
+  // A lane reads its half-spectrum entries k = j + TT q once, all of them before any is used,
+  // and writes position k and its conjugate mirror N - k of the line.
   auto inverse_pair = [&](const Comb& qa, const Comb& qb) -> const cpx<T>* {
-    for (int n = j; n < N; n += TT) {
-      cpx<T> h = {T(0), T(0)};
-      if (n <= K) {
-        h = coeff(qa, n) + mul_i(coeff(qb, n));
-      } else if (n >= N - K) {
-        h = conj(coeff(qa, N - n)) + mul_i(conj(coeff(qb, N - n)));
+    cpx<T> va[kXLineEntries], vb[kXLineEntries];
+#pragma unroll
+    for (int q = 0; q < kXLineEntries; ++q) {
+      const int k = j + TT * q;
+      va[q] = k <= K ? coeff(qa, k) : cpx<T>{T(0), T(0)};
+      vb[q] = k <= K ? coeff(qb, k) : cpx<T>{T(0), T(0)};
+    }
+    for (int n = K + 1 + j; n < N - K; n += TT) L.b0[n] = {T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < kXLineEntries; ++q) {
+      const int k = j + TT * q;
+      if (k <= K) {
+        L.b0[k] = va[q] + mul_i(vb[q]);
+        if (k > 0) L.b0[N - k] = conj(va[q]) + mul_i(conj(vb[q]));
       }
-      L.b0[n] = h;
     }
     __syncthreads();
     return fft<true>(L.b0, L.b1, fx, 1, 0, j, TT, tw);
@@ -468,6 +482,12 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     }
     if (j == 0) atomicMax(&dyn[slot].umax, (unsigned long long)__double_as_longlong(L.red[0]));
   }
+}
+
+// LDS of the line-moment kernel (two line buffers, six real lines, the reduction)
+inline size_t moment_lds_bytes(int N, int csize, int threads) {
+  const size_t real = csize / 2;
+  return 2 * (size_t)N * csize + (size_t)6 * N * real + (N & 1) * real + (size_t)threads * sizeof(double);
 }
 
 inline size_t x_lds_bytes(int N, int S, int csize, int threads) {
