@@ -21,6 +21,7 @@ Ops ops_n256(int);
 Ops ops_n512(int);
 Ops ops_n1024(int);
 Ops ops_general(int);
+int general_x_lines(int n, int precision);
 }  // namespace psdns
 
 using namespace psdns;
@@ -513,6 +514,7 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
   if (!plan) return fail(PSDNS_E_NOMEM, "host allocation of the plan failed");
   plan->p = *p;
   plan->ops = ops_for(p);
+  if (general_plan(p)) plan->ops.sched[0].x_lines = general_x_lines(p->n, p->precision);
   plan->L = make_layout(p);
   hipError_t e = hipGetDevice(&plan->device);
   if (e != hipSuccess) {

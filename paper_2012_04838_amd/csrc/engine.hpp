@@ -1102,7 +1102,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     for (int m = 0; m < E; ++m) bstore<C::STORE>(b, voff, (uint32_t)(TT * m) * rsb, v[m]);
   };
   // inverse z of the next stage input (scaled by 1/N^3) into A field f, and of i kz * it into fd
-  auto inverse_out = [&](cpx<T> (&v)[E], int f, int fd) {
+  auto inverse_out = [&](cpx<T> (&v)[E], int f, int fd, auto&& between) {
     cpx<T> d[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
@@ -1111,20 +1111,29 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     }
     fft<N, E, true>(v, lds, j, tw);
     store_a(f, v);
+    between();
     if (fd >= 0) {
       fft<N, E, true>(d, lds, j, tw);
       store_a(fd, d);
     }
   };
+  auto nothing = [] {};
   // state offsets of element m (false where truncated or outside the kx range)
   auto state_at = [&](int m, uint32_t& vo, uint32_t& so) {
     return valid && compact_at<N, TT>(m, j, voff, rsb, vo, so);
   };
 
+  cpx<T> nx[E];
+  if constexpr (FUSE) fetch(g.S > 0 ? 2 + g.S : 0, nx);
   // scalars: F = -a_hat (a already holds u.grad phi + g.u)
   for (int s = g.S - 1; s >= 0; --s) {
     cpx<T> a[E];
-    fetch(3 + s, a);
+    if constexpr (FUSE) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) a[m] = nx[m];
+    } else {
+      fetch(3 + s, a);
+    }
     fft<N, E, false>(a, lds, j, tw);
     const double dif = sp.diff[3 + s];
     const double exy = exy_of(1 + s);
@@ -1166,14 +1175,19 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
         a[m] = nxt;
       }
     }
-    if constexpr (FUSE) inverse_out(a, 5 + 2 * s, 6 + 2 * s);
+    if constexpr (FUSE) inverse_out(a, 5 + 2 * s, 6 + 2 * s, [&] { fetch(s > 0 ? 2 + s : 0, nx); });
   }
   // velocity: F = P(k) c_hat + A 1_band u_hat
   {
     cpx<T> c1[E], c2[E], c3[E];
 #if PSDNS_FUSED_PF
     // the next component's loads are in flight while the current one is transformed
-    fetch(0, c1);
+    if constexpr (FUSE) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) c1[m] = nx[m];
+    } else {
+      fetch(0, c1);
+    }
     fetch(1, c2);
     fft<N, E, false>(c1, lds, j, tw);
     fetch(2, c3);
@@ -1304,9 +1318,9 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       }
     }
     if constexpr (FUSE) {
-      inverse_out(c1, 0, 3);
-      inverse_out(c2, 1, 4);
-      inverse_out(c3, 2, -1);
+      inverse_out(c1, 0, 3, nothing);
+      inverse_out(c2, 1, 4, nothing);
+      inverse_out(c3, 2, -1, nothing);
     }
   }
 }

@@ -78,7 +78,17 @@ Spec plain_spec(int nf) {
 template <typename T>
 struct GEngine {
   static Shape shape(const Geom& g) { return gen::col_shape(g.N, (int)sizeof(cpx<T>)); }
-  static int x_threads(const Geom&) { return gen::kXLineThreads; }
+  // x pass: P positions per lane of the physical fields, lw lines (wavefronts) per block
+  template <int P>
+  static void launch_x(const Ctx& x, int shift, int umax, hipStream_t s) {
+    const Geom& g = x.g;
+    const int csize = (int)sizeof(cpx<T>);
+    const int lw = gen::x_lines(g.N, csize);
+    const long long lines = (long long)g.N * g.N;
+    gen::k_x_pass<T, P><<<dim3((unsigned)((lines + lw - 1) / lw), g.batch), 64 * lw, gen::x_lds_bytes(g.N, csize, lw),
+                          s>>>(static_cast<cpx<T>*>(x.bbuf), static_cast<const cpx<T>*>(x.tw), x.slots, x.dyn, g,
+                               gen::factor(g.N), shift, umax);
+  }
   // the line-moment kernel of the statistics: up to 256 threads per line
   static int moment_threads(const Geom& g) {
     int t = 64;
@@ -103,11 +113,16 @@ struct GEngine {
         g, gen::factor(g.N), sp, sh.W, sh.TT, shift);
   }
   static void x_pass(const Ctx& x, int shift, int umax, hipStream_t s) {
-    const Geom& g = x.g;
-    const int t = x_threads(g);
-    gen::k_x_pass<T><<<dim3(g.N * g.N, g.batch), t, gen::x_lds_bytes(g.N, g.S, (int)sizeof(cpx<T>), t), s>>>(
-        static_cast<cpx<T>*>(x.bbuf), static_cast<const cpx<T>*>(x.tw), x.slots, x.dyn, g, gen::factor(g.N), shift,
-        umax);
+    switch (gen::x_positions(x.g.N)) {
+      case 2: launch_x<2>(x, shift, umax, s); break;
+      case 4: launch_x<4>(x, shift, umax, s); break;
+      case 6: launch_x<6>(x, shift, umax, s); break;
+      case 8: launch_x<8>(x, shift, umax, s); break;
+      case 10: launch_x<10>(x, shift, umax, s); break;
+      case 12: launch_x<12>(x, shift, umax, s); break;
+      case 14: launch_x<14>(x, shift, umax, s); break;
+      default: launch_x<16>(x, shift, umax, s); break;
+    }
   }
   static void y_forward(const Ctx& x, void* out, int out_fields, int shift, hipStream_t s) {
     const Geom& g = x.g;
@@ -165,9 +180,24 @@ struct GEngine {
     sa.rhs = static_cast<cpx<T>*>(rhs_out);
     sa.fband = x.fband;
     sa.stage = stage;
-    const Shape sh = shape(g);
     TimedLaunch tl(x.timer, KID_ZFWD, s);
-    gen::k_z_forward_update<T><<<dim3((g.KX + sh.W - 1) / sh.W, g.M, g.batch), sh.W * sh.TT, sh.lds, s>>>(
+    switch (gen::zf_positions(g.N, gen::zf_shape(g.N, (int)sizeof(cpx<T>)).TT)) {
+      case 2: launch_zf<2>(x, sa, s); break;
+      case 4: launch_zf<4>(x, sa, s); break;
+      case 6: launch_zf<6>(x, sa, s); break;
+      case 8: launch_zf<8>(x, sa, s); break;
+      case 10: launch_zf<10>(x, sa, s); break;
+      case 12: launch_zf<12>(x, sa, s); break;
+      case 14: launch_zf<14>(x, sa, s); break;
+      default: launch_zf<16>(x, sa, s); break;
+    }
+  }
+  // z forward + update: P positions per thread of each column
+  template <int P>
+  static void launch_zf(const Ctx& x, const gen::GStage<T>& sa, hipStream_t s) {
+    const Geom& g = x.g;
+    const Shape sh = gen::zf_shape(g.N, (int)sizeof(cpx<T>));
+    gen::k_z_forward_update<T, P><<<dim3((g.KX + sh.W - 1) / sh.W, g.M, g.batch), sh.W * sh.TT, sh.lds, s>>>(
         static_cast<const cpx<T>*>(x.abuf), g.sphere ? static_cast<const cpx<T>*>(x.akeep) : nullptr, sa,
         static_cast<const cpx<T>*>(x.tw), x.slots, x.dyn, g, gen::factor(g.N), sh.W, sh.TT);
   }
@@ -275,10 +305,24 @@ struct GEngine {
                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_y_forward<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_x_pass<T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_z_forward_update<T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    for (const void* k : {reinterpret_cast<const void*>(&gen::k_x_pass<T, 2>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 4>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 6>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 8>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 10>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 12>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 14>),
+                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 16>)})
+      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    for (const void* k : {reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 2>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 4>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 6>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 8>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 10>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 12>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 14>),
+                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 16>)})
+      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_x_moments<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
   }
@@ -309,5 +353,6 @@ struct GEngine {
 }  // namespace
 
 Ops ops_general(int precision) { return precision == 32 ? GEngine<float>::ops() : GEngine<double>::ops(); }
+int general_x_lines(int n, int precision) { return gen::x_lines(n, precision == 32 ? 8 : 16); }
 
 }  // namespace psdns

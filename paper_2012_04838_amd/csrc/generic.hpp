@@ -125,10 +125,11 @@ __device__ __forceinline__ void stage(const cpx<T>* src, cpx<T>* dst, int W, int
   }
 }
 
-// Full N-point transform of the W columns held in b0 (all threads of the block call it).
+// Full N-point transform of the W columns held in b0 (all threads of the block call it, or
+// all lanes of one wavefront with Sync = WaveSync when the wave owns its lines alone).
 // Returns the buffer (b0 or b1) that holds the result in natural order.
-template <bool INV, typename T>
-__device__ cpx<T>* fft(cpx<T>* b0, cpx<T>* b1, const Factors& f, int W, int c, int j, int TT,
+template <bool INV, typename Sync = BlockSync, typename T>
+__device__ __forceinline__ cpx<T>* fft(cpx<T>* b0, cpx<T>* b1, const Factors& f, int W, int c, int j, int TT,
                        const cpx<T>* __restrict__ tw) {
   cpx<T>* src = b0;
   cpx<T>* dst = b1;
@@ -145,7 +146,7 @@ __device__ cpx<T>* fft(cpx<T>* b0, cpx<T>* b1, const Factors& f, int W, int c, i
       case 11: stage<11, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
       default: stage<13, INV>(src, dst, W, c, j, TT, f.n, NS, tw); break;
     }
-    __syncthreads();
+    Sync::sync();
     NS *= R;
     cpx<T>* t = src;
     src = dst;
@@ -317,44 +318,65 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ aout, int a_fi
 }
 
 // ---------------------------------------------------------------------------
-// x pass: one (z, y) line per block.  Pairs of real fields travel as one complex line
-// h = f + i g (half-spectrum entries kx <= K, their conjugates at N - kx); the physical
-// fields are kept in LDS, the products u x omega and u.grad phi_s + g_s.u formed pointwise
-// and transformed back, kx <= K written in place into the first F fields of B.  shift
-// multiplies the inputs by exp(i pi kx / N) and the outputs by its conjugate; with umax
-// the block's max |u1|+|u2|+|u3| joins the slot's maximum (Eq. (10)).
+// x pass: one wavefront per (z, y) line, lw lines per block.  Pairs of real fields travel as
+// one complex line h = f + i g (half-spectrum entries kx <= K, their conjugates at N - kx);
+// the products u x omega and u.grad phi_s + g_s.u are formed pointwise and transformed back,
+// kx <= K written in place into the first F fields of B.  shift multiplies the inputs by
+// exp(i pi kx / N) and the outputs by its conjugate; with umax the line's
+// max |u1|+|u2|+|u3| joins the slot's maximum (Eq. (10)).
+//
+// The block copies the root table (stage twiddles, odd-radix roots, half-cell shifts) to
+// LDS once for its lines; each wave then owns two line buffers and synchronises its
+// transform stages alone.  Lane j keeps positions n = j + 64 q (q < P) of the physical
+// fields in registers: u1 u2 u3, and c1 c2 c3 while they are formed; c1 and c2 are
+// transformed as soon as they exist, and each scalar product then pairs with the field
+// before it, so that at most six fields are live.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct XLds {
-  cpx<T>* b0;
-  cpx<T>* b1;
-  T* phys;  // [6 + S][N]: u1 u2 u3 c1 c2 c3 (omega while it is formed) a_0 .. a_{S-1}
-  double* red;
-};
+constexpr int kXMaxLines = 4;     // lines (wavefronts) per block
 
-// x pass: one wavefront per (z, y) line (its stage barriers are those of a single wave), so
-// a lane holds at most kXLineEntries half-spectrum entries k = j + 64 q <= K of a field.
-constexpr int kXLineThreads = 64;
-constexpr int kXLineEntries = 8;  // K + 1 <= 512 for every accepted N and dealiasing
+// positions per lane of the physical fields of an N-point line (instantiated in steps of 2);
+// the half spectrum kx <= K <= N/2 then needs at most P/2 + 1 entries per lane
+inline int x_positions(int N) {
+  const int p = (N + 63) / 64;
+  return p < 2 ? 2 : (p + 1) / 2 * 2;
+}
+// lines per block: as many as fit two blocks in the 160 KB of a CU
+inline int x_lines(int N, int csize) {
+  int lw = kXMaxLines;
+  while (lw > 1 && ((size_t)root_table_entries(N) + (size_t)lw * 2 * N) * csize > 80 * 1024) lw /= 2;
+  return lw;
+}
+inline size_t x_lds_bytes(int N, int csize, int lw) {
+  return ((size_t)root_table_entries(N) + (size_t)lw * 2 * N) * csize;
+}
 
-template <typename T>
-__global__ void __launch_bounds__(kXLineThreads)
-k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots,
+// waves per SIMD the register allocation of the x pass aims at (six fields of P positions
+// per lane next to the transform stages)
+template <typename T, int P>
+constexpr int x_waves() {
+  return sizeof(T) == 4 ? (P <= 4 ? 4 : P <= 12 ? 3 : 2) : (P <= 10 ? 2 : 1);
+}
+
+template <typename T, int P>
+__global__ void __launch_bounds__(64 * kXMaxLines, (x_waves<T, P>()))
+k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
          DynDev* __restrict__ dyn, Geom g, Factors fx, int shift, int umax) {
   extern __shared__ char lds_raw[];
   const int N = g.N, S = g.S, K = g.K;
-  XLds<T> L;
-  L.b0 = reinterpret_cast<cpx<T>*>(lds_raw);
-  L.b1 = L.b0 + N;
-  L.phys = reinterpret_cast<T*>(L.b1 + N);
-  L.red = reinterpret_cast<double*>(L.phys + (size_t)(6 + S) * N + (N & 1));
+  const int nt = (int)root_table_entries(N);
+  cpx<T>* tw = reinterpret_cast<cpx<T>*>(lds_raw);
   const int slot = blockIdx.y;
-  if (!slots[slot].active) return;
   const SlotDev& sp = slots[slot];
-  const long long line = blockIdx.x;  // z * N + y
-  const int TT = blockDim.x, j = threadIdx.x;
+  if (!sp.active) return;
+  for (int i = threadIdx.x; i < nt; i += blockDim.x) tw[i] = tw_g[i];
+  __syncthreads();
+  const int lw = blockDim.x / 64, wv = threadIdx.x / 64, j = threadIdx.x % 64;
+  const long long line = (long long)blockIdx.x * lw + wv;  // z * N + y
+  if (line >= (long long)N * N) return;
+  cpx<T>* b0 = tw + nt + (size_t)wv * 2 * N;
+  cpx<T>* b1 = b0 + N;
   cpx<T>* lbase = bbuf + (long long)slot * g.FB * g.b_field + line * g.PX;
-  // entry kx of the combination (field fa, optional i kx factor, sign)
+  // entry kx of the combination (field f, optional i kx factor, sign)
   auto entry = [&](int f, bool dx, T sg, int kx) {
     cpx<T> v = lbase[(long long)f * g.b_field + kx];
     if (dx) v = mul_is(v, T(kx));
@@ -362,8 +384,8 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     if (shift) v = cmul(v, shift_of(tw, N, kx));
     return v;
   };
-  // a_e (sa x) + b_e: value of real field (fa1 (+ i kx) ... ) at kx, as a combination of up to
-  // two B fields: first (f1, dx1, s1), second (f2, dx2, s2) with f2 < 0 for none
+  // value of a real field at kx as a combination of up to two B fields: first (f1, dx1, s1),
+  // second (f2, dx2, s2) with f2 < 0 for none
   struct Comb {
     int f1;
     bool dx1;
@@ -379,108 +401,174 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw, const SlotDev
     if (kx == 0) v.y = T(0);
     return v;
   };
-  // inverse transform of the pair (qa, qb); the physical values are Re and Im of the result.
-  // A lane reads its half-spectrum entries k = j + TT q once, all of them before any is used,
-  // and writes position k and its conjugate mirror N - k of the line.
-  auto inverse_pair = [&](const Comb& qa, const Comb& qb) -> const cpx<T>* {
-    cpx<T> va[kXLineEntries], vb[kXLineEntries];
-#pragma unroll
-    for (int q = 0; q < kXLineEntries; ++q) {
-      const int k = j + TT * q;
-      va[q] = k <= K ? coeff(qa, k) : cpx<T>{T(0), T(0)};
-      vb[q] = k <= K ? coeff(qb, k) : cpx<T>{T(0), T(0)};
-    }
-    for (int n = K + 1 + j; n < N - K; n += TT) L.b0[n] = {T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < kXLineEntries; ++q) {
-      const int k = j + TT * q;
-      if (k <= K) {
-        L.b0[k] = va[q] + mul_i(vb[q]);
-        if (k > 0) L.b0[N - k] = conj(va[q]) + mul_i(conj(vb[q]));
-      }
-    }
-    __syncthreads();
-    return fft<true>(L.b0, L.b1, fx, 1, 0, j, TT, tw);
-  };
-  T* u1 = L.phys;
-  T* u2 = u1 + N;
-  T* u3 = u2 + N;
-  T* c1 = u3 + N;
-  T* c2 = c1 + N;
-  T* c3 = c2 + N;
-  T* as = c3 + N;
-  const Comb none = {-1, false, T(0), -1, false, T(0)};
-  // B fields: 0 u1, 1 u2, 2 u3, 3 omega1, 4 dz u1, 5 dy u1, 6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s
-  const cpx<T>* r = inverse_pair({0, false, T(1), -1, false, T(0)}, {1, false, T(1), -1, false, T(0)});
-  for (int n = j; n < N; n += TT) {
-    u1[n] = r[n].x;
-    u2[n] = r[n].y;
-  }
-  __syncthreads();
-  r = inverse_pair({2, false, T(1), -1, false, T(0)}, {3, false, T(1), -1, false, T(0)});
-  for (int n = j; n < N; n += TT) {
-    u3[n] = r[n].x;
-    c1[n] = r[n].y;  // omega1 until c is formed
-  }
-  __syncthreads();
-  // omega2 = dz u1 - dx u3, omega3 = dx u2 - dy u1
-  r = inverse_pair({4, false, T(1), 2, true, T(-1)}, {1, true, T(1), 5, false, T(-1)});
+  // The transforms of a line run as one sequence of jobs through a single forward transform
+  // (an inverse transform is the conjugate of the forward transform of the conjugate):
+  //   0  inverse (u1, u2)
+  //   1  inverse (u3, omega1), omega1 into C
+  //   2  inverse (omega2, omega3), then c = u x omega into A, B, C
+  //   3  forward of the pair (A, B) into output fields (fa, fb), fb < 0 for A alone
+  //   4  inverse (dx phi_s, dy phi_s), then a_s = u1 dx phi_s + u2 dy phi_s + g_s.u into B
+  //   5  inverse dz phi_s, then a_s += u3 dz phi_s
+  // c1 and c2 are transformed first; c3 then waits in A for a_0, and every second scalar
+  // product waits in A for the next.  For an inverse job a lane reads its half-spectrum entries
+  // k = j + 64 q once, all of them before any is used, and writes position k and its conjugate
+  // mirror N - k of the line.
+  constexpr int Q = P / 2 + 1;
+  T u1[P], u2[P], u3[P], A[P], B[P], C[P];
   double mx = 0.0;
-  for (int n = j; n < N; n += TT) {
-    const T w1 = c1[n], w2 = r[n].x, w3 = r[n].y;
-    const T a = u1[n], b = u2[n], c = u3[n];
-    c1[n] = b * w3 - c * w2;
-    c2[n] = c * w1 - a * w3;
-    c3[n] = a * w2 - b * w1;
-    const double sm = fabs((double)a) + fabs((double)b) + fabs((double)c);
-    mx = (sm > mx || sm != sm) ? sm : mx;
-  }
-  __syncthreads();
-  for (int s = 0; s < S; ++s) {
-    const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
-    r = inverse_pair({6 + 3 * s, true, T(1), -1, false, T(0)}, {7 + 3 * s, false, T(1), -1, false, T(0)});
-    for (int n = j; n < N; n += TT)
-      as[s * N + n] = u1[n] * r[n].x + u2[n] * r[n].y + (g0 * u1[n] + g1 * u2[n] + g2 * u3[n]);
-    __syncthreads();
-    r = inverse_pair({8 + 3 * s, false, T(1), -1, false, T(0)}, none);
-    for (int n = j; n < N; n += TT) as[s * N + n] += u3[n] * r[n].x;
-    __syncthreads();
-  }
-  // forward: pairs of the F output fields c1 c2 c3 a_0 .. a_{S-1}
-  const int F = 3 + S;
-  auto out_field = [&](int f) -> const T* { return f < 3 ? c1 + (size_t)f * N : as + (size_t)(f - 3) * N; };
-  for (int fp = 0; fp < F; fp += 2) {
-    const int fq = fp + 1 < F ? fp + 1 : -1;
-    const T* p = out_field(fp);
-    const T* q = fq >= 0 ? out_field(fq) : nullptr;
-    for (int n = j; n < N; n += TT) L.b0[n] = {p[n], q ? q[n] : T(0)};
-    __syncthreads();
-    const cpx<T>* Z = fft<false>(L.b0, L.b1, fx, 1, 0, j, TT, tw);
-    for (int k = j; k <= K; k += TT) {
-      const cpx<T> zk = Z[k], zc = conj(Z[(N - k) % N]);
-      cpx<T> P = T(0.5) * (zk + zc);
-      cpx<T> Q = mul_mi(T(0.5) * (zk - zc));
-      if (shift) {
-        const cpx<T> e = conj(shift_of(tw, N, k));
-        P = cmul(P, e);
-        Q = cmul(Q, e);
+  int job = 0, s = 0, fa = 0, fb = 1, pend = -1;
+  while (job >= 0) {
+    if (job == 3) {
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int n = j + 64 * i;
+        if (n < N) b0[n] = {A[i], fb >= 0 ? B[i] : T(0)};
       }
-      lbase[(long long)fp * g.b_field + k] = P;
-      if (fq >= 0) lbase[(long long)fq * g.b_field + k] = Q;
+    } else {
+      Comb qa = {-1, false, T(0), -1, false, T(0)}, qb = qa;
+      // B fields: 0 u1, 1 u2, 2 u3, 3 omega1, 4 dz u1, 5 dy u1, 6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s
+      switch (job) {
+        case 0: qa = {0, false, T(1), -1, false, T(0)}; qb = {1, false, T(1), -1, false, T(0)}; break;
+        case 1: qa = {2, false, T(1), -1, false, T(0)}; qb = {3, false, T(1), -1, false, T(0)}; break;
+        // omega2 = dz u1 - dx u3, omega3 = dx u2 - dy u1
+        case 2: qa = {4, false, T(1), 2, true, T(-1)}; qb = {1, true, T(1), 5, false, T(-1)}; break;
+        case 4: qa = {6 + 3 * s, true, T(1), -1, false, T(0)}; qb = {7 + 3 * s, false, T(1), -1, false, T(0)}; break;
+        default: qa = {8 + 3 * s, false, T(1), -1, false, T(0)}; break;
+      }
+      cpx<T> va[Q], vb[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int k = j + 64 * q;
+        va[q] = k <= K ? coeff(qa, k) : cpx<T>{T(0), T(0)};
+        vb[q] = k <= K ? coeff(qb, k) : cpx<T>{T(0), T(0)};
+      }
+      for (int n = K + 1 + j; n < N - K; n += 64) b0[n] = {T(0), T(0)};
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int k = j + 64 * q;
+        if (k <= K) {
+          b0[k] = conj(va[q] + mul_i(vb[q]));
+          if (k > 0) b0[N - k] = conj(conj(va[q]) + mul_i(conj(vb[q])));
+        }
+      }
     }
-    __syncthreads();
+    WaveSync::sync();
+    const cpx<T>* r = fft<false, WaveSync>(b0, b1, fx, 1, 0, j, 64, tw);
+    if (job == 3) {
+      for (int k = j; k <= K; k += 64) {
+        const cpx<T> zk = r[k], zc = conj(r[(N - k) % N]);
+        cpx<T> Pv = T(0.5) * (zk + zc);
+        cpx<T> Qv = mul_mi(T(0.5) * (zk - zc));
+        if (shift) {
+          const cpx<T> e = conj(shift_of(tw, N, k));
+          Pv = cmul(Pv, e);
+          Qv = cmul(Qv, e);
+        }
+        lbase[(long long)fa * g.b_field + k] = Pv;
+        if (fb >= 0) lbase[(long long)fb * g.b_field + k] = Qv;
+      }
+    } else {
+      // physical values of the pair: Re and Im of the inverse, the conjugate of r
+      T rx[P], ry[P];
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const int n = j + 64 * i;
+        rx[i] = n < N ? r[n].x : T(0);
+        ry[i] = n < N ? -r[n].y : T(0);
+      }
+      switch (job) {
+        case 0:
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            u1[i] = rx[i];
+            u2[i] = ry[i];
+          }
+          break;
+        case 1:
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            u3[i] = rx[i];
+            C[i] = ry[i];
+          }
+          break;
+        case 2:
+#pragma unroll
+          for (int i = 0; i < P; ++i) {
+            const T w1 = C[i], w2 = rx[i], w3 = ry[i];
+            const T a = u1[i], b = u2[i], c = u3[i];
+            A[i] = b * w3 - c * w2;
+            B[i] = c * w1 - a * w3;
+            C[i] = a * w2 - b * w1;
+            const double sm = fabs((double)a) + fabs((double)b) + fabs((double)c);
+            mx = (sm > mx || sm != sm) ? sm : mx;
+          }
+          break;
+        case 4: {
+          const T g0 = T(sp.g[s][0]), g1 = T(sp.g[s][1]), g2 = T(sp.g[s][2]);
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+            B[i] = u1[i] * rx[i] + u2[i] * ry[i] + (g0 * u1[i] + g1 * u2[i] + g2 * u3[i]);
+          break;
+        }
+        default:
+#pragma unroll
+          for (int i = 0; i < P; ++i) B[i] += u3[i] * rx[i];
+          break;
+      }
+    }
+    WaveSync::sync();
+    // the next job
+    switch (job) {
+      case 0: job = 1; break;
+      case 1: job = 2; break;
+      case 2: job = 3; fa = 0; fb = 1; break;
+      case 3:
+        if (fa == 0) {  // c1, c2 done: c3 (field 2) waits for a_0
+#pragma unroll
+          for (int i = 0; i < P; ++i) A[i] = C[i];
+          pend = 2;
+        } else {
+          pend = -1;
+        }
+        if (s < S) {
+          job = 4;
+        } else if (pend >= 0) {
+          fa = pend;
+          fb = -1;
+          pend = -1;
+        } else {
+          job = -1;
+        }
+        break;
+      case 4: job = 5; break;
+      default:
+        if (pend >= 0) {  // the pending field and a_s
+          fa = pend;
+          fb = 3 + s;
+          job = 3;
+        } else {  // a_s waits for a_{s+1}, or goes alone after the last scalar
+#pragma unroll
+          for (int i = 0; i < P; ++i) A[i] = B[i];
+          pend = 3 + s;
+          if (s + 1 < S) {
+            job = 4;
+          } else {
+            fa = pend;
+            fb = -1;
+            job = 3;
+          }
+        }
+        ++s;
+        break;
+    }
   }
   if (umax) {
-    L.red[j] = mx;
-    __syncthreads();
-    for (int o = TT / 2; o > 0; o >>= 1) {
-      if (j < o) {
-        const double a = L.red[j], b = L.red[j + o];
-        L.red[j] = (b > a || b != b) ? b : a;
-      }
-      __syncthreads();
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double b = __shfl_xor(mx, o);
+      mx = (b > mx || b != b) ? b : mx;
     }
-    if (j == 0) atomicMax(&dyn[slot].umax, (unsigned long long)__double_as_longlong(L.red[0]));
+    if (j == 0) atomicMax(&dyn[slot].umax, (unsigned long long)__double_as_longlong(mx));
   }
 }
 
@@ -490,10 +578,6 @@ inline size_t moment_lds_bytes(int N, int csize, int threads) {
   return 2 * (size_t)N * csize + (size_t)6 * N * real + (N & 1) * real + (size_t)threads * sizeof(double);
 }
 
-inline size_t x_lds_bytes(int N, int S, int csize, int threads) {
-  const size_t real = csize / 2;
-  return 2 * (size_t)N * csize + (size_t)(6 + S) * N * real + (N & 1) * real + (size_t)threads * sizeof(double);
-}
 
 // ---------------------------------------------------------------------------
 // z forward + assembly + stage update.  Each field is transformed along z; with the phase
@@ -553,8 +637,28 @@ __device__ __forceinline__ cpx<T> update(const GStage<T>& a, long long o, cpx<T>
   return nxt;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(1024)
+// Launch shape of the z-forward pass: blocks of at most 512 threads (64 columns of threads in
+// FP32, 128 in FP64, and 8 or 4 columns), so that a thread may hold its P positions
+// n = j + TT m of three fields (c1, c2 and the current one) in registers.
+inline Shape zf_shape(int N, int csize) {
+  Shape s{};
+  s.TT = csize == 8 ? 64 : 128;
+  if (s.TT > N / 2) s.TT = N / 2;
+  s.W = csize == 8 ? 8 : 4;
+  while (s.W > 1 && 2 * (size_t)s.W * N * csize > 150 * 1024) s.W /= 2;
+  s.lds = 2 * (size_t)s.W * N * csize;
+  return s;
+}
+inline int zf_positions(int N, int TT) {
+  const int p = (N + TT - 1) / TT;
+  return p < 2 ? 2 : (p + 1) / 2 * 2;
+}
+
+// The fields go through one transform call in a loop (scalars 0 .. S-1, each updated as soon
+// as it is transformed, then the velocity components), each field once, or twice with the
+// shift (abuf, then akeep).
+template <typename T, int P>
+__global__ void __launch_bounds__(512)
 k_z_forward_update(const cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ akeep, GStage<T> sa,
                    const cpx<T>* __restrict__ tw, const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn,
                    Geom g, Factors fz, int W, int TT) {
@@ -574,89 +678,83 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ a
   const cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
   const cpx<T>* kslot = akeep ? akeep + (long long)slot * g.F * g.a_field : nullptr;
   const long long sslot = (long long)slot * g.F * g.st_field;
-  const int np = (N - j + TT - 1) / TT;  // positions n = j + TT m of this thread
-  // transformed (and, with the shift, averaged) field f at this thread's positions
-  auto forward = [&](int f, cpx<T> (&v)[kMaxPerThread]) {
-    for (int n = j; n < N; n += TT)
-      b0[n * W + c] = valid ? aslot[(long long)f * g.a_field + a_row(n, kyc, M, g.PX) + kx] : cpx<T>{T(0), T(0)};
-    __syncthreads();
-    const cpx<T>* r = fft<false>(b0, b1, fz, W, c, j, TT, tw);
-#pragma unroll
-    for (int m = 0; m < kMaxPerThread; ++m)
-      if (m < np) v[m] = r[(j + TT * m) * W + c];
-    __syncthreads();
-    if (kslot) {
-      for (int n = j; n < N; n += TT)
-        b0[n * W + c] = valid ? kslot[(long long)f * g.a_field + a_row(n, kyc, M, g.PX) + kx] : cpx<T>{T(0), T(0)};
-      __syncthreads();
-      r = fft<false>(b0, b1, fz, W, c, j, TT, tw);
-#pragma unroll
-      for (int m = 0; m < kMaxPerThread; ++m)
-        if (m < np) {
-          const int kz = wave(j + TT * m, N);
-          // akeep holds the unshifted product, abuf the shifted one
-          v[m] = T(0.5) * (r[(j + TT * m) * W + c] + cmul(v[m], conj(shift_of(tw, N, kz))));
-        }
-      __syncthreads();
-    }
-  };
   auto mode_of = [&](int m, long long& o, double& k2) {
-    if (!valid || m >= np) return false;
-    const int kz = wave(j + TT * m, N), kc = compact(kz, K, M);
+    const int n = j + TT * m;
+    if (!valid || n >= N) return false;
+    const int kz = wave(n, N), kc = compact(kz, K, M);
     if (kc < 0 || !retained(g, kx, ky, kz)) return false;
     o = st_row(kc, kyc, M, g.PX) + kx;
     k2 = double(kx) * kx + double(ky) * ky + double(kz) * kz;
     return true;
   };
-  for (int s = 0; s < g.S; ++s) {
-    cpx<T> a[kMaxPerThread];
-    forward(3 + s, a);
-    const double dif = sp.diff[3 + s];
+  auto stage_of = [&](int f) {
     GStage<T> q = sa;
-    const long long foff = sslot + (long long)(3 + s) * g.st_field;
+    const long long foff = sslot + (long long)f * g.st_field;
     q.yn += foff;
     q.acc += foff;
     q.ys += foff;
     q.sin += foff;
     q.rhs += sa.stage < 0 ? foff : 0;
+    return q;
+  };
+  const int S = g.S, per = kslot ? 2 : 1;
+  cpx<T> v[P], c1[P], c2[P];
+  for (int t = 0; t < (S + 3) * per; ++t) {
+    const int fi = t / per, half = t % per;
+    const int f = fi < S ? 3 + fi : fi - S;  // A field: scalar fi, or velocity component fi - S
+    const cpx<T>* src = (half ? kslot : aslot) + (long long)f * g.a_field;
+    for (int n = j; n < N; n += TT)
+      b0[n * W + c] = valid ? src[a_row(n, kyc, M, g.PX) + kx] : cpx<T>{T(0), T(0)};
+    __syncthreads();
+    const cpx<T>* r = fft<false>(b0, b1, fz, W, c, j, TT, tw);
 #pragma unroll
-    for (int m = 0; m < kMaxPerThread; ++m) {
-      long long o;
-      double k2;
-      if (m < np && mode_of(m, o, k2)) {
-        const cpx<T> F = k2 == 0.0 ? cpx<T>{T(0), T(0)} : cpx<T>{-a[m].x, -a[m].y};
-        update(q, o, F, dif * k2, h, expl);
+    for (int m = 0; m < P; ++m) {
+      const int n = j + TT * m;
+      if (n < N) {
+        const cpx<T> x = r[n * W + c];
+        // with the shift abuf holds the shifted product and akeep the unshifted one
+        v[m] = half ? T(0.5) * (x + cmul(v[m], conj(shift_of(tw, N, wave(n, N))))) : x;
       }
     }
+    __syncthreads();
+    if (half + 1 < per) continue;
+    if (fi < S) {
+      // scalar: F = -a_hat
+      const double dif = sp.diff[f];
+      const GStage<T> q = stage_of(f);
+#pragma unroll
+      for (int m = 0; m < P; ++m) {
+        long long o;
+        double k2;
+        if (mode_of(m, o, k2)) {
+          const cpx<T> F = k2 == 0.0 ? cpx<T>{T(0), T(0)} : cpx<T>{-v[m].x, -v[m].y};
+          update(q, o, F, dif * k2, h, expl);
+        }
+      }
+    } else if (f == 0) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) c1[m] = v[m];
+    } else if (f == 1) {
+#pragma unroll
+      for (int m = 0; m < P; ++m) c2[m] = v[m];
+    }
   }
-  cpx<T> c1[kMaxPerThread], c2[kMaxPerThread], c3[kMaxPerThread];
-  forward(0, c1);
-  forward(1, c2);
-  forward(2, c3);
+  // velocity (v holds c3): F = P(k) c_hat + A 1_band u_hat (+ the stochastic band term)
   int kfs = 0;
   while ((double)(kfs + 1) * (kfs + 1) <= sp.kf2) ++kfs;
   if (kfs > K) kfs = K;
   const bool stoch = sp.forcing == PSDNS_FORCING_STOCHASTIC || sp.forcing == PSDNS_FORCING_ALVELIUS;
-  GStage<T> q[3];
-  for (int f = 0; f < 3; ++f) {
-    q[f] = sa;
-    const long long foff = sslot + (long long)f * g.st_field;
-    q[f].yn += foff;
-    q[f].acc += foff;
-    q[f].ys += foff;
-    q[f].sin += foff;
-    q[f].rhs += sa.stage < 0 ? foff : 0;
-  }
+  const GStage<T> q0 = stage_of(0), q1 = stage_of(1), q2 = stage_of(2);
 #pragma unroll
-  for (int m = 0; m < kMaxPerThread; ++m) {
+  for (int m = 0; m < P; ++m) {
     long long o;
     double k2;
-    if (!(m < np && mode_of(m, o, k2))) continue;
+    if (!mode_of(m, o, k2)) continue;
     const int kz = wave(j + TT * m, N);
     cpx<T> F1 = {T(0), T(0)}, F2 = F1, F3 = F1;
     const bool band = k2 > 0.0 && k2 <= sp.kf2;
     if (k2 > 0.0) {
-      cpx<T> p1 = c1[m], p2 = c2[m], p3 = c3[m];
+      cpx<T> p1 = c1[m], p2 = c2[m], p3 = v[m];
       if (stoch && band) {
         const double* e = sa.fband + ((long long)slot * kStochCand + kx + (kfs + 1) * ((ky + kfs) + (2 * kfs + 1) * (kz + kfs))) * 12 + 6;
         p1 = p1 + cpx<T>{T(e[0]), T(e[1])};
@@ -671,15 +769,15 @@ k_z_forward_update(const cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ a
       F3 = p3 - (kzt * ik2) * kdc;
       if (A != 0.0 && band) {
         const T At = T(A);
-        F1 = F1 + At * q[0].sin[o];
-        F2 = F2 + At * q[1].sin[o];
-        F3 = F3 + At * q[2].sin[o];
+        F1 = F1 + At * q0.sin[o];
+        F2 = F2 + At * q1.sin[o];
+        F3 = F3 + At * q2.sin[o];
       }
     }
     const double lk2 = sp.nu * k2;
-    update(q[0], o, F1, lk2, h, expl);
-    update(q[1], o, F2, lk2, h, expl);
-    update(q[2], o, F3, lk2, h, expl);
+    update(q0, o, F1, lk2, h, expl);
+    update(q1, o, F2, lk2, h, expl);
+    update(q2, o, F3, lk2, h, expl);
   }
 }
 
