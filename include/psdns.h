@@ -315,6 +315,14 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
  * results are those of any schedule (the same transforms; only the association order of the
  * butterflies differs).  A captured step graph is dropped and re-captured. */
 psdns_status psdns_set_pass_schedules(psdns_plan* plan, const int32_t* sched);
+/* Run this plan on the general (mixed-radix) kernels even where the tuned power-of-two
+ * kernels apply (a power-of-two n with the 2/3 rule): both families read and write the same
+ * state and workspace layouts and compute the same right-hand side (Sec. 2.2), so the one
+ * cross-checks the other on one grid, up to the largest lines (n = 1024).  From then on the
+ * plan reports general = 1, has one schedule, and psdns_pressure returns
+ * PSDNS_E_UNSUPPORTED.  No-op on a plan that already runs the general kernels; a captured
+ * step graph is dropped.  There is no way back. */
+psdns_status psdns_use_general_kernels(psdns_plan* plan);
 /* Autotuner per pass: times the passes of `reps` RK stages with each schedule (the trial of
  * psdns_tune, and the standalone z inverse) with an event pair around every kernel and
  * selects for each pass the lowest-index schedule within 1% of its fastest (schedules that

@@ -262,6 +262,7 @@ struct psdns_plan {
   double graph_dt = 0.0;
   bool graph_hold = false;  // captured with the hold forcing's step structure
   bool graph_expl = false;  // captured with the unfused stages of an explicit-integrator slot
+  bool general = false;     // runs the general kernels (ops_general)
   int psched[kNumPasses] = {0, 0, 0, 0, 0};  // schedule of each pass (psdns_set_pass_schedules)
 };
 
@@ -514,7 +515,8 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
   if (!plan) return fail(PSDNS_E_NOMEM, "host allocation of the plan failed");
   plan->p = *p;
   plan->ops = ops_for(p);
-  if (general_plan(p)) plan->ops.sched[0].x_lines = general_x_lines(p->n, p->precision);
+  plan->general = general_plan(p);
+  if (plan->general) plan->ops.sched[0].x_lines = general_x_lines(p->n, p->precision);
   plan->L = make_layout(p);
   hipError_t e = hipGetDevice(&plan->device);
   if (e != hipSuccess) {
@@ -608,7 +610,7 @@ psdns_status psdns_plan_get_info(const psdns_plan* plan, psdns_plan_info* out) {
   out->workspace_bytes = (int64_t)plan->L.ws_bytes;
   out->plan_bytes = (int64_t)plan_table_bytes(&plan->p);
   out->dealias = plan->p.dealias;
-  out->general = general_plan(&plan->p) ? 1 : 0;
+  out->general = plan->general ? 1 : 0;
   out->elems_col = plan->ops.sched[plan->psched[kPassYInverse]].ec;
   out->elems_x = plan->ops.sched[plan->psched[kPassX]].ex;
   out->n_schedules = plan->ops.nsched;
@@ -651,6 +653,20 @@ psdns_status psdns_set_pass_schedules(psdns_plan* plan, const int32_t* sched) {
     plan->graph_exec = nullptr;
   }
   for (int p = 0; p < kNumPasses; ++p) plan->psched[p] = sched[p];
+  return PSDNS_OK;
+}
+
+psdns_status psdns_use_general_kernels(psdns_plan* plan) {
+  if (psdns_status s = check_plan(plan)) return s;
+  if (plan->general) return PSDNS_OK;
+  if (plan->graph_exec) {
+    HIP_TRY(hipGraphExecDestroy(plan->graph_exec));
+    plan->graph_exec = nullptr;
+  }
+  plan->ops = ops_general(plan->p.precision);
+  plan->ops.sched[0].x_lines = general_x_lines(plan->p.n, plan->p.precision);
+  for (int p = 0; p < kNumPasses; ++p) plan->psched[p] = 0;
+  plan->general = true;
   return PSDNS_OK;
 }
 

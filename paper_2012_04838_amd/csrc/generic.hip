@@ -2,6 +2,8 @@
 // statistics and the state conversions of plans whose N is not a power of two or that use
 // the paper's phase-shift dealiasing.  N, K and the retained set come from the plan's
 // geometry at run time; one schedule.
+#include <type_traits>
+
 #include "engine.hpp"
 #include "generic.hpp"
 
@@ -75,6 +77,29 @@ Spec plain_spec(int nf) {
   return s;
 }
 
+// fn(std::integral_constant<int, P>) for the runtime count p of positions per thread (1..16)
+template <typename Fn>
+void with_positions(int p, Fn&& fn) {
+  switch (p) {
+    case 1: fn(std::integral_constant<int, 1>{}); break;
+    case 2: fn(std::integral_constant<int, 2>{}); break;
+    case 3: fn(std::integral_constant<int, 3>{}); break;
+    case 4: fn(std::integral_constant<int, 4>{}); break;
+    case 5: fn(std::integral_constant<int, 5>{}); break;
+    case 6: fn(std::integral_constant<int, 6>{}); break;
+    case 7: fn(std::integral_constant<int, 7>{}); break;
+    case 8: fn(std::integral_constant<int, 8>{}); break;
+    case 9: fn(std::integral_constant<int, 9>{}); break;
+    case 10: fn(std::integral_constant<int, 10>{}); break;
+    case 11: fn(std::integral_constant<int, 11>{}); break;
+    case 12: fn(std::integral_constant<int, 12>{}); break;
+    case 13: fn(std::integral_constant<int, 13>{}); break;
+    case 14: fn(std::integral_constant<int, 14>{}); break;
+    case 15: fn(std::integral_constant<int, 15>{}); break;
+    default: fn(std::integral_constant<int, 16>{}); break;
+  }
+}
+
 template <typename T>
 struct GEngine {
   static Shape shape(const Geom& g) { return gen::col_shape(g.N, (int)sizeof(cpx<T>)); }
@@ -113,16 +138,7 @@ struct GEngine {
         g, gen::factor(g.N), sp, sh.W, sh.TT, shift);
   }
   static void x_pass(const Ctx& x, int shift, int umax, hipStream_t s) {
-    switch (gen::x_positions(x.g.N)) {
-      case 2: launch_x<2>(x, shift, umax, s); break;
-      case 4: launch_x<4>(x, shift, umax, s); break;
-      case 6: launch_x<6>(x, shift, umax, s); break;
-      case 8: launch_x<8>(x, shift, umax, s); break;
-      case 10: launch_x<10>(x, shift, umax, s); break;
-      case 12: launch_x<12>(x, shift, umax, s); break;
-      case 14: launch_x<14>(x, shift, umax, s); break;
-      default: launch_x<16>(x, shift, umax, s); break;
-    }
+    with_positions(gen::x_positions(x.g.N), [&](auto p) { launch_x<decltype(p)::value>(x, shift, umax, s); });
   }
   static void y_forward(const Ctx& x, void* out, int out_fields, int shift, hipStream_t s) {
     const Geom& g = x.g;
@@ -181,16 +197,8 @@ struct GEngine {
     sa.fband = x.fband;
     sa.stage = stage;
     TimedLaunch tl(x.timer, KID_ZFWD, s);
-    switch (gen::zf_positions(g.N, gen::zf_shape(g.N, (int)sizeof(cpx<T>)).TT)) {
-      case 2: launch_zf<2>(x, sa, s); break;
-      case 4: launch_zf<4>(x, sa, s); break;
-      case 6: launch_zf<6>(x, sa, s); break;
-      case 8: launch_zf<8>(x, sa, s); break;
-      case 10: launch_zf<10>(x, sa, s); break;
-      case 12: launch_zf<12>(x, sa, s); break;
-      case 14: launch_zf<14>(x, sa, s); break;
-      default: launch_zf<16>(x, sa, s); break;
-    }
+    with_positions(gen::zf_positions(g.N, gen::zf_shape(g.N, (int)sizeof(cpx<T>)).TT),
+                   [&](auto p) { launch_zf<decltype(p)::value>(x, sa, s); });
   }
   // z forward + update: P positions per thread of each column
   template <int P>
@@ -305,24 +313,14 @@ struct GEngine {
                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_y_forward<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    for (const void* k : {reinterpret_cast<const void*>(&gen::k_x_pass<T, 2>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 4>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 6>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 8>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 10>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 12>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 14>),
-                          reinterpret_cast<const void*>(&gen::k_x_pass<T, 16>)})
-      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
-    for (const void* k : {reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 2>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 4>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 6>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 8>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 10>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 12>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 14>),
-                          reinterpret_cast<const void*>(&gen::k_z_forward_update<T, 16>)})
-      (void)hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, b);
+    for (int p = 1; p <= gen::kMaxPositions; ++p)
+      with_positions(p, [&](auto q) {
+        constexpr int P = decltype(q)::value;
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_x_pass<T, P>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_z_forward_update<T, P>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, b);
+      });
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&gen::k_x_moments<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, b);
   }

@@ -101,8 +101,12 @@ __device__ __forceinline__ void stage(const cpx<T>* src, cpx<T>* dst, int W, int
 #pragma unroll
     for (int m = 0; m < R; ++m) root[m] = tw[N + kRootOff(R) + m];
   }
+  // b / NS from a float reciprocal: for b, NS <= 1024 the rounding error of (b + 1/2) / NS
+  // stays far below its distance 1 / (2 NS) from the nearest integer, so the quotient is exact
+  const float rns = 1.0f / float(NS);
   for (int b = j; b < nb; b += TT) {
-    const int kv = b % NS;
+    const int bq = int((float(b) + 0.5f) * rns);
+    const int kv = b - bq * NS;
     cpx<T> a[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) a[r] = src[(b + r * nb) * W + c];
@@ -119,7 +123,7 @@ __device__ __forceinline__ void stage(const cpx<T>* src, cpx<T>* dst, int W, int
       dft_odd<R, INV>(a, root);
     else
       dft<R, INV>(a);
-    const int base = (b / NS) * NS * R + kv;
+    const int base = bq * NS * R + kv;
 #pragma unroll
     for (int r = 0; r < R; ++r) dst[(base + r * NS) * W + c] = a[r];
   }
@@ -334,12 +338,10 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ aout, int a_fi
 // ---------------------------------------------------------------------------
 constexpr int kXMaxLines = 4;     // lines (wavefronts) per block
 
-// positions per lane of the physical fields of an N-point line (instantiated in steps of 2);
-// the half spectrum kx <= K <= N/2 then needs at most P/2 + 1 entries per lane
-inline int x_positions(int N) {
-  const int p = (N + 63) / 64;
-  return p < 2 ? 2 : (p + 1) / 2 * 2;
-}
+// positions per lane of the physical fields of an N-point line; the half spectrum
+// kx <= K <= N/2 then needs at most P/2 + 1 entries per lane
+inline int x_positions(int N) { return (N + 63) / 64; }
+constexpr int kMaxPositions = 16;  // N <= 1024: 64 lanes per x line, 64 or more threads per z column
 // lines per block: as many as fit two blocks in the 160 KB of a CU
 inline int x_lines(int N, int csize) {
   int lw = kXMaxLines;
@@ -649,10 +651,7 @@ inline Shape zf_shape(int N, int csize) {
   s.lds = 2 * (size_t)s.W * N * csize;
   return s;
 }
-inline int zf_positions(int N, int TT) {
-  const int p = (N + TT - 1) / TT;
-  return p < 2 ? 2 : (p + 1) / 2 * 2;
-}
+inline int zf_positions(int N, int TT) { return (N + TT - 1) / TT; }
 
 // The fields go through one transform call in a loop (scalars 0 .. S-1, each updated as soon
 // as it is transformed, then the velocity components), each field once, or twice with the

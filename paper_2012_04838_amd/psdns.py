@@ -116,6 +116,7 @@ _SIGS = {
     "psdns_get_schedule_info": (ctypes.c_int, [_c_void_p, _c_int32, ctypes.POINTER(ScheduleInfo)]),
     "psdns_set_schedule": (ctypes.c_int, [_c_void_p, _c_int32]),
     "psdns_set_pass_schedules": (ctypes.c_int, [_c_void_p, ctypes.POINTER(_c_int32)]),
+    "psdns_use_general_kernels": (ctypes.c_int, [_c_void_p]),
     "psdns_tune_passes": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(_c_int32), _c_void_p]),
     "psdns_tune": (ctypes.c_int, [_c_void_p, _c_void_p, _c_void_p, _c_int32, ctypes.POINTER(ctypes.c_double),
@@ -385,6 +386,12 @@ class Plan:
             raise ValueError(f"{NUM_PASSES} schedule indices expected")
         arr = (_c_int32 * NUM_PASSES)(*[int(v) for v in sched])
         _check(lib().psdns_set_pass_schedules(self._h, arr))
+        self._refresh_info()
+
+    def use_general_kernels(self) -> None:
+        """Run this plan on the general (mixed-radix) kernels even on a power-of-two grid
+        with the 2/3 rule (a cross-check of the two kernel families; irreversible)."""
+        _check(lib().psdns_use_general_kernels(self._h))
         self._refresh_info()
 
     def tune_passes(self, state, ws, reps: int = 3):

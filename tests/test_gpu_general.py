@@ -6,7 +6,9 @@ FP64 bar 1e-12 relative L2, FP32 1e-5.  Workspaces start filled with NaN bytes, 
 that reads an entry nobody wrote (e.g. modes of the bounding cube outside the sphere) fails.
 Sizes: N = 24 (2^3 3), 40 (2^3 5), 52 (2^2 13),
 56 (2^3 7), 44 (2^2 11) with the 2/3 rule; N = 16, 32, 64 and 48 with the phase shift;
-N = 520 for one right-hand side and one step.
+N = 150, 200, 260 and 390 (lines of 3, 4, 5 and 7 positions per lane and per thread);
+N = 520 for one right-hand side and one step; N = 1024 (the longest lines, 16 positions)
+against the tuned power-of-two kernels on the same plan.
 """
 import math
 
@@ -191,3 +193,69 @@ def test_paper_grid_520_rhs_and_step_match_oracle():
     err = rel_l2(got, ref)
     progress(f"[general] 520^3 one step FP32 vs oracle rel L2 {err:.2e}")
     assert err < 1e-5 and info["flags"] == 0
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("N,S", [(150, 1), (200, 1), (260, 1), (390, 0)])
+def test_general_kernels_at_every_line_length_match_oracle(N, S):
+    """The x pass holds ceil(N/64) positions of a line per lane and the z-forward pass
+    ceil(N/TT) per thread, each count compiled on its own: N = 150 (2 3 5^2), 200 (2^3 5^2),
+    260 (2^2 5 13) and 390 (2 3 5 13) reach 3, 4, 5 and 7."""
+    x = inputs.random_spectral_state(N, 3 + S, 70 + N, ora.kmax_retained(N), 8.0)
+    prm = _prm(S)
+    progress(f"[general] N={N} S={S} oracle right-hand side")
+    ref = ora.rhs(x, prm)
+    got = gpu_rhs(x, prm, 64)
+    err = rel_l2(got, ref)
+    got32 = gpu_rhs(x, prm, 32)
+    err32 = rel_l2(got32, ref)
+    progress(f"[general] N={N} S={S} rhs FP64 rel L2 {err:.2e}, FP32 {err32:.2e}")
+    assert err < 1e-12
+    assert err32 < 1e-5
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("S,prec", [(1, 32), (0, 64)])
+def test_general_kernels_match_tuned_kernels_at_1024(S, prec):
+    """N = 1024 with the 2/3 rule, the largest grid: the right-hand side and one CFL step of
+    the general kernels (16 positions per lane and per thread in FP32) against the tuned
+    power-of-two kernels on the same plan, state and workspace."""
+    torch = torch_mod()
+    N = 1024
+    prm = ora.Params(nu=3e-4, schmidt=(1.0,)[:S], mean_grad=((0.0, 1.0, 0.0),)[:S], power=0.1, k_force=2.0)
+    plan = make_plan(N, S, prec)
+    assert plan.info.general == 0
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    progress(f"[general] 1024^3 S={S} FP{prec}: tuned kernels")
+    plan.init_field(st, ws, 0, seed=4, k_peak=8.0, kinetic_energy=1.0)
+    if S:
+        plan.step(st, ws, -0.5, 1)  # scalar structure
+    out_t, st_t = plan.new_state(), st.clone()
+    plan.rhs(st, out_t, ws)
+    plan.step(st_t, ws, -0.5, 1)
+    dt_t = plan.read_step_info(ws)[0]["dt"]
+    progress(f"[general] 1024^3 S={S} FP{prec}: general kernels")
+    plan.use_general_kernels()
+    assert plan.info.general == 1 and plan.info.n_schedules == 1
+    out_g = plan.new_state()
+    plan.rhs(st, out_g, ws)
+    plan.step(st, ws, -0.5, 1)
+    dt_g = plan.read_step_info(ws)[0]["dt"]
+    real = torch.float32 if prec == 32 else torch.float64
+
+    def rel(a, b):
+        a, b = a.view(real), b.view(real)
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    e_rhs, e_step = rel(out_g, out_t), rel(st, st_t)
+    tol = 1e-5 if prec == 32 else 1e-12
+    progress(f"[general] 1024^3 S={S} FP{prec}: rhs rel L2 {e_rhs:.2e}, step {e_step:.2e}, "
+             f"dt {dt_g:.6e} vs {dt_t:.6e}")
+    assert e_rhs < tol and e_step < tol
+    assert abs(dt_g - dt_t) <= (1e-6 if prec == 32 else 1e-13) * dt_t
+    with pytest.raises(psdns.PsdnsError, match="general kernels"):
+        plan.pressure(st, ws)
+    del st, st_t, out_t, out_g, ws
+    plan.close()
+    torch.cuda.empty_cache()
