@@ -45,29 +45,33 @@ GRAD = ((0.0, 1.0, 0.0), (0.0, 1.0, 0.0))
 # and build flags they were taken with; a different digest reports null.
 _SAME = (0, 1, 2, 4, 5, 6)  # schedules with 128-byte kx tiles at this size (3 has 64-byte ones)
 MEASURED_TRAFFIC = {
-    "src": "32599d052e2f5264",
+    "src": "e2ec0da39932a37d",
     "workload": (512, 2, 32),
     "bytes": {
-        "z_inverse": {**{v: 2983.2e6 for v in _SAME}, 3: 3459.3e6},
-        "y_inverse": {**{v: 6543.0e6 for v in _SAME}, 3: 8106.3e6},
+        "z_inverse": {**{v: 2983.1e6 for v in _SAME}, 3: 3066.8e6},
+        "y_inverse": {**{v: 6542.9e6 for v in _SAME}, 3: 7929.8e6},
         "x_pass": {v: 6233.0e6 for v in range(7)},
-        "y_forward": {**{v: 3047.0e6 for v in _SAME}, 3: 4134.2e6},
+        "y_forward": {**{v: 3047.0e6 for v in _SAME}, 3: 4040.0e6},
         "z_forward_update": {0: 2848.8e6},
-        "z_forward_update_inverse": {v: 5420.6e6 for v in _SAME},
+        "z_forward_update_inverse": {v: 5420.5e6 for v in _SAME},
     },
 }
 
 
+# the sources that define the step kernels of the table and their launch shapes (the host
+# API that sequences them is left out)
+KERNEL_SOURCES = ("common.hpp", "engine.hpp", "fft.hpp", "mem.hpp", "inst_n512.hip")
+
+
 def kernel_source_digest() -> str:
-    """sha256 over the device sources and the build flags of the shared library."""
+    """sha256 over the sources of the step kernels and the build flags of the library."""
     import hashlib
 
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2012_04838_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hpp", ".hip")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     with open(os.path.join(ROOT, "paper_2012_04838_amd", "build.py"), "rb") as f:
         h.update(f.read())
     return h.hexdigest()[:16]

@@ -220,23 +220,29 @@ struct EventTimer : Timer {
   }
   void begin(int kid, hipStream_t s) override {
     Rec r{kid, get(), get(), false};
-    if (r.a) hipEventRecord(r.a, s);
+    if (r.a) {
+      const hipError_t e = hipEventRecord(r.a, s);
+      if (e != hipSuccess) err = e;
+    }
     recs.push_back(r);
   }
   void end(int kid, hipStream_t s) override {
     for (auto it = recs.rbegin(); it != recs.rend(); ++it)
       if (it->kid == kid && !it->closed) {
-        if (it->b) hipEventRecord(it->b, s);
+        if (it->b) {
+          const hipError_t e = hipEventRecord(it->b, s);
+          if (e != hipSuccess) err = e;
+        }
         it->closed = true;
         return;
       }
   }
   ~EventTimer() override {
     for (auto& r : recs) {
-      if (r.a) hipEventDestroy(r.a);
-      if (r.b) hipEventDestroy(r.b);
+      if (r.a) (void)hipEventDestroy(r.a);
+      if (r.b) (void)hipEventDestroy(r.b);
     }
-    for (auto e : pool) hipEventDestroy(e);
+    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -352,8 +358,11 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
   Ctx c = make_ctx(plan, ws);
   c.timer = timer;
   // Every stage's last pass also inverts the next stage input along z (it is in its
-  // registers already), so only the first stage of a call runs the standalone z pass;
-  // the very last stage of a direct call skips the unneeded inverse.
+  // registers already), so only the first stage of a call runs the standalone z pass.
+  // The last stage of a call is fused too, although its inverse goes unused: each
+  // y_{n+1} then comes from the same kernel however the steps are split into calls or
+  // replayed from a graph, so the results are bitwise the same (the fused and unfused
+  // passes compute the same sums, but the compiler may round them differently).
   // With the hold forcing y_{n+1} is rescaled on the band after the last stage, so that
   // stage cannot run the next step's z inverse: every step then starts with its own.
   bool hold = false;
@@ -362,12 +371,12 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
   // The fused passes update integrating-factor slots only; a batch with an explicit-
   // integrator slot runs every stage unfused (its own z inverse, then the update).
   const bool expl = any_explicit(plan);
-  auto one_step = [&](const Ctx& cx, bool first, bool last) {
+  auto one_step = [&](const Ctx& cx, bool first) {
     for (int stage = 0; stage < 4; ++stage) {
       const void* sin = stage == 0 ? state : cx.ystage;
       int fl = kStageFuse;
       if ((first || hold) && stage == 0) fl |= kStageZinv;
-      if ((last || hold) && stage == 3) fl &= ~kStageFuse;
+      if (hold && stage == 3) fl &= ~kStageFuse;
       if (expl) fl = kStageZinv;
       stage_fn(plan)(cx, state, sin, stage, nullptr, stage == 0, dt, fl, s);
     }
@@ -383,7 +392,7 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
       Ctx cc = c;
       cc.timer = nullptr;  // no event records inside a captured graph
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-      one_step(cc, false, false);
+      one_step(cc, false);
       hipGraph_t graph = nullptr;
       const hipError_t le = hipGetLastError();
       const hipError_t ce = hipStreamEndCapture(s, &graph);
@@ -416,7 +425,7 @@ psdns_status run_steps(psdns_plan* plan, void* state, void* ws, double dt, int n
   }
   for (int n = 0; n < nsteps; ++n) {
     if (timer) timer->begin(KID_STEP, s);
-    one_step(c, n == 0, n == nsteps - 1);
+    one_step(c, n == 0);
     if (timer) timer->end(KID_STEP, s);
     HIP_TRY(hipGetLastError());
   }
@@ -559,7 +568,7 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
   }
   e = hipMalloc(reinterpret_cast<void**>(&plan->slots_dev), sizeof(SlotDev) * p->batch);
   if (e != hipSuccess) {
-    hipFree(plan->tw);
+    (void)hipFree(plan->tw);
     delete plan;
     return fail(PSDNS_E_NOMEM, std::string("hipMalloc(slot table): ") + hipGetErrorString(e));
   }
@@ -573,8 +582,8 @@ psdns_status psdns_plan_create(const psdns_plan_params* p, psdns_plan** out) {
   if (e == hipSuccess)
     e = hipMemcpy(plan->slots_dev, plan->slots_host.data(), sizeof(SlotDev) * p->batch, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
-    hipFree(plan->tw);
-    hipFree(plan->slots_dev);
+    (void)hipFree(plan->tw);
+    (void)hipFree(plan->slots_dev);
     delete plan;
     return hip_fail(e, "hipMemcpy(plan tables)");
   }
@@ -586,8 +595,8 @@ psdns_status psdns_plan_destroy(psdns_plan* plan) {
   if (!plan) return PSDNS_OK;
   if (plan->graph_exec) (void)hipGraphExecDestroy(plan->graph_exec);
   delete plan->timer;
-  if (plan->tw) hipFree(plan->tw);
-  if (plan->slots_dev) hipFree(plan->slots_dev);
+  if (plan->tw) (void)hipFree(plan->tw);
+  if (plan->slots_dev) (void)hipFree(plan->slots_dev);
   delete plan;
   return PSDNS_OK;
 }
@@ -789,7 +798,7 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return fail(PSDNS_E_HIP, "hipEventCreate failed");
   }
   hipError_t err = hipSuccess;
@@ -813,8 +822,8 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
     ms[i] = (double)t / reps;
     if (ms[i] < ms[b]) b = i;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (err != hipSuccess) return hip_fail(err, "schedule trial");
   if (ms_out)
     for (int i = 0; i < plan->ops.nsched; ++i) ms_out[i] = ms[i];
