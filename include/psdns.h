@@ -84,11 +84,12 @@ typedef enum {
 #define PSDNS_DEALIAS_TWO_THIRDS 0
 #define PSDNS_DEALIAS_PHASE_SPHERE 1
 
-/* Plan geometry, fixed for the life of a plan.  Grids that are powers of two with the 2/3
- * rule run the tuned step kernels; any other even n whose prime factors are 2, 3, 5, 7, 11
- * and 13 (the paper's n = 520 = 2^3 5 13, Sec. 3.1 and Table 2), and every plan with
- * PHASE_SPHERE, run general kernels built on mixed-radix transforms (one schedule; no
- * psdns_pressure, which returns PSDNS_E_UNSUPPORTED there). */
+/* Plan geometry, fixed for the life of a plan.  Grids that are powers of two run the tuned
+ * step kernels: with the 2/3 rule in every schedule, with PHASE_SPHERE in one schedule
+ * (their phase-shift stage).  Any other even n whose prime factors are 2, 3, 5, 7, 11 and
+ * 13 (the paper's n = 520 = 2^3 5 13, Sec. 3.1 and Table 2) runs general kernels built on
+ * mixed-radix transforms (one schedule).  Plans with PHASE_SPHERE, and plans on the
+ * general kernels, have no psdns_pressure (PSDNS_E_UNSUPPORTED). */
 typedef struct {
   int32_t n;         /* points per axis: even, 8 <= n <= 1024, prime factors in {2, 3, 5, 7, 11, 13} */
   int32_t n_scalars; /* S, 0 <= S <= PSDNS_MAX_SCALARS */
@@ -183,7 +184,7 @@ typedef struct {
   int32_t schedule;           /* schedule in use, or -1 when the passes run in different ones */
   int64_t plan_bytes;         /* device bytes of the plan's own tables (psdns_plan_device_bytes) */
   int32_t dealias;            /* PSDNS_DEALIAS_* of the plan */
-  int32_t general;            /* 1 when the plan runs the general (mixed-radix) kernels */
+  int32_t general;            /* 1 when the plan steps on the general (mixed-radix) kernels */
   int32_t pass_schedules[5];  /* schedule of each pass, PSDNS_PASS_* order */
 } psdns_plan_info;
 
@@ -316,9 +317,10 @@ psdns_status psdns_tune(psdns_plan* plan, const void* state, void* ws, int32_t r
  * butterflies differs).  A captured step graph is dropped and re-captured. */
 psdns_status psdns_set_pass_schedules(psdns_plan* plan, const int32_t* sched);
 /* Run this plan on the general (mixed-radix) kernels even where the tuned power-of-two
- * kernels apply (a power-of-two n with the 2/3 rule): both families read and write the same
- * state and workspace layouts and compute the same right-hand side (Sec. 2.2), so the one
- * cross-checks the other on one grid, up to the largest lines (n = 1024).  From then on the
+ * kernels apply (a power-of-two n, either dealiasing): both families read and write the same
+ * state and workspace layouts and compute the same right-hand side (Sec. 2.2, and the
+ * phase-shift dealiasing of Sec. 2.3), so the one cross-checks the other on one grid, up to
+ * the largest lines (n = 1024).  From then on the
  * plan reports general = 1, has one schedule, and psdns_pressure returns
  * PSDNS_E_UNSUPPORTED.  No-op on a plan that already runs the general kernels; a captured
  * step graph is dropped.  There is no way back. */

@@ -57,8 +57,8 @@ int kmax_of(int n, int dealias) {
   return k;
 }
 
-// whether the plan runs the general kernels (mixed radix or phase-shift dealiasing)
-bool general_plan(const psdns_plan_params* p) { return !is_pow2(p->n) || p->dealias == PSDNS_DEALIAS_PHASE_SPHERE; }
+// whether the plan's steps run on the general kernels (mixed radix)
+bool general_plan(const psdns_plan_params* p) { return !is_pow2(p->n); }
 
 bool valid_params(const psdns_plan_params* p, std::string* why) {
   if (!p) {
@@ -102,9 +102,7 @@ bool valid_params(const psdns_plan_params* p, std::string* why) {
   return true;
 }
 
-Ops ops_for(const psdns_plan_params* p) {
-  const int n = p->n, prec = p->precision;
-  if (general_plan(p)) return ops_general(prec);
+Ops ops_pow2(int n, int prec) {
   switch (n) {
     case 8: return ops_n8(prec);
     case 16: return ops_n16(prec);
@@ -115,6 +113,23 @@ Ops ops_for(const psdns_plan_params* p) {
     case 512: return ops_n512(prec);
     default: return ops_n1024(prec);
   }
+}
+
+// The step kernels of a plan: the tuned ones of its N, or the general ones.  A power-of-two
+// plan with the phase-shift dealiasing steps on the tuned kernels (their phase-shift stage,
+// one schedule) and takes its initial fields, statistics and state conversions from the
+// general kernels, whose layouts are the same.
+Ops ops_for(const psdns_plan_params* p) {
+  const int n = p->n, prec = p->precision;
+  if (!is_pow2(n)) return ops_general(prec);
+  Ops t = ops_pow2(n, prec);
+  if (p->dealias != PSDNS_DEALIAS_PHASE_SPHERE) return t;
+  Ops o = ops_general(prec);
+  o.nsched = 1;
+  o.sched[0] = t.sched[0];
+  o.sched[0].rhs_stage = t.rhs_phase;
+  o.rhs_mixed = nullptr;
+  return o;
 }
 
 
@@ -964,7 +979,8 @@ psdns_status psdns_pressure(psdns_plan* plan, const void* state, void* ws, void*
   if (state == canonical_out) return fail(PSDNS_E_INVAL, "canonical_out must not alias state");
   hipStream_t s = static_cast<hipStream_t>(hip_stream);
   if (!plan->ops.pressure)
-    return fail(PSDNS_E_UNSUPPORTED, "psdns_pressure is not available for plans with the general kernels");
+    return fail(PSDNS_E_UNSUPPORTED,
+                "psdns_pressure is not available for plans with the general kernels or the phase-shift dealiasing");
   Ctx c = make_ctx(plan, ws);
   std::vector<int> active(plan->p.batch);
   for (int i = 0; i < plan->p.batch; ++i) active[i] = plan->slots_host[i].active;

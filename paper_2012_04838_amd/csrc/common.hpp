@@ -170,6 +170,8 @@ struct Ops {
   StepSched sched[kMaxSched];
   // the stage with each pass in the schedule Ctx::psched names (null: sched[0] only)
   RhsStageFn rhs_mixed;
+  // the stage with the phase-shift dealiasing on the step kernels of this N (null: none)
+  RhsStageFn rhs_phase;
   void (*init_field)(const Ctx&, void* state, int slot, uint64_t seed, double k_peak, int spectrum, double energy,
                      hipStream_t);
   void (*get_state)(const Ctx&, const void* state, int slot, void* canon, hipStream_t);

@@ -235,6 +235,25 @@ __device__ __forceinline__ ColBlock col_block(int ntile, int nrow) {
   return b;
 }
 
+// Largest retained |k_i| of the step kernels: the 2/3 rule's (N-1)/3 (DL = 0), or the
+// largest K with 9 K^2 < 2 N^2 that bounds the phase-shift sphere (DL = 1, Sec. 3.1).
+template <int N, int DL>
+constexpr int kmax() {
+  if constexpr (DL == 0) {
+    return (N - 1) / 3;
+  } else {
+    int k = 0;
+    while (9LL * (k + 1) * (k + 1) < 2LL * N * N) ++k;
+    return k;
+  }
+}
+// exp(i pi k / N), the half-cell shift of wavenumber k (|k| <= N/2), from the root table
+template <typename T>
+__device__ __forceinline__ cpx<T> shift_phase(const cpx<T>* __restrict__ tw_g, int N, int k) {
+  const cpx<T> v = tw_g[N + kShiftOff + (k < 0 ? -k : k)];
+  return k < 0 ? conj(v) : v;
+}
+
 // position n of an N-point line -> compact index (or -1 if the wavenumber is truncated)
 __device__ __forceinline__ int compact_of(int n, int N, int K, int M) {
   return n <= K ? n : (n >= N - K ? n - N + M : -1);
@@ -243,6 +262,16 @@ __device__ __forceinline__ int compact_of(int n, int N, int K, int M) {
 __device__ __forceinline__ int wave_of(int n, int N) { return n <= N / 2 ? n : n - N; }
 // compact index -> signed wavenumber
 __device__ __forceinline__ int wave_of_compact(int c, int K, int M) { return c <= K ? c : c - M; }
+// the half-cell shift phases of the N positions of a line, exp(i pi k / N) with k their
+// wavenumbers (conjugated with CONJ), copied to the block's LDS (the caller's next block
+// barrier publishes them)
+template <int N, bool CONJ, typename T>
+__device__ __forceinline__ void stage_shift(cpx<T>* dst, const cpx<T>* __restrict__ tw_g) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    const cpx<T> v = shift_phase(tw_g, N, wave_of(i, N));
+    dst[i] = CONJ ? conj(v) : v;
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ cpx<T> czero() { return {T(0), T(0)}; }
@@ -252,23 +281,28 @@ __device__ __forceinline__ cpx<T> czero() { return {T(0), T(0)}; }
 // A fields: 0 U1, 1 U2, 2 U3, 3 dz U1, 4 dz U2, 5+2s Phi_s, 6+2s dz Phi_s
 // (all carry the 1/N^3 of Eq. (5) so that physical values are the true ones).
 // The next field's loads are issued before the current field is transformed.
+// DL = 1 (phase-shift dealiasing): the retained set is the sphere 9|k|^2 < 2N^2 inside
+// the cube |k_i| <= K, only its modes are read, and with shift the inputs carry
+// exp(i pi kz / N) (the kx and ky parts are applied by the later passes).
 // ---------------------------------------------------------------------------
-template <int N, typename T, int V>
+template <int N, typename T, int V, int DL = 0>
 __global__ void PSDNS_COL_BOUNDS(Cfg<N, T, V>::COL_THREADS)
 k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
-            const SlotDev* __restrict__ slots, Geom g) {
+            const SlotDev* __restrict__ slots, Geom g, int shift = 0) {
   using C = Cfg<N, T, V>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
-  constexpr int K = (N - 1) / 3;
+  constexpr int K = kmax<N, DL>();
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
   using L = ColLds<N, T, W>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
+  __shared__ cpx<T> sph[DL ? N : 1];
   const ColBlock cb = col_block<C::Col::PAIR>((g.KX + W - 1) / W, M);
   if (!cb.ok) return;
   const int slot = cb.slot;
   if (!slots[slot].active) return;
+  if constexpr (DL) stage_shift<N, false>(sph, tw_g);
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
@@ -284,12 +318,17 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
   const cpx<T>* sslot = st + (long long)slot * g.F * g.st_field;
   cpx<T>* aslot = abuf + (long long)slot * g.FA * g.a_field;
 
+  [[maybe_unused]] const int ky = wave_of_compact(kyc, K, M);
   auto load = [&](int f, cpx<T> (&v)[E]) {
     const Buf<T> b = make_buf<T>(sslot + (long long)f * g.st_field);
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       uint32_t vo, so;
-      v[m] = (valid && compact_at<N, TT>(m, j, voff, rsb, vo, so)) ? bload(b, vo, so) : czero<T>();
+      bool in = valid && compact_at<N, TT, K>(m, j, voff, rsb, vo, so);
+      if constexpr (DL) in = in && retained(g, kx, ky, wave_of(j + TT * m, N));
+      v[m] = in ? bload(b, vo, so) : czero<T>();
+      if constexpr (DL)
+        if (shift) v[m] = cmul(v[m], sph[j + TT * m]);
     }
   };
   auto store = [&](int f, const cpx<T> (&v)[E]) {
@@ -342,23 +381,27 @@ k_z_inverse(const cpx<T>* __restrict__ st, cpx<T>* __restrict__ abuf, const cpx<
 // B fields: 0 u1, 1 u2, 2 u3, 3 omega1 = dy u3 - dz u2, 4 dz u1, 5 dy u1,
 //           6+3s phi_s, 7+3s dy phi_s, 8+3s dz phi_s   (x still spectral)
 // The next field's loads are issued before the current field is transformed.
+// DL = 1: the cube |ky| <= K of the phase-shift sphere; with shift the inputs carry
+// exp(i pi ky / N).
 // ---------------------------------------------------------------------------
-template <int N, typename T, int V>
+template <int N, typename T, int V, int DL = 0>
 __global__ void PSDNS_COL_BOUNDS(Cfg<N, T, V>::COL_THREADS)
 k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g,
-            const SlotDev* __restrict__ slots, Geom g) {
+            const SlotDev* __restrict__ slots, Geom g, int shift = 0) {
   using C = Cfg<N, T, V>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
-  constexpr int K = (N - 1) / 3;
+  constexpr int K = kmax<N, DL>();
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
   using L = ColLds<N, T, W>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
+  __shared__ cpx<T> sph[DL ? N : 1];
   const ColBlock cb = col_block<C::Col::PAIR>((g.KX + W - 1) / W, N);
   if (!cb.ok) return;
   const int slot = cb.slot;
   if (!slots[slot].active) return;
+  if constexpr (DL) stage_shift<N, false>(sph, tw_g);
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
@@ -379,8 +422,10 @@ k_y_inverse(const cpx<T>* __restrict__ abuf, cpx<T>* __restrict__ bbuf, const cp
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       uint32_t vo, so;
-      v[m] = (valid && compact_at<N, TT>(m, j, voff, rsb, vo, so)) ? bload<T, kPolicyStream>(b, vo, so)
-                                                                     : czero<T>();
+      v[m] = (valid && compact_at<N, TT, K>(m, j, voff, rsb, vo, so)) ? bload<T, kPolicyStream>(b, vo, so)
+                                                                        : czero<T>();
+      if constexpr (DL)
+        if (shift) v[m] = cmul(v[m], sph[j + TT * m]);
     }
   };
   auto store = [&](int f, const cpx<T> (&v)[E]) {
@@ -469,10 +514,10 @@ __device__ __forceinline__ cpx<T> shfl_c(cpx<T> v, int src) {
 
 // Lane-level helpers of the x pass: which unique half-spectrum entries a lane
 // loads, and how it assembles its strided positions of h = f + i g.
-template <int N, typename T>
+template <int N, typename T, int K_ = (N - 1) / 3>
 struct XLine {
   static constexpr int E = Cfg<N, T>::EX, TT = Cfg<N, T>::TX;
-  static constexpr int K = (N - 1) / 3;
+  static constexpr int K = K_;
   static constexpr int NQ = (K + 1 + TT - 1) / TT;  // unique entries per lane and field
   // a line inside one wavefront exchanges with its mirror lane by a cross-lane permute;
   // a line over several wavefronts goes through LDS (block barriers)
@@ -593,16 +638,18 @@ struct XLine {
 // mode bits of the x pass
 constexpr int kXMax = 1;       // partial maxima of |u1|+|u2|+|u3| (CFL)
 constexpr int kXPressure = 2;  // with S = 0: forward field 3 is |u|^2/2 (pressure assembly)
+constexpr int kXShift = 4;     // DL = 1: inputs times exp(i pi kx / N), outputs times its conjugate
 
-template <int N, typename T, int V>
+template <int N, typename T, int V, int DL = 0>
 __global__ void __launch_bounds__((Cfg<N, T, V>::X_THREADS), (Cfg<N, T, V>::X_WAVES))
 k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotDev* __restrict__ slots,
          DynDev* __restrict__ dyn, Geom g, int mode) {
   using C = Cfg<N, T, V>;
-  using XL = XLine<N, T>;
+  constexpr int K = kmax<N, DL>();
+  using XL = XLine<N, T, K>;
   using XS = typename XL::Sync;
   constexpr int E = C::EX, TT = C::TX, L = C::LX, LP = C::LP;
-  constexpr int K = (N - 1) / 3;
+  [[maybe_unused]] const bool shifted = DL && (mode & kXShift);
   constexpr int NQ = XL::NQ;  // unique entries per lane and field
   __shared__ cpx<T> smem[L * LP];
   __shared__ cpx<T> stw[N];
@@ -635,7 +682,24 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
   auto fbuf = [&](int f) { return make_buf<T>(bblock + (long long)f * g.b_field); };
 
   const XL xl(threadIdx.x, xch);
-  auto load = [&](int f, cpx<T> (&r)[NQ]) { xl.load(fbuf(f), voff, r); };
+  // DL = 1 with the shift: the phases exp(i pi kx / N) of the lane's entries, read once
+  [[maybe_unused]] cpx<T> xph[DL ? NQ : 1];
+  if constexpr (DL) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = j + TT * q;
+      xph[q] = (shifted && k <= K) ? shift_phase(tw_g, N, k) : cpx<T>{T(1), T(0)};
+    }
+  }
+  auto load = [&](int f, cpx<T> (&r)[NQ]) {
+    xl.load(fbuf(f), voff, r);
+    if constexpr (DL) {
+      if (shifted) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) r[q] = cmul(r[q], xph[q]);
+      }
+    }
+  };
   auto build = [&](const cpx<T> (&va)[NQ], const cpx<T> (&vb)[NQ], cpx<T> (&h)[E]) { xl.build(va, vb, h); };
   auto kxq = [&](int q) { return T(j + TT * q); };
 
@@ -725,8 +789,16 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
       const int kx = j + TT * s;
       if (kx <= K) {
         const uint32_t so = (uint32_t)(TT * s * (int)sizeof(cpx<T>));
-        bstore(fbuf(fp), voff, so, T(0.5) * (zk + zc));
-        if (fq >= 0) bstore(fbuf(fq), voff, so, mul_mi(T(0.5) * (zk - zc)));
+        cpx<T> pv = T(0.5) * (zk + zc), qv = mul_mi(T(0.5) * (zk - zc));
+        if constexpr (DL) {
+          if (shifted) {
+            const cpx<T> e = conj(xph[s]);
+            pv = cmul(pv, e);
+            qv = cmul(qv, e);
+          }
+        }
+        bstore(fbuf(fp), voff, so, pv);
+        if (fq >= 0) bstore(fbuf(fq), voff, so, qv);
       }
     });
   };
@@ -833,22 +905,24 @@ k_x_pass(cpx<T>* __restrict__ bbuf, const cpx<T>* __restrict__ tw_g, const SlotD
 // y forward: columns along y at fixed (z, kx-tile); keeps |ky| <= K.
 // The next field's loads are issued before the current field is transformed.
 // ---------------------------------------------------------------------------
-template <int N, typename T, int V>
+template <int N, typename T, int V, int DL = 0>
 __global__ void PSDNS_YF_BOUNDS(Cfg<N, T, V>::COL_THREADS)
 k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cpx<T>* __restrict__ tw_g,
-            const SlotDev* __restrict__ slots, Geom g) {
+            const SlotDev* __restrict__ slots, Geom g, int shift = 0, int afields = 0) {
   using C = Cfg<N, T, V>;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
-  constexpr int K = (N - 1) / 3;
+  constexpr int K = kmax<N, DL>();
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
   using L = ColLds<N, T, W, PSDNS_YF_DB>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
+  __shared__ cpx<T> sph[DL ? N : 1];
   const ColBlock cb = col_block<C::Col::PAIR>((g.KX + W - 1) / W, N);
   if (!cb.ok) return;
   const int slot = cb.slot;
   if (!slots[slot].active) return;
+  if constexpr (DL) stage_shift<N, true>(sph, tw_g);
   stage_twiddles<N>(stw, tw_g);
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
@@ -860,7 +934,9 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
   const uint32_t rsb = (uint32_t)g.PX * CS;
   const uint32_t voff = ((uint32_t)j * g.PX + (uint32_t)kx) * CS;
   const cpx<T>* bplane = bbuf + (long long)slot * g.FB * g.b_field + (long long)z * N * g.PX;
-  cpx<T>* aplane = abuf + (long long)slot * g.FA * g.a_field + a_row(z, 0, M, g.PX);
+  // DL = 1: the output has afields fields per slot (A, or the kept unshifted products)
+  const int ofields = DL ? afields : g.FA;
+  cpx<T>* aplane = abuf + (long long)slot * ofields * g.a_field + a_row(z, 0, M, g.PX);
   auto load = [&](int f, cpx<T> (&v)[E]) {
     const Buf<T> b = make_buf<T>(bplane + (long long)f * g.b_field);
 #pragma unroll
@@ -885,7 +961,11 @@ k_y_forward(const cpx<T>* __restrict__ bbuf, cpx<T>* __restrict__ abuf, const cp
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         uint32_t vo, so;
-        if (compact_at<N, TT>(m, j, voff, rsb, vo, so)) bstore<C::Col::STORE>(b, vo, so, a[m]);
+        if (!compact_at<N, TT, K>(m, j, voff, rsb, vo, so)) continue;
+        cpx<T> v = a[m];
+        if constexpr (DL)
+          if (shift) v = cmul(v, sph[j + TT * m]);
+        bstore<C::Col::STORE>(b, vo, so, v);
       }
     }
   }
@@ -1025,19 +1105,27 @@ __device__ __forceinline__ cpx<T> rk_apply(const StageArgs<T>& a, long long foff
 //
 // STG: the stage (0..3) when the launch fixes it, so that the update compiles to straight
 // code; -2 reads it from the arguments (the rarer unfused launches and dy/dt).
-template <int N, typename T, bool FUSE, int V, int STG>
+//
+// DL = 1 (phase-shift dealiasing, unfused): A holds the products evaluated on the shifted
+// grid and akeep those on the grid itself; each field is the mean of the two transforms,
+// the shifted one brought back by exp(-i pi kz / N) (the kx and ky parts were applied by
+// the x and y forward passes), and only modes inside the sphere 9|k|^2 < 2N^2 are updated.
+template <int N, typename T, bool FUSE, int V, int STG, int DL = 0>
 __global__ void PSDNS_FUSED_BOUNDS(Cfg<N, T, V>::Fused::THREADS)
 k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __restrict__ tw_g,
-                   const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g) {
+                   const SlotDev* __restrict__ slots, const DynDev* __restrict__ dyn, Geom g,
+                   const cpx<T>* __restrict__ akeep = nullptr) {
+  static_assert(!(FUSE && DL), "the phase-shift pass runs unfused");
   using C = typename Cfg<N, T, V>::Fused;
   constexpr int W = C::W, E = C::EC, TT = C::TC;
-  constexpr int K = (N - 1) / 3;
+  constexpr int K = kmax<N, DL>();
   constexpr int M = 2 * K + 1;
   constexpr uint32_t CS = sizeof(cpx<T>);
   using L = ColLds<N, T, W, PSDNS_FUSED_DB>;
   __shared__ cpx<T> smem[L::kEntries];
   __shared__ cpx<T> stw[N];
   __shared__ double ez[(1 + kMaxScalars) * (K + 1)];  // exp(-D h kz^2 / 2), |kz| <= K
+  __shared__ cpx<T> sph[DL ? N : 1];                  // exp(-i pi kz / N) at position n
   const ColBlock cb = col_block<C::PAIR>((g.KX + W - 1) / W, g.M);
   if (!cb.ok) return;
   const int slot = cb.slot;
@@ -1060,7 +1148,8 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       ez[i] = exp(-0.5 * sp.diff[cls == 0 ? 0 : 2 + cls] * h * (double(kz) * kz));
     }
   }
-  stage_twiddles<N>(stw, tw_g);  // its barrier also covers ez
+  if constexpr (DL) stage_shift<N, true>(sph, tw_g);
+  stage_twiddles<N>(stw, tw_g);  // its barrier also covers ez and sph
   const cpx<T>* tw = stw;
   const int c = threadIdx.x % W;
   const int j = threadIdx.x / W;
@@ -1120,7 +1209,24 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   auto nothing = [] {};
   // state offsets of element m (false where truncated or outside the kx range)
   auto state_at = [&](int m, uint32_t& vo, uint32_t& so) {
-    return valid && compact_at<N, TT>(m, j, voff, rsb, vo, so);
+    bool in = valid && compact_at<N, TT, K>(m, j, voff, rsb, vo, so);
+    if constexpr (DL) in = in && retained(g, kx, ky, wave_of(j + TT * m, N));
+    return in;
+  };
+  // DL = 1: v (the transformed shifted product of field f) becomes the mean of the two
+  // evaluations
+  auto average = [&](int f, cpx<T> (&v)[E]) {
+    if constexpr (DL) {
+      __builtin_amdgcn_sched_barrier(0);  // the kept field's loads stay here (registers)
+      cpx<T> u[E];
+      const Buf<T> b = make_buf<T>(akeep + ((long long)slot * g.F + f) * g.a_field);
+#pragma unroll
+      for (int m = 0; m < E; ++m) u[m] = valid ? bload(b, voff, (uint32_t)(TT * m) * rsb) : czero<T>();
+      fft<N, E, false>(u, lds, j, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) v[m] = T(0.5) * (u[m] + cmul(v[m], sph[j + TT * m]));
+      __builtin_amdgcn_sched_barrier(0);
+    }
   };
 
   cpx<T> nx[E];
@@ -1135,6 +1241,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
       fetch(3 + s, a);
     }
     fft<N, E, false>(a, lds, j, tw);
+    average(3 + s, a);
     const double dif = sp.diff[3 + s];
     const double exy = exy_of(1 + s);
     const long long foff = sslot + (long long)(3 + s) * g.st_field;
@@ -1181,6 +1288,18 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
   {
     cpx<T> c1[E], c2[E], c3[E];
 #if PSDNS_FUSED_PF
+    if constexpr (DL) {
+      // one component at a time: each with its kept transform, then the next
+      fetch(0, c1);
+      fft<N, E, false>(c1, lds, j, tw);
+      average(0, c1);
+      fetch(1, c2);
+      fft<N, E, false>(c2, lds, j, tw);
+      average(1, c2);
+      fetch(2, c3);
+      fft<N, E, false>(c3, lds, j, tw);
+      average(2, c3);
+    } else {
     // the next component's loads are in flight while the current one is transformed
     if constexpr (FUSE) {
 #pragma unroll
@@ -1193,6 +1312,7 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     fetch(2, c3);
     fft<N, E, false>(c2, lds, j, tw);
     fft<N, E, false>(c3, lds, j, tw);
+    }
 #else
     fetch(0, c1);
     fft<N, E, false>(c1, lds, j, tw);
@@ -1200,6 +1320,9 @@ k_z_forward_update(cpx<T>* __restrict__ abuf, StageArgs<T> sa, const cpx<T>* __r
     fft<N, E, false>(c2, lds, j, tw);
     fetch(2, c3);
     fft<N, E, false>(c3, lds, j, tw);
+    average(0, c1);
+    average(1, c2);
+    average(2, c3);
 #endif
     if ((sp.forcing == PSDNS_FORCING_STOCHASTIC || sp.forcing == PSDNS_FORCING_ALVELIUS) && valid) {
       // the stochastic forcing term of the band modes (solenoidal, from k_stochastic_update)
@@ -2272,6 +2395,12 @@ void with_sched(int v, Fn&& fn) {
 
 // One right-hand-side evaluation and stage update, each pass with the schedule that
 // x.psched names for it.
+// schedule of the x pass of the phase-shift stage
+#ifndef PSDNS_PHASE_X
+#define PSDNS_PHASE_X 0
+#endif
+constexpr int kPhaseX = PSDNS_PHASE_X;
+
 template <int N, typename T>
 struct Stage {
   // flags: kStageZinv launches the standalone z inverse of stage_in first; kStageFuse makes
@@ -2310,6 +2439,71 @@ struct Stage {
     const bool fuse = (flags & kStageFuse) != 0;
     with_sched<N>(x.psched[kPassZForward],
                   [&](auto v) { Step<N, T, decltype(v)::value>::z_forward(x, sa, stage, fuse, s); });
+  }
+
+  // The paper's dealiasing (Sec. 2.3): the products are evaluated twice, on the grid
+  // (y forward into akeep) and on the grid shifted by half a cell along each axis (into A),
+  // and the z-forward pass takes their mean on the sphere 9|k|^2 < 2N^2 before projection,
+  // forcing and the stage update.  The passes run with the sphere's bounding K, in
+  // schedule 0 but for the x pass (kPhaseX) and the z forward (below); each stage runs its
+  // own z inverses (no fusion), and the CFL maximum comes from the unshifted evaluation.
+  static void rhs_phase(const Ctx& x, void* state, const void* stage_in, int stage, void* rhs_out, int want_max,
+                        double dt_arg, int flags, hipStream_t s) {
+    using C = Cfg<N, T, 0>;
+    using St = Step<N, T, 0>;
+    Geom g = x.g;
+    g.nblk_x = Step<N, T, kPhaseX>::kXBlocks;
+    const cpx<T>* sin = static_cast<const cpx<T>*>(stage_in);
+    const cpx<T>* tw = static_cast<const cpx<T>*>(x.tw);
+    cpx<T>* A = static_cast<cpx<T>*>(x.abuf);
+    cpx<T>* B = static_cast<cpx<T>*>(x.bbuf);
+    cpx<T>* keep = static_cast<cpx<T>*>(x.akeep);
+    {
+      TimedLaunch tl(x.timer, KID_FORCE, s);
+      k_forcing_amplitude<T><<<g.batch, 256, 0, s>>>(sin, x.slots, x.dyn, g);
+    }
+    if (flags & kStagePrologue) return;
+    const int nt = St::ntile(g);
+    for (int p = 0; p < 2; ++p) {
+      {
+        TimedLaunch tl(x.timer, KID_ZINV, s);
+        k_z_inverse<N, T, 0, 1><<<dim3(nt, g.M, g.batch), C::COL_THREADS, 0, s>>>(sin, A, tw, x.slots, g, p);
+      }
+      {
+        TimedLaunch tl(x.timer, KID_YINV, s);
+        k_y_inverse<N, T, 0, 1><<<dim3(nt, N, g.batch), C::COL_THREADS, 0, s>>>(A, B, tw, x.slots, g, p);
+      }
+      {
+        TimedLaunch tl(x.timer, KID_XPASS, s);
+        const int mode = (want_max && p == 0 ? kXMax : 0) | (p ? kXShift : 0);
+        k_x_pass<N, T, kPhaseX, 1><<<dim3(Step<N, T, kPhaseX>::kXBlocks, g.batch), Cfg<N, T, kPhaseX>::X_THREADS, 0,
+                                     s>>>(B, tw, x.slots, x.dyn, g, mode);
+      }
+      if (stage == 0 && p == 0) {
+        TimedLaunch tl(x.timer, KID_DT, s);
+        k_step_dt<<<g.batch, 64, 0, s>>>(x.slots, x.dyn, g, dt_arg);
+        k_stochastic_update<T><<<g.batch, 256, 0, s>>>(static_cast<const cpx<T>*>(state), x.slots, x.dyn, x.fband, g);
+      }
+      {
+        TimedLaunch tl(x.timer, KID_YFWD, s);
+        k_y_forward<N, T, 0, 1><<<dim3(nt, N, g.batch), C::COL_THREADS, 0, s>>>(B, p ? A : keep, tw, x.slots, g, p,
+                                                                                  p ? g.FA : g.F);
+      }
+    }
+    StageArgs<T> sa;
+    sa.yn = static_cast<cpx<T>*>(state);
+    sa.acc = static_cast<cpx<T>*>(x.acc);
+    sa.ys = static_cast<cpx<T>*>(x.ystage);
+    sa.sin = sin;
+    sa.rhs = static_cast<cpx<T>*>(rhs_out);
+    sa.fband = x.fband;
+    sa.stage = stage;
+    // the sphere leaves more retained modes per thread than the 2/3 rule: the z-forward
+    // pass takes the narrow tiles of schedule 3 (512-thread blocks, 256 registers)
+    using CZ = typename Cfg<N, T, 3>::Fused;
+    TimedLaunch tl(x.timer, KID_ZFWD, s);
+    const dim3 grid_u(CZ::grid_x((g.KX + CZ::W - 1) / CZ::W), g.M, g.batch);
+    k_z_forward_update<N, T, false, 3, -2, 1><<<grid_u, CZ::THREADS, 0, s>>>(A, sa, tw, x.slots, x.dyn, g, keep);
   }
 
   // the stage with every pass in schedule V
@@ -2470,6 +2664,7 @@ struct Engine {
     o.nsched = sched_count<N>();
     add_scheds<0, sched_count<N>()>(o);
     o.rhs_mixed = &Stage<N, T>::rhs_stage;
+    o.rhs_phase = &Stage<N, T>::rhs_phase;
     o.init_field = &init_field;
     o.get_state = &get_state;
     o.set_state = &set_state;

@@ -80,12 +80,13 @@ __device__ __forceinline__ void bstore(const Buf<T>& b, uint32_t voff, uint32_t 
 
 // Positions along a column of N points handled by a thread: element m of thread j
 // is position n = j + TT m.  A compact column keeps the retained positions n <= K
-// and n >= N - K only, at compact index n and n - N + M respectively (K = (N-1)/3,
-// M = 2K + 1).  For most m every thread of a column falls in the same class, so the
-// compact row is j plus a uniform shift.
-template <int N, int TT>
+// and n >= N - K only, at compact index n and n - N + M respectively (K = (N-1)/3 for
+// the 2/3 rule, or the bounding K of the phase-shift sphere; M = 2K + 1).  For most m
+// every thread of a column falls in the same class, so the compact row is j plus a
+// uniform shift.
+template <int N, int TT, int K_ = (N - 1) / 3>
 struct ColPos {
-  static constexpr int K = (N - 1) / 3;
+  static constexpr int K = K_;
   static constexpr int M = 2 * K + 1;
   static constexpr bool low(int m) { return TT * m + TT - 1 <= K; }
   static constexpr bool high(int m) { return TT * m >= N - K; }
@@ -96,9 +97,9 @@ struct ColPos {
 // Byte offsets (vo per thread, so uniform) of element m of a compact column whose
 // rows are rsb bytes apart and whose row-0 offset for this thread is voff (that of
 // row j).  Returns false where the element is truncated.
-template <int N, int TT>
+template <int N, int TT, int K_ = (N - 1) / 3>
 __device__ __forceinline__ bool compact_at(int m, int j, uint32_t voff, uint32_t rsb, uint32_t& vo, uint32_t& so) {
-  using P = ColPos<N, TT>;
+  using P = ColPos<N, TT, K_>;
   if (P::cut(m)) return false;
   if (P::low(m) || P::high(m)) {
     vo = voff;

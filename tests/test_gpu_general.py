@@ -4,8 +4,10 @@ and the paper's dealiasing (phase shift with spherical truncation, Sec. 2.3) at 
 
 FP64 bar 1e-12 relative L2, FP32 1e-5.  Workspaces start filled with NaN bytes, so a pass
 that reads an entry nobody wrote (e.g. modes of the bounding cube outside the sphere) fails.
+Power-of-two grids with the phase shift step on the tuned kernels (their phase-shift stage)
+and are checked here too, and against the general kernels on the same plan at 256^3 and 512^3.
 Sizes: N = 24 (2^3 3), 40 (2^3 5), 52 (2^2 13),
-56 (2^3 7), 44 (2^2 11) with the 2/3 rule; N = 16, 32, 64 and 48 with the phase shift;
+56 (2^3 7), 44 (2^2 11) with the 2/3 rule; N = 16, 32, 64, 128 and 48 with the phase shift;
 N = 150, 200, 260 and 390 (lines of 3, 4, 5 and 7 positions per lane and per thread);
 N = 520 for one right-hand side and one step; N = 1024 (the longest lines, 16 positions)
 against the tuned power-of-two kernels on the same plan.
@@ -40,7 +42,9 @@ def _state(N, S, seed, dealias="cube", kp=4.0):
 def _run(N, S, prec, prm, y0, dt, nsteps, dealias):
     torch = torch_mod()
     plan = make_plan(N, S, prec, dealias=1 if dealias == "phase" else 0)
-    assert plan.info.general == 1
+    # power-of-two grids step on the tuned kernels (their phase-shift stage), others on the
+    # general ones
+    assert plan.info.general == (0 if N & (N - 1) == 0 else 1)
     set_params(plan, 0, prm)
     st, ws = plan.new_state(), poisoned_workspace(plan)
     plan.set_state(st, y0, 0)
@@ -76,7 +80,8 @@ def test_mixed_radix_cfl_steps_match_oracle(N, S, prec):
     assert abs(info["t"] - sum(dts)) < (1e-12 if prec == 64 else 1e-6) * sum(dts)
 
 
-@pytest.mark.parametrize("N,S,prec", [(16, 1, 64), (32, 2, 64), (64, 1, 64), (48, 1, 64), (32, 1, 32)])
+@pytest.mark.parametrize("N,S,prec", [(16, 1, 64), (32, 2, 64), (64, 1, 64), (48, 1, 64), (32, 1, 32),
+                                     (128, 1, 64), (128, 2, 32)])
 def test_phase_shift_rhs_matches_oracle(N, S, prec):
     K = ora.kmax_retained(N, "phase")
     x = inputs.random_spectral_state(N, 3 + S, 80 + N, K, 5.0) * ora.retained_mask(N, "phase")
@@ -256,6 +261,48 @@ def test_general_kernels_match_tuned_kernels_at_1024(S, prec):
     assert abs(dt_g - dt_t) <= (1e-6 if prec == 32 else 1e-13) * dt_t
     with pytest.raises(psdns.PsdnsError, match="general kernels"):
         plan.pressure(st, ws)
+    del st, st_t, out_t, out_g, ws
+    plan.close()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("N,S,prec", [(256, 2, 64), (512, 2, 32)])
+def test_tuned_phase_shift_matches_general_kernels(N, S, prec):
+    """The phase-shift dealiasing on the tuned kernels of a power-of-two grid (sphere of
+    bounding K, shifted and unshifted evaluations) against the general kernels on the same
+    plan, state and workspace: the right-hand side and one CFL step."""
+    torch = torch_mod()
+    prm = _prm(S, "phase", nu=7e-4)
+    plan = make_plan(N, S, prec, dealias=psdns.DEALIAS_PHASE_SPHERE)
+    assert plan.info.general == 0
+    set_params(plan, 0, prm)
+    st, ws = plan.new_state(), plan.new_workspace()
+    progress(f"[general] {N}^3 S={S} FP{prec} phase shift: tuned kernels")
+    plan.init_field(st, ws, 0, seed=6, k_peak=8.0, kinetic_energy=1.0)
+    plan.step(st, ws, -0.5, 1)  # scalar structure
+    out_t, st_t = plan.new_state(), st.clone()
+    plan.rhs(st, out_t, ws)
+    plan.step(st_t, ws, -0.5, 1)
+    dt_t = plan.read_step_info(ws)[0]["dt"]
+    plan.use_general_kernels()
+    assert plan.info.general == 1
+    out_g = plan.new_state()
+    plan.rhs(st, out_g, ws)
+    plan.step(st, ws, -0.5, 1)
+    dt_g = plan.read_step_info(ws)[0]["dt"]
+    real = torch.float32 if prec == 32 else torch.float64
+
+    def rel(a, b):
+        a, b = a.view(real), b.view(real)
+        return float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+
+    e_rhs, e_step = rel(out_t, out_g), rel(st_t, st)
+    tol = 1e-5 if prec == 32 else 1e-12
+    progress(f"[general] {N}^3 S={S} FP{prec} phase shift: tuned vs general rhs rel L2 {e_rhs:.2e}, "
+             f"step {e_step:.2e}, dt {dt_t:.6e} vs {dt_g:.6e}")
+    assert e_rhs < tol and e_step < tol
+    assert abs(dt_g - dt_t) <= (1e-6 if prec == 32 else 1e-13) * dt_g
     del st, st_t, out_t, out_g, ws
     plan.close()
     torch.cuda.empty_cache()
