@@ -70,7 +70,7 @@ typedef enum {
   PSDNS_E_INVAL = -1,       /* invalid argument; nothing launched */
   PSDNS_E_NOMEM = -2,       /* allocation of plan-owned tables failed */
   PSDNS_E_HIP = -3,         /* a HIP runtime call failed */
-  PSDNS_E_UNSUPPORTED = -4  /* valid request this build does not implement */
+  PSDNS_E_UNSUPPORTED = -4  /* valid request this library does not implement */
 } psdns_status;
 
 /* Dealiasing of the quadratic products (Sec. 2.3).

@@ -2277,8 +2277,8 @@ k_spectra_finalize(const double* __restrict__ shells, const double* __restrict__
     }
   }
   if ((flags & 2) && threadIdx.x == 0) {
-    // round 1: fields u1 u2 u3 | du1/dx1 du2/dx2 (moments of the last two) + max
-    // round 2: du3/dx3, dphi_s/dx2 (moments of all)
+    // first sweep: fields u1 u2 u3 | du1/dx1 du2/dx2 (moments of the last two) + max
+    // second sweep: du3/dx3, dphi_s/dx2 (moments of all)
     double m1[2][3] = {{0, 0, 0}, {0, 0, 0}}, mx = 0.0;
     double m2[1 + kMaxScalars][3] = {};
     const int r1 = 3 * 2 + 1, r2 = 3 * (1 + S) + 1;

@@ -267,7 +267,7 @@ struct GEngine {
     if (flags & 2) {
       const int t = moment_threads(g);
       const size_t xl = gen::moment_lds_bytes(g.N, (int)sizeof(cpx<T>), t);
-      // round 1: u1 u2 u3, du1/dx1, du2/dx2 (moments of the last two) and the max
+      // first sweep: u1 u2 u3, du1/dx1, du2/dx2 (moments of the last two) and the max
       Spec z1{};
       const int f1[5] = {0, 1, 2, 0, 1}, a1[5] = {0, 0, 0, 1, 2};
       for (int i = 0; i < 5; ++i) {
@@ -282,7 +282,7 @@ struct GEngine {
       gen::k_x_moments<T><<<dim3(x.nbm, g.batch), t, xl, s>>>(static_cast<const cpx<T>*>(x.bbuf),
                                                              static_cast<const cpx<T>*>(x.tw), g, gen::factor(g.N), 5,
                                                              3, 1, mom1);
-      // round 2: du3/dx3, dphi_s/dx2
+      // second sweep: du3/dx3, dphi_s/dx2
       Spec z2{};
       z2.nout = 1 + g.S;
       z2.nterm[0] = 1;
