@@ -18,21 +18,23 @@ from tests.gpu_helpers import make_plan, rel_l2, set_params, to_numpy, torch_mod
 pytestmark = pytest.mark.gpu
 
 
-def _case(N, S, prec, batch, dt, steps, seed):
+def _case(N, S, prec, batch, dt, steps, seed, dealias="cube"):
     torch = torch_mod()
     prms = []
     for i in range(batch):
-        prm = ora.Params(nu=0.01, schmidt=(0.7, 1.0)[:S], mean_grad=((0.0, 1.0, 0.0),) * S, power=0.1, k_force=2.0)
+        prm = ora.Params(nu=0.01, schmidt=(0.7, 1.0)[:S], mean_grad=((0.0, 1.0, 0.0),) * S, power=0.1, k_force=2.0,
+                         dealias=dealias)
         if i % 2 == 1:
             prm.forcing_mode, prm.stoch_sigma, prm.stoch_tl, prm.stoch_seed = "stochastic", 0.05, 0.4, 11 + i
         prms.append(prm)
-    plan = make_plan(N, S, prec, batch)
+    plan = make_plan(N, S, prec, batch, dealias=1 if dealias == "phase" else 0)
     st = plan.new_state()
     for i in range(batch):
         set_params(plan, i, prms[i])
-        y = ora.init_field(N, S, seed + i, 4.0, 1.0)
+        y = ora.init_field(N, S, seed + i, 4.0, 1.0, dealias=dealias)
         if S:
-            y[3:] = inputs.random_spectral_state(N, S, seed + 10 + i, ora.kmax_retained(N), 4.0, 0.3)
+            y[3:] = (inputs.random_spectral_state(N, S, seed + 10 + i, ora.kmax_retained(N, dealias), 4.0, 0.3)
+                     * ora.retained_mask(N, dealias))
         plan.set_state(st, y, i)
     st_na = st.clone()
     ws = plan.new_workspace()
@@ -59,6 +61,12 @@ def test_noalloc_matches_step_on_calls_in_a_row():
     _case(64, 2, 64, 2, -0.5, 3, 3)      # CFL steps, one stochastic slot
     _case(32, 1, 32, 1, 0.004, 4, 7)     # a smaller input right after
     _case(64, 2, 64, 2, -0.5, 3, 3)      # the first again: records restart, no stale data
+
+
+def test_noalloc_phase_shift_plan():
+    # the paper's dealiasing: the kept unshifted products live in the scratch too
+    _case(32, 1, 64, 2, -0.5, 3, 5, dealias="phase")
+    _case(32, 2, 32, 1, -0.5, 2, 9, dealias="phase")
 
 
 def test_noalloc_rejects_plans_beyond_the_scratch():
