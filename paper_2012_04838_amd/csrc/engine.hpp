@@ -2395,9 +2395,11 @@ void with_sched(int v, Fn&& fn) {
 
 // One right-hand-side evaluation and stage update, each pass with the schedule that
 // x.psched names for it.
-// schedule of the x pass of the phase-shift stage
+// schedule of the x pass of the phase-shift stage: three waves per SIMD with the stage
+// twiddles in LDS (its four half-spectrum entries per lane at N = 512 spill a little, and
+// it still ran 5% faster than schedule 0's two waves)
 #ifndef PSDNS_PHASE_X
-#define PSDNS_PHASE_X 0
+#define PSDNS_PHASE_X 5
 #endif
 constexpr int kPhaseX = PSDNS_PHASE_X;
 
