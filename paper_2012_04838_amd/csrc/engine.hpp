@@ -161,6 +161,9 @@ constexpr Sched kSched[] = {
     {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2, 3, 0, 0},
     // the same with the twiddles kept in registers
     {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2, 3, 1, 0},
+    // radix 16 on 64-byte tiles: at N = 1024 a column is one wavefront of 16 elements per
+    // lane in 512-thread blocks, whose 256-register budget holds the fused pass unspilled
+    {16, 16, 64, 16, 16, 64, 64, 2},
 };
 constexpr int kNumSched = (int)(sizeof(kSched) / sizeof(kSched[0]));
 static_assert(kNumSched <= kMaxSched, "schedule table exceeds the dispatch table");
