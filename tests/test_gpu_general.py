@@ -267,64 +267,71 @@ def test_general_kernels_match_tuned_kernels_at_1024(S, prec):
 
 
 @pytest.mark.timeout(900)
-def test_every_schedule_at_1024_matches_general_kernels():
-    """1024^3 S=1 FP32: the schedules differ most at this size (64-byte tiles of 8 elements
-    per thread against 128-byte tiles of 16, one or two x-pass lines per block, register or
-    LDS twiddles, one wavefront per column in schedule 7), and the per-pass tuner mixes
-    them.  The right-hand side of every schedule, and of the per-pass mix the tuner picks
-    here (column passes on 128-byte tiles, the x pass in one-line blocks, the fused pass in
-    schedule 7), against the general kernels on the same state; one CFL step of the mix and
-    of schedules 1, 4 and 7 against schedule 0."""
+@pytest.mark.parametrize("S,prec", [(1, 32), (0, 64)])
+def test_every_schedule_at_1024_matches_general_kernels(S, prec):
+    """1024^3: the schedules differ most at this size (64-byte tiles of 8 elements per
+    thread against 128-byte tiles of 16, one or two x-pass lines per block, register or LDS
+    twiddles, one wavefront per column in schedule 7), and the per-pass tuner mixes them.
+    The right-hand side of every schedule, and of the per-pass mix the FP32 tuner picks here
+    (column passes on 128-byte tiles, the x pass in one-line blocks, the fused pass in
+    schedule 7), against schedule 0's, and schedule 0's against the general kernels on the
+    same state; one CFL step of the mix and of schedules 1, 4 and 7 against schedule 0."""
     torch = torch_mod()
-    N, S = 1024, 1
-    prm = ora.Params(nu=3e-4, schmidt=(1.0,), mean_grad=((0.0, 1.0, 0.0),), power=0.1, k_force=2.0)
-    plan = make_plan(N, S, 32)
+    N = 1024
+    prm = ora.Params(nu=3e-4, schmidt=(1.0,)[:S], mean_grad=((0.0, 1.0, 0.0),)[:S], power=0.1, k_force=2.0)
+    plan = make_plan(N, S, prec)
     set_params(plan, 0, prm)
     st, ws, out = plan.new_state(), plan.new_workspace(), plan.new_state()
     plan.init_field(st, ws, 0, seed=4, k_peak=8.0, kinetic_energy=1.0)
     plan.set_schedule(0)
-    plan.step(st, ws, -0.5, 1)  # scalar structure
+    if S:
+        plan.step(st, ws, -0.5, 1)  # scalar structure
+    real = torch.float32 if prec == 32 else torch.float64
+    tol = 1e-5 if prec == 32 else 1e-12
+    tag = f"[general] 1024^3 S={S} FP{prec}"
 
     def rel(a, b):
-        a, b = a.view(torch.float32), b.view(torch.float32)
+        a, b = a.view(real), b.view(real)
         return float(torch.linalg.vector_norm((a - b).double()) / torch.linalg.vector_norm(b.double()))
 
-    mix = [1, 1, 4, 1, 7]
-    rhs = {}
+    def select(v):
+        if v == "mix":
+            plan.set_pass_schedules([1, 1, 4, 1, 7])
+        else:
+            plan.set_schedule(v)
+
+    # each schedule against schedule 0 as it comes (one right-hand side kept)
+    rhs0 = None
     for v in list(range(plan.n_schedules)) + ["mix"]:
-        if v == "mix":
-            plan.set_pass_schedules(mix)
-        else:
-            plan.set_schedule(v)
+        select(v)
         plan.rhs(st, out, ws)
-        rhs[v] = out.clone()
-    steps = {}
+        if rhs0 is None:
+            rhs0 = out.clone()
+            continue
+        e = rel(out, rhs0)
+        progress(f"{tag} schedule {v}: rhs rel L2 against schedule 0 {e:.2e}")
+        assert e < tol, (v, e)
+    y0, dt0 = None, None
     for v in (0, 1, 4, 7, "mix"):
-        if v == "mix":
-            plan.set_pass_schedules(mix)
-        else:
-            plan.set_schedule(v)
+        select(v)
         y = st.clone()
         plan.clear_step_info(ws)
         plan.step(y, ws, -0.5, 1)
-        steps[v] = (y, plan.read_step_info(ws)[0]["dt"])
-    progress("[general] 1024^3 S=1 FP32: every schedule done, general kernels")
-    plan.use_general_kernels()
-    out_g = plan.new_state()
-    plan.rhs(st, out_g, ws)
-    for v, r in rhs.items():
-        e = rel(r, out_g)
-        progress(f"[general] 1024^3 S=1 FP32 schedule {v}: rhs rel L2 against the general kernels {e:.2e}")
-        assert e < 1e-5, (v, e)
-    y0, dt0 = steps[0]
-    for v in (1, 4, 7, "mix"):
-        y, dt = steps[v]
+        dt = plan.read_step_info(ws)[0]["dt"]
+        if y0 is None:
+            y0, dt0 = y, dt
+            continue
         e = rel(y, y0)
-        progress(f"[general] 1024^3 S=1 FP32 schedule {v}: one CFL step rel L2 against schedule 0 {e:.2e}, "
-                 f"dt {dt:.9e} vs {dt0:.9e}")
-        assert e < 1e-6, (v, e)
-        assert abs(dt - dt0) <= 1e-6 * dt0
-    del st, ws, out, out_g, rhs, steps, y, y0
+        progress(f"{tag} schedule {v}: one CFL step rel L2 against schedule 0 {e:.2e}, dt {dt:.9e} vs {dt0:.9e}")
+        assert e < tol / 10, (v, e)
+        assert abs(dt - dt0) <= (1e-6 if prec == 32 else 1e-13) * dt0
+        del y
+    plan.use_general_kernels()
+    plan.rhs(st, out, ws)
+    e = rel(rhs0, out)
+    progress(f"{tag} schedule 0: rhs rel L2 against the general kernels {e:.2e}")
+    assert e < tol
+    del st, ws, out, rhs0, y0
     plan.close()
     torch.cuda.empty_cache()
 
