@@ -275,7 +275,8 @@ def test_every_schedule_at_1024_matches_general_kernels(S, prec):
     The right-hand side of every schedule, and of the per-pass mix the FP32 tuner picks here
     (column passes on 128-byte tiles, the x pass in one-line blocks, the fused pass in
     schedule 7), against schedule 0's, and schedule 0's against the general kernels on the
-    same state; one CFL step of the mix and of schedules 1, 4 and 7 against schedule 0."""
+    same state; one CFL step of the mix and of schedules 1, 4 and 7 against schedule 0, and
+    a repeated step bitwise equal to the first."""
     torch = torch_mod()
     N = 1024
     prm = ora.Params(nu=3e-4, schmidt=(1.0,)[:S], mean_grad=((0.0, 1.0, 0.0),)[:S], power=0.1, k_force=2.0)
@@ -326,6 +327,18 @@ def test_every_schedule_at_1024_matches_general_kernels(S, prec):
         assert e < tol / 10, (v, e)
         assert abs(dt - dt0) <= (1e-6 if prec == 32 else 1e-13) * dt0
         del y
+    # the same step again on the same inputs repeats bitwise (schedule 0 and the mix)
+    for v in (0, "mix"):
+        select(v)
+        ya, yb = st.clone(), st.clone()
+        plan.step(ya, ws, -0.5, 1)
+        plan.step(yb, ws, -0.5, 1)
+        torch.cuda.synchronize()
+        assert torch.equal(ya, yb), v
+        if v == 0:
+            assert torch.equal(ya, y0)
+        del ya, yb
+    progress(f"{tag}: repeated steps bitwise equal")
     plan.use_general_kernels()
     plan.rhs(st, out, ws)
     e = rel(rhs0, out)
