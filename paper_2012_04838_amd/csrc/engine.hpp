@@ -89,13 +89,24 @@ namespace psdns {
 #define PSDNS_FB64 PSDNS_COL_BYTES
 #endif
 
+// Threads per column block: PSDNS_COL_MAXT, and at most 512 for FP32 columns longer than
+// 512 points.  There 512-thread blocks of 32 (128-byte tiles) or 16 (64-byte tiles) elements
+// per thread, with 256 registers each, beat 1024-thread blocks of 16 or 8 elements held in
+// 128 registers, spills included (1024^3: z inverse 6.1 against 7.1 ms, y inverse 9.0
+// against 9.7, y forward 3.8 against 4.2).
+template <int N, typename T>
+constexpr int col_max_threads() {
+  return (N > 512 && sizeof(T) == 4 && PSDNS_COL_MAXT > 512) ? 512 : PSDNS_COL_MAXT;
+}
+
 // Geometry of a column pass: W columns (one row segment of BYTES bytes) per block,
 // TC = N/EC threads per column, EC elements per thread.
 template <int N, typename T, int E_REQ, int BYTES = PSDNS_COL_BYTES>
 struct ColCfg {
   static constexpr int W = BYTES / (int)sizeof(cpx<T>);
-  // at least N * W / PSDNS_COL_MAXT elements per thread, so a block stays within the cap
-  static constexpr int EC1 = E_REQ * PSDNS_COL_MAXT < N * W ? N * W / PSDNS_COL_MAXT : E_REQ;
+  static constexpr int MAXT = col_max_threads<N, T>();
+  // at least N * W / MAXT elements per thread, so a block stays within the cap
+  static constexpr int EC1 = E_REQ * MAXT < N * W ? N * W / MAXT : E_REQ;
   static constexpr int EC = N < EC1 ? N : EC1;
   static constexpr int TC = N / EC;
   static constexpr int THREADS = W * TC;
@@ -163,6 +174,7 @@ constexpr Sched kSched[] = {
     {PSDNS_EC32, PSDNS_EC64, 0, PSDNS_EF32, PSDNS_EF64, 0, 0, 2, 3, 1, 0},
     // radix 16 on 64-byte tiles: at N = 1024 a column is one wavefront of 16 elements per
     // lane in 512-thread blocks, whose 256-register budget holds the fused pass unspilled
+    // (in FP32 there the cap of col_max_threads gives schedules 0, 3, 5 and 6 this shape too)
     {16, 16, 64, 16, 16, 64, 64, 2},
 };
 constexpr int kNumSched = (int)(sizeof(kSched) / sizeof(kSched[0]));
